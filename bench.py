@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the LGF Poisson hot path on one MI355X.
+
+Workload: a dense 256^3-cell single-level scalar solve (dx = R/64 over
+[-2R, 2R]^3, 4096 blocks of 16^3 cells, source = x-vorticity of a thin
+Gaussian-core vortex ring, R = 1, sigma = 0.1 R), the 256^3 configuration
+of the headline metric.  A step is one full solve through the C ABI
+(forward block FFTs, spectral multiply-accumulate over all 16.8M block
+pairs, inverse block FFTs), with the source already resident in HBM.
+
+Prints one JSON line (rank 0, N = 1).  The roofline entry is for the
+dominant kernel, the spectral multiply-accumulate, timed with HIP events
+recorded by the library around each of its launches on the solve stream.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "target cells solved/s at 256^3, FP32+refine vs FP64; p50/p99 solve latency"
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X FP64 vector FMA: 256 CU * 4 SIMD * 16 lanes * 2 * 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def cpu_baseline(problem, budget_s=12.0, seed=0):
+    """Time the oracle direct sum on a sample of targets (all sources)."""
+    import numpy as np
+    from oracle import direct
+    from paper_2010_13213_amd import inputs
+    c = inputs.cell_coords(problem.levels[0].blocks, problem.nb)
+    f = problem.levels[0].values[0].reshape(-1)
+    rng = np.random.default_rng(seed)
+    direct.build(force=False)
+    probe = c[rng.choice(len(c), 8, replace=False)]
+    t0 = time.perf_counter()
+    direct.direct_sum(c, f, probe, problem.dx0)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    n = int(max(16, min(len(c), 8 * budget_s / dt)))
+    tg = c[rng.choice(len(c), n, replace=False)]
+    t0 = time.perf_counter()
+    direct.direct_sum(c, f, tg, problem.dx0)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "cells/s", "cores": direct.num_threads(), "kind": "oracle",
+            "sample": "%d random target cells of the 256^3 box, each summed over all %d source "
+                      "cells (C/OpenMP direct sum), %.1f s" % (n, len(c), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the LGF path here runs on a single MI355X and has no "
+              "multi-GPU implementation (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2010_13213_amd import inputs, lgf
+
+    torch.cuda.init()
+    ctx = lgf.Context(0)
+    prob = inputs.mstar()
+    nb = prob.nb
+    n_blocks = len(prob.levels[0].blocks)
+    cells = n_blocks * nb ** 3 * prob.n_components
+    t_plan = time.perf_counter()
+    plan = lgf.Plan.for_problem(ctx, prob, "fp64")
+    t_plan = time.perf_counter() - t_plan
+    f = torch.from_numpy(prob.flat_source()).cuda()
+    u = torch.empty_like(f)
+
+    for _ in range(args.warmup):
+        plan.solve(f, u)
+    torch.cuda.synchronize()
+
+    ctx.set_timing(True)
+    ctx.stage_times()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        plan.solve(f, u)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    lat = [a.elapsed_time(b) for a, b in evs]
+
+    wall = t1 - t0
+    ms_step = 1e3 * wall / args.steps
+    value = cells * args.steps / wall
+
+    n_freq = (2 * nb) ** 2 * (nb + 1)
+    pairs = n_blocks * n_blocks
+    flops_mac = 8.0 * pairs * n_freq                       # one complex MAC = 8 flops
+    smac_ms, smac_n = st["smac"]
+    smac_avg = smac_ms / max(1, smac_n)
+    achieved = flops_mac / (smac_avg * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense 256^3 box, 4096 blocks of 16^3, dx=R/64, ring x-vorticity, "
+                               "single level, scalar, FP64",
+                   "cells": cells, "block_pairs": pairs, "plan_s": round(t_plan, 3)},
+        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+        "roofline": {"bound": "alu", "kernel": "smac_kernel<16,8,16,16,double>",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flops_per_launch": flops_mac, "avg_launch_ms": smac_avg},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+    plan.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

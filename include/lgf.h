@@ -1,0 +1,191 @@
+/*
+ * lgf.h -- C ABI of the MI355X (gfx950) lattice-Green's-function Poisson
+ * library (liblgf.so).
+ *
+ * What it computes.  Yu, Dorschner & Colonius, "Multi-resolution lattice
+ * Green's function method for incompressible flows":
+ *   - Sec. 2.2, eqs. discrete_laplace / lgf_convolution: on an unbounded
+ *     Cartesian lattice of spacing dx, the decaying solution of the 7-point
+ *     Poisson problem  dx^-2 (sum_{+-e_i} u(n +- e_i) - 6 u(n)) = f(n)  is
+ *     u = dx^2 * (G * f), G the lattice Green's function (LGF).
+ *   - Sec. 3.4, eqs. AMR-LGF-2 ... FLGF-AMR: on a composite mesh of levels
+ *     k = 0..K-1 (dx_k = dx0 / 2^k) the solution returned is
+ *     phi^ = [Gamma L^-1 P] f^  -- every level solved with its own LGF, the
+ *     coarse levels' contributions carried to finer levels by interpolation
+ *     plus the correction source S (eq. source_correct), and the result
+ *     restricted to each level's region Omega_k.
+ *
+ * Support.  The source support and the evaluation targets of level k are
+ * the cells of a list of occupied blocks of nb^3 cells (nb = 8 or 16).  Block
+ * (bx, by, bz) of level k holds lattice cells (bx*nb + x, by*nb + y, bz*nb + z),
+ * x, y, z in [0, nb).  Level k+1 blocks must lie inside level-k blocks (each
+ * fine block's parent octant belongs to a level-k block).  Omega_k is the
+ * set of level-k cells not covered by a level-(k+1) block.
+ *
+ * Field layout (f and u).  One float64 array per call:
+ *   [component][level][block][z][y][x],  x fastest,
+ * blocks of a level in the order the plan was given them.  Cells of a
+ * level-k block that are covered by finer blocks are ignored on input and
+ * written as 0 on output.
+ *
+ * Ownership.  f and u are device pointers owned by the caller (e.g. PyTorch
+ * tensors on the plan's device); the library never frees them.  Host arrays
+ * passed to lgf_plan_create are copied.  Contexts and plans are opaque,
+ * created and destroyed only through this API.
+ *
+ * Errors.  No C++ exception crosses the ABI.  Each call returns an
+ * lgf_status; on failure lgf_last_error() (thread-local) holds a message.
+ */
+#ifndef LGF_H
+#define LGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lgf_status {
+    LGF_OK = 0,
+    LGF_E_INVALID = 1,      /* bad argument, malformed block list        */
+    LGF_E_NOMEM = 2,        /* HBM budget or device allocation exceeded  */
+    LGF_E_DEVICE = 3,       /* a HIP runtime call failed                  */
+    LGF_E_UNSUPPORTED = 4   /* a valid request this build does not serve */
+} lgf_status;
+
+typedef enum lgf_precision {
+    LGF_FP64 = 0,           /* every step in float64                       */
+    LGF_FP32_REFINE = 1     /* float32 block FFTs and spectral products,
+                               float64 residual and accumulation           */
+} lgf_precision;
+
+typedef struct lgf_context lgf_context;
+typedef struct lgf_plan lgf_plan;
+
+/* One refinement level: n_blocks block coordinates, [n_blocks][3] (x, y, z). */
+typedef struct lgf_level {
+    int32_t n_blocks;
+    const int32_t *block_ijk;
+} lgf_level;
+
+/* Problem description (Sec. 3.1 composite grid, Sec. 5 block structure). */
+typedef struct lgf_problem {
+    int32_t n_levels;       /* K >= 1                                       */
+    int32_t nb;             /* block edge in cells: 8 or 16                 */
+    double dx0;             /* cell width of level 0 (> 0)                  */
+    int32_t n_components;   /* 1 (scalar) or 3 (vector Poisson)            */
+    int32_t precision;      /* an lgf_precision value                       */
+    int32_t ne_blocks;      /* extended-correction layers in blocks (>= 1;
+                               0 selects the default 1, i.e. N_E = nb)       */
+    const lgf_level *levels;/* n_levels entries, coarsest first             */
+} lgf_problem;
+
+/* Optional per-solve report, filled after the solve's stream work is done. */
+typedef struct lgf_report {
+    double device_ms;       /* stream time of the solve (HIP events)        */
+    double refine_rel_l2;   /* mixed path: ||correction|| / ||u||, else 0   */
+    int32_t passes;         /* LGF convolutions run per component           */
+    int32_t reserved;
+} lgf_report;
+
+/*
+ * Create a context on HIP device `device`.  The context owns the device-
+ * resident LGF table (built here, in float64) and the cache of LGF block
+ * spectra shared by every plan made from it.  `hbm_budget_bytes` caps what
+ * plans and spectra may allocate (0 = no cap).  Errors: LGF_E_INVALID
+ * (bad device or null out), LGF_E_DEVICE.
+ */
+lgf_status lgf_context_create(int device, size_t hbm_budget_bytes, lgf_context **out);
+void lgf_context_destroy(lgf_context *ctx);
+
+/* Bytes of device memory currently held by the context and its plans. */
+size_t lgf_context_bytes(const lgf_context *ctx);
+
+/*
+ * Build an immutable plan for one support (all levels).  Validates the block
+ * lists (duplicates, nesting, sizes -> LGF_E_INVALID), builds any LGF block
+ * spectra missing from the context cache, and allocates the plan's
+ * workspace (-> LGF_E_NOMEM if the budget would be exceeded).  Work runs on
+ * the context's own stream and is complete when this returns.
+ */
+lgf_status lgf_plan_create(lgf_context *ctx, const lgf_problem *desc, lgf_plan **out);
+
+/*
+ * Validate a problem description on the host only (no device work): the
+ * same checks lgf_plan_create applies before it builds anything.  Returns
+ * LGF_OK or LGF_E_INVALID with the reason in lgf_last_error().
+ */
+lgf_status lgf_problem_check(const lgf_problem *desc);
+void lgf_plan_destroy(lgf_plan *plan);
+
+/* Device bytes the plan's workspace holds (excluding shared spectra). */
+size_t lgf_plan_workspace_bytes(const lgf_plan *plan);
+
+/* Cells of level `level` (n_blocks * nb^3), i.e. the per-component length. */
+size_t lgf_plan_cells(const lgf_plan *plan, int level);
+
+/* Total float64 elements of f / u for this plan (all components, levels). */
+size_t lgf_plan_field_len(const lgf_plan *plan);
+
+/*
+ * Solve (Sec. 2.2 one level, Sec. 3.4 composite).  f, u: device float64
+ * arrays of lgf_plan_field_len() elements in the layout above; u is
+ * overwritten.  Asynchronous on HIP stream `stream` (a hipStream_t; NULL =
+ * the null stream).  If `rep` is non-null the call waits for its own work
+ * and fills the report.  Errors: LGF_E_INVALID (null/misaligned pointers),
+ * LGF_E_DEVICE.  Calls that share a plan must not overlap in time: the plan
+ * owns one workspace.
+ */
+lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream,
+                     lgf_report *rep);
+
+/*
+ * Solve n independent requests with one launch per pipeline stage: the block
+ * FFTs, spectral products and inverse FFTs of all requests that share block
+ * size and precision run in common grids.  Each u[i] equals what
+ * lgf_solve(plans[i], f[i], u[i], ...) writes, bit for bit (every request's
+ * reduction order is fixed by its own plan).  The plans must be distinct
+ * and come from `ctx`.  `reps` (optional) has n entries.
+ */
+lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans,
+                           const double *const *f, double *const *u, void *stream,
+                           lgf_report *reps);
+
+/*
+ * Evaluate the context's device LGF table at n lattice points (host arrays:
+ * ijk [n][3] int32 in, out [n] float64): the exact near field for
+ * max|n_i| <= lgf_table_radius(), the asymptotic series beyond (Sec. 5,
+ * "exact values for near points, asymptotic expansions for far points").
+ */
+lgf_status lgf_table_values(lgf_context *ctx, int64_t n, const int32_t *ijk, double *out);
+int lgf_table_radius(void);
+
+/*
+ * One LGF block spectrum (host out, (2nb)^2 (nb+1) complex float64 as
+ * interleaved re/im): the r2c FFT of the window G(d*nb + m),
+ * m in [-(nb-1), nb-1]^3, laid circularly on a (2nb)^3 grid.  Index
+ * [kz][ky][kx], kx in [0, nb].  The spectrum is computed on the device.
+ */
+lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], double *out);
+
+/*
+ * Stage timing for measurement.  While enabled, every solve on this context
+ * records HIP events around each launch of the forward block FFT, the
+ * spectral multiply-accumulate and the inverse block FFT, on the stream the
+ * launch uses (no synchronisation is added).  lgf_context_stage_times waits
+ * for the recorded events, returns the summed milliseconds and launch
+ * counts per stage (index 0 forward FFT, 1 spectral MAC, 2 inverse FFT,
+ * 3 everything else), and clears them.  ms and launches have 4 entries.
+ */
+lgf_status lgf_context_set_timing(lgf_context *ctx, int enable);
+lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
+
+const char *lgf_last_error(void);
+const char *lgf_status_string(lgf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGF_H */

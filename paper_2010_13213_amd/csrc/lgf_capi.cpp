@@ -1,0 +1,310 @@
+// extern "C" entry points of include/lgf.h.  Every call converts failures
+// into an lgf_status and a thread-local message; no exception crosses.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lgf.h"
+#include "lgf_device.hpp"
+#include "lgf_runtime.hpp"
+
+using namespace lgf;
+
+namespace {
+
+template <typename F> lgf_status guard(F &&f) {
+    try {
+        f();
+        return LGF_OK;
+    } catch (const Failure &e) {
+        set_error(e.what());
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return LGF_E_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return LGF_E_DEVICE;
+    }
+}
+
+void require(bool ok, const std::string &msg) {
+    if (!ok) throw Failure(LGF_E_INVALID, msg);
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != dev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) hipSetDevice(prev);
+    }
+};
+
+using Key = std::tuple<int, int, int>;
+
+void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
+    require(d != nullptr, "null problem");
+    require(d->n_levels >= 1 && d->n_levels <= 8, "n_levels must be in [1, 8]");
+    require(d->nb == 8 || d->nb == 16, "nb must be 8 or 16");
+    require(d->dx0 > 0 && std::isfinite(d->dx0), "dx0 must be positive");
+    require(d->n_components == 1 || d->n_components == 3, "n_components must be 1 or 3");
+    require(d->precision == LGF_FP64 || d->precision == LGF_FP32_REFINE, "unknown precision");
+    require(d->ne_blocks >= 0 && d->ne_blocks <= 4, "ne_blocks must be in [0, 4]");
+    require(d->levels != nullptr, "null levels");
+    p->K = d->n_levels;
+    p->nb = d->nb;
+    p->nc = d->n_components;
+    p->prec = d->precision;
+    p->ne = d->ne_blocks == 0 ? 1 : d->ne_blocks;
+    p->dx0 = d->dx0;
+    const int64_t nb3 = (int64_t)d->nb * d->nb * d->nb;
+    int64_t base = 0;
+    std::vector<std::set<Key>> sets(p->K);
+    for (int k = 0; k < p->K; ++k) {
+        const lgf_level &L = d->levels[k];
+        require(L.n_blocks >= 1, "every level needs at least one block");
+        require(L.block_ijk != nullptr, "null block list");
+        std::vector<Blk> v;
+        v.reserve(L.n_blocks);
+        for (int i = 0; i < L.n_blocks; ++i) {
+            Blk b;
+            for (int a = 0; a < 3; ++a) {
+                b.ijk[a] = L.block_ijk[3 * i + a];
+                require(b.ijk[a] > -(1 << 20) && b.ijk[a] < (1 << 20), "block coordinate out of range");
+            }
+            b.off = base + (int64_t)i * nb3;
+            require(sets[k].insert(Key(b.ijk[0], b.ijk[1], b.ijk[2])).second, "duplicate block in a level");
+            v.push_back(b);
+        }
+        p->level_base.push_back(base);
+        base += (int64_t)L.n_blocks * nb3;
+        p->levels.push_back(std::move(v));
+    }
+    p->comp_len = base;
+    // nesting: a level-(k+1) block's parent octant lies in a level-k block
+    auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    for (int k = 1; k < p->K; ++k)
+        for (const auto &b : p->levels[k])
+            require(sets[k - 1].count(Key(fdiv(b.ijk[0], 2), fdiv(b.ijk[1], 2), fdiv(b.ijk[2], 2))) > 0,
+                    "level " + std::to_string(k) + " block outside level " + std::to_string(k - 1));
+}
+
+}  // namespace
+
+size_t lgf_plan::workspace_bytes() const {
+    size_t b = Fhat.bytes + Uhat.bytes;
+    for (auto &c : convs)
+        b += c->d_src_slot.bytes + c->d_tgt_slot.bytes + c->d_src_off.bytes + c->d_tgt_off.bytes +
+             c->d_rows.bytes + c->d_tiles.bytes;
+    return b;
+}
+
+extern "C" {
+
+lgf_status lgf_context_create(int device, size_t hbm_budget_bytes, lgf_context **out) {
+    if (!out) {
+        set_error("null out pointer");
+        return LGF_E_INVALID;
+    }
+    *out = nullptr;
+    lgf_context *ctx = nullptr;
+    lgf_status st = guard([&] {
+        int n = 0;
+        hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+        require(device >= 0 && device < n, "no such device");
+        DeviceScope ds(device);
+        ctx = new lgf_context(device, hbm_budget_bytes);
+        hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "hipStreamCreate");
+        build_context_table(ctx);
+    });
+    if (st != LGF_OK) {
+        if (ctx) lgf_context_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return LGF_OK;
+}
+
+void lgf_context_destroy(lgf_context *ctx) {
+    if (!ctx) return;
+    int prev = -1;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &e : ctx->pending) {
+        (void)hipEventSynchronize(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->pending.clear();
+    ctx->tables.clear();
+    ctx->gcube.release();
+    if (ctx->stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+    if (prev >= 0) hipSetDevice(prev);
+}
+
+size_t lgf_context_bytes(const lgf_context *ctx) { return ctx ? ctx->used : 0; }
+
+lgf_status lgf_plan_create(lgf_context *ctx, const lgf_problem *desc, lgf_plan **out) {
+    if (!ctx || !out) {
+        set_error("null context or out pointer");
+        return LGF_E_INVALID;
+    }
+    *out = nullptr;
+    lgf_plan *p = new lgf_plan();
+    p->ctx = ctx;
+    lgf_status st = guard([&] {
+        DeviceScope ds(ctx->device);
+        validate_and_copy(p, desc);
+        build_schedule(p);
+    });
+    if (st != LGF_OK) {
+        lgf_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return LGF_OK;
+}
+
+lgf_status lgf_problem_check(const lgf_problem *desc) {
+    return guard([&] {
+        lgf_plan tmp;
+        validate_and_copy(&tmp, desc);
+    });
+}
+
+void lgf_plan_destroy(lgf_plan *plan) {
+    if (!plan) return;
+    int prev = -1;
+    hipGetDevice(&prev);
+    hipSetDevice(plan->ctx->device);
+    hipDeviceSynchronize();
+    delete plan;
+    if (prev >= 0) hipSetDevice(prev);
+}
+
+size_t lgf_plan_workspace_bytes(const lgf_plan *plan) { return plan ? plan->workspace_bytes() : 0; }
+
+size_t lgf_plan_cells(const lgf_plan *plan, int level) {
+    if (!plan || level < 0 || level >= plan->K) return 0;
+    return plan->levels[level].size() * (size_t)plan->nb * plan->nb * plan->nb;
+}
+
+size_t lgf_plan_field_len(const lgf_plan *plan) { return plan ? (size_t)plan->comp_len * plan->nc : 0; }
+
+lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream, lgf_report *rep) {
+    return guard([&] {
+        require(plan != nullptr, "null plan");
+        require(f != nullptr && u != nullptr, "null field pointer");
+        require(((uintptr_t)f % 8) == 0 && ((uintptr_t)u % 8) == 0, "misaligned field pointer");
+        DeviceScope ds(plan->ctx->device);
+        run_plan(plan, f, u, (hipStream_t)stream, rep);
+    });
+}
+
+lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f,
+                           double *const *u, void *stream, lgf_report *reps) {
+    return guard([&] {
+        require(ctx != nullptr && n >= 0, "bad batch arguments");
+        if (n == 0) return;
+        require(plans && f && u, "null batch arrays");
+        std::set<const lgf_plan *> seen;
+        for (int i = 0; i < n; ++i) {
+            require(plans[i] && plans[i]->ctx == ctx, "plan from another context");
+            require(seen.insert(plans[i]).second, "a plan appears twice in one batch");
+            require(f[i] && u[i], "null field pointer");
+        }
+        DeviceScope ds(ctx->device);
+        run_batch(ctx, n, plans, f, u, (hipStream_t)stream, reps);
+    });
+}
+
+int lgf_table_radius(void) { return kTableRadius; }
+
+lgf_status lgf_table_values(lgf_context *ctx, int64_t n, const int32_t *ijk, double *out) {
+    return guard([&] {
+        require(ctx && n >= 0, "bad arguments");
+        if (n == 0) return;
+        require(ijk && out, "null arrays");
+        DeviceScope ds(ctx->device);
+        DeviceBuffer di, dout;
+        di.alloc(ctx, sizeof(int32_t) * 3 * n, "points");
+        dout.alloc(ctx, sizeof(double) * n, "values");
+        hip_check(hipMemcpy(di.ptr, ijk, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice), "upload");
+        hip_check(eval_lgf_points((const double *)ctx->gcube.ptr, (const int *)di.ptr, (double *)dout.ptr, n,
+                                  ctx->stream),
+                  "eval");
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        hip_check(hipMemcpy(out, dout.ptr, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
+    });
+}
+
+lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], double *out) {
+    return guard([&] {
+        require(ctx && d && out, "null arguments");
+        require(nb == 8 || nb == 16, "nb must be 8 or 16");
+        const int XH = std::abs(d[0]), YH = std::abs(d[1]), ZH = std::abs(d[2]);
+        require(XH <= 64 && YH <= 64 && ZH <= 64, "offset too large");
+        DeviceScope ds(ctx->device);
+        // build a private table for exactly this half-width box, copy one offset out
+        SpecTable t;
+        const int N = 2 * nb, H = nb + 1;
+        const size_t n_freq = (size_t)N * N * H;
+        const size_t n_off = (size_t)(2 * XH + 1) * (2 * YH + 1) * (2 * ZH + 1);
+        t.data.alloc(ctx, 16 * n_off * n_freq, "spectrum");
+        DeviceBuffer scratch;
+        scratch.alloc(ctx, 16 * n_freq * std::min<size_t>(n_off, 512), "spectrum scratch");
+        hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, XH, YH, ZH, false, t.data.ptr, scratch.ptr,
+                                scratch.bytes, ctx->stream),
+                  "build_spectra");
+        hip_check(hipStreamSynchronize(ctx->stream), "sync");
+        const size_t o = ((size_t)(d[1] + YH) * (2 * ZH + 1) + (d[2] + ZH)) * (2 * XH + 1) + (d[0] + XH);
+        std::vector<double> all(2 * n_off * n_freq);
+        hip_check(hipMemcpy(all.data(), t.data.ptr, all.size() * 8, hipMemcpyDeviceToHost), "download");
+        for (size_t w = 0; w < n_freq; ++w) {
+            out[2 * w] = all[2 * (w * n_off + o)];
+            out[2 * w + 1] = all[2 * (w * n_off + o) + 1];
+        }
+    });
+}
+
+lgf_status lgf_context_set_timing(lgf_context *ctx, int enable) {
+    return guard([&] {
+        require(ctx != nullptr, "null context");
+        ctx->timing = enable != 0;
+    });
+}
+
+lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launches) {
+    return guard([&] {
+        require(ctx && ms && launches, "null arguments");
+        DeviceScope ds(ctx->device);
+        resolve_stage_times(ctx, ms, launches);
+    });
+}
+
+const char *lgf_last_error(void) { return g_last_error.c_str(); }
+
+const char *lgf_status_string(lgf_status s) {
+    switch (s) {
+    case LGF_OK: return "LGF_OK";
+    case LGF_E_INVALID: return "LGF_E_INVALID";
+    case LGF_E_NOMEM: return "LGF_E_NOMEM";
+    case LGF_E_DEVICE: return "LGF_E_DEVICE";
+    case LGF_E_UNSUPPORTED: return "LGF_E_UNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Device-side building blocks shared by the LGF kernels (gfx950).
+//
+// * cplx<R>: a 2-vector complex number in float or double.
+// * fft_reg<N, INV>: an in-register radix-2 FFT of length N (16 or 32) on a
+//   per-thread array; all indices are compile-time so the array lives in
+//   VGPRs.  Forward uses exp(-2 pi i k / N), inverse exp(+2 pi i k / N), no
+//   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 32),
+//   folded into the unrolled butterflies.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgf {
+
+template <typename R> struct alignas(2 * sizeof(R)) cplx {
+    R x, y;
+};
+
+template <typename R> __device__ __forceinline__ cplx<R> cmake(R a, R b) {
+    cplx<R> c;
+    c.x = a;
+    c.y = b;
+    return c;
+}
+template <typename R> __device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) {
+    return cmake(a.x + b.x, a.y + b.y);
+}
+template <typename R> __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) {
+    return cmake(a.x - b.x, a.y - b.y);
+}
+template <typename R> __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return cmake(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc + a * b with four fused multiply-adds
+template <typename R> __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<R> a, cplx<R> b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+
+// exp(-2 pi i k / 32), k = 0..15, as (cos, -sin) pairs.
+constexpr double kTw32[16][2] = {
+    {1.0, 0.0},
+    {9.80785280403230449126e-1, -1.95090322016128267848e-1},
+    {9.23879532511286756128e-1, -3.82683432365089771728e-1},
+    {8.31469612302545237079e-1, -5.55570233019602224743e-1},
+    {7.07106781186547524401e-1, -7.07106781186547524401e-1},
+    {5.55570233019602224743e-1, -8.31469612302545237079e-1},
+    {3.82683432365089771728e-1, -9.23879532511286756128e-1},
+    {1.95090322016128267848e-1, -9.80785280403230449126e-1},
+    {0.0, -1.0},
+    {-1.95090322016128267848e-1, -9.80785280403230449126e-1},
+    {-3.82683432365089771728e-1, -9.23879532511286756128e-1},
+    {-5.55570233019602224743e-1, -8.31469612302545237079e-1},
+    {-7.07106781186547524401e-1, -7.07106781186547524401e-1},
+    {-8.31469612302545237079e-1, -5.55570233019602224743e-1},
+    {-9.23879532511286756128e-1, -3.82683432365089771728e-1},
+    {-9.80785280403230449126e-1, -1.95090322016128267848e-1},
+};
+
+template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle(int k) {
+    // exp(-+2 pi i k / N) = table entry k * (32 / N)
+    const int j = k * (32 / N);
+    const R c = (R)kTw32[j][0];
+    const R s = (R)kTw32[j][1];
+    return INV ? cmake(c, -s) : cmake(c, s);
+}
+
+template <int N> struct bitrev {
+    static constexpr int L = (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : 2;
+    static __host__ __device__ constexpr int of(int i) {
+        int r = 0;
+        for (int b = 0; b < L; ++b)
+            if (i & (1 << b)) r |= 1 << (L - 1 - b);
+        return r;
+    }
+};
+
+// In-register radix-2 decimation-in-time FFT.
+template <typename R, int N, bool INV> __device__ __forceinline__ void fft_reg(cplx<R> (&a)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = bitrev<N>::of(i);
+        if (j > i) {
+            cplx<R> t = a[i];
+            a[i] = a[j];
+            a[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= N; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int i = 0; i < N; i += len) {
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                cplx<R> v = a[i + k + half];
+                if (k != 0) v = cmul(v, twiddle<R, N, INV>(k * (N / len)));
+                const cplx<R> u = a[i + k];
+                a[i + k] = cadd(u, v);
+                a[i + k + half] = csub(u, v);
+            }
+        }
+    }
+}
+
+// ---- LGF lookup (device table + asymptotic series) ----------------------
+
+constexpr int kTableRadius = 128;       // exact near field for max|n_i| <= 128
+
+// Asymptotic LGF of the unscaled 7-point Laplacian for large |n| (three
+// corrections beyond -1/(4 pi r)); coefficients from the symbol expansion of
+// sum_i 4 sin^2(theta_i / 2).
+__device__ __forceinline__ double lgf_far(double x, double y, double z) {
+    const double pi = 3.14159265358979323846;
+    const double x2 = x * x, y2 = y * y, z2 = z * z;
+    const double x4 = x2 * x2, y4 = y2 * y2, z4 = z2 * z2;
+    const double x6 = x4 * x2, y6 = y4 * y2, z6 = z4 * z2;
+    const double x8 = x4 * x4, y8 = y4 * y4, z8 = z4 * z4;
+    const double p2 = x2 * y2 * z2;
+    const double r2 = x2 + y2 + z2;
+    const double r = sqrt(r2);
+    const double s4 = x4 + y4 + z4;
+    const double m22 = x2 * y2 + y2 * z2 + z2 * x2;
+    const double q4 = s4 - 3.0 * m22;
+    const double q8 = 23.0 * (x8 + y8 + z8) - 244.0 * (x6 * (y2 + z2) + y6 * (z2 + x2) + z6 * (x2 + y2)) +
+                      621.0 * (x4 * y4 + y4 * z4 + z4 * x4) - 228.0 * p2 * r2;
+    const double q12 = 647.0 * (x6 * x6 + y6 * y6 + z6 * z6) -
+                       16419.0 * (x8 * x2 * (y2 + z2) + y8 * y2 * (z2 + x2) + z8 * z2 * (x2 + y2)) +
+                       106536.0 * (x8 * (y4 + z4) + y8 * (z4 + x4) + z8 * (x4 + y4)) -
+                       15723.0 * p2 * (x6 + y6 + z6) - 178221.0 * (x6 * y6 + y6 * z6 + z6 * x6) -
+                       74469.0 * p2 * (x4 * (y2 + z2) + y4 * (z2 + x2) + z4 * (x2 + y2)) +
+                       626835.0 * x4 * y4 * z4;
+    const double ir = 1.0 / r;
+    const double ir2 = ir * ir;
+    const double ir6 = ir2 * ir2 * ir2;
+    const double g = ir * (0.25 / pi) * (1.0 + q4 * ir6 * 0.25 + q8 * ir6 * ir6 * (1.0 / 32.0) +
+                                        q12 * ir6 * ir6 * ir6 * (1.0 / 128.0));
+    return -g;
+}
+
+// G(n) from the dense near cube gc[(a*(R+1) + b)*(R+1) + c], a,b,c = |n_i|.
+__device__ __forceinline__ double lgf_G(const double *__restrict__ gc, int nx, int ny, int nz) {
+    const int a = abs(nx), b = abs(ny), c = abs(nz);
+    if (a <= kTableRadius && b <= kTableRadius && c <= kTableRadius) {
+        const int s = kTableRadius + 1;
+        return gc[((size_t)a * s + b) * s + c];
+    }
+    return lgf_far((double)a, (double)b, (double)c);
+}
+
+}  // namespace lgf

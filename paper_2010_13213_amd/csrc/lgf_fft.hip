@@ -1,0 +1,193 @@
+// Batched zero-padded (2nb)^3 block FFTs staged in LDS (gfx950).
+//
+// The LGF convolution of one source block with one target block (paper
+// Sec. 2.2, eq. lgf_convolution, evaluated blockwise) is a linear
+// convolution of an nb^3 block with a (2nb-1)^3 kernel window; zero-padding
+// the block to (2nb)^3 makes the circular convolution of the FFT exact.
+//
+// Forward (one workgroup per source block, 256 threads):
+//   x: nb^2 rows of nb reals, zero-padded to N = 2nb -> N/2+1 complex  (LDS A)
+//   y: nb (N/2+1) columns, zero-padded to N                            (LDS B, half of kx at a time)
+//   z: N (N/2+1) columns, zero-padded to N -> written frequency-major to HBM
+// The zero half of the input is never loaded.  Inverse runs the same stages
+// backwards and keeps only the [0, nb)^3 corner of the result.
+#include "lgf_device.hpp"
+#include "lgf_kernels.hpp"
+
+namespace lgf {
+
+namespace {
+
+template <int NB, typename R> struct FftShape {
+    static constexpr int N = 2 * NB;
+    static constexpr int H = NB + 1;            // r2c length along x
+    static constexpr int HH = (H + 1) / 2;      // kx handled per half
+    static constexpr int A_ELEMS = NB * NB * H; // [z][y][kx]
+    static constexpr int B_ELEMS = NB * N * HH; // [z][ky][kxl]
+    static constexpr int NT = 256;
+};
+
+template <int NB, typename R>
+__global__ void __launch_bounds__(256) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
+                                                  const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
+                                                  int64_t n_slots, double scale) {
+    using S = FftShape<NB, R>;
+    constexpr int N = S::N, H = S::H, HH = S::HH;
+    __shared__ cplx<R> A[S::A_ELEMS];
+    __shared__ cplx<R> B[S::B_ELEMS];
+    const int b = blockIdx.x;
+    const double *in = src + blk_off[b];
+    const int64_t sl = slot[b];
+    const int t = threadIdx.x;
+
+    // x pass: row (y, z)
+    for (int line = t; line < NB * NB; line += S::NT) {
+        const int y = line % NB, z = line / NB;
+        cplx<R> a[N];
+        const double *row = in + ((size_t)z * NB + y) * NB;
+#pragma unroll
+        for (int x = 0; x < N; ++x) a[x] = cmake<R>(x < NB ? (R)(row[x] * scale) : (R)0, (R)0);
+        fft_reg<R, N, false>(a);
+#pragma unroll
+        for (int k = 0; k < H; ++k) A[(z * NB + y) * H + k] = a[k];
+    }
+    __syncthreads();
+
+    for (int half = 0; half < 2; ++half) {
+        const int k0 = half * HH;
+        const int nk = (half == 0) ? HH : H - HH;
+        // y pass: column (z, kx)
+        for (int line = t; line < NB * nk; line += S::NT) {
+            const int kxl = line % nk, z = line / nk;
+            cplx<R> a[N];
+#pragma unroll
+            for (int y = 0; y < N; ++y) a[y] = y < NB ? A[(z * NB + y) * H + k0 + kxl] : cmake<R>((R)0, (R)0);
+            fft_reg<R, N, false>(a);
+#pragma unroll
+            for (int ky = 0; ky < N; ++ky) B[(z * N + ky) * HH + kxl] = a[ky];
+        }
+        __syncthreads();
+        // z pass: column (ky, kx) -> HBM
+        for (int line = t; line < N * nk; line += S::NT) {
+            const int kxl = line % nk, ky = line / nk;
+            cplx<R> a[N];
+#pragma unroll
+            for (int z = 0; z < N; ++z) a[z] = z < NB ? B[(z * N + ky) * HH + kxl] : cmake<R>((R)0, (R)0);
+            fft_reg<R, N, false>(a);
+            const int kx = k0 + kxl;
+#pragma unroll
+            for (int kz = 0; kz < N; ++kz) {
+                const int64_t omega = ((int64_t)kz * N + ky) * H + kx;
+                Fhat[omega * n_slots + sl] = a[kz];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NB, typename R>
+__global__ void __launch_bounds__(256) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+                                                  const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
+                                                  double *__restrict__ dst, double scale, int accumulate) {
+    using S = FftShape<NB, R>;
+    constexpr int N = S::N, H = S::H, HH = S::HH;
+    __shared__ cplx<R> D[S::A_ELEMS];   // [z][y][kx] after the z and y passes
+    __shared__ cplx<R> C[S::B_ELEMS];   // [z][ky][kxl]
+    const int b = blockIdx.x;
+    const int64_t sl = slot[b];
+    const int t = threadIdx.x;
+
+    for (int half = 0; half < 2; ++half) {
+        const int k0 = half * HH;
+        const int nk = (half == 0) ? HH : H - HH;
+        // inverse z pass: column (ky, kx) from HBM, keep z < nb
+        for (int line = t; line < N * nk; line += S::NT) {
+            const int kxl = line % nk, ky = line / nk;
+            const int kx = k0 + kxl;
+            cplx<R> a[N];
+#pragma unroll
+            for (int kz = 0; kz < N; ++kz) {
+                const int64_t omega = ((int64_t)kz * N + ky) * H + kx;
+                a[kz] = Uhat[omega * n_slots + sl];
+            }
+            fft_reg<R, N, true>(a);
+#pragma unroll
+            for (int z = 0; z < NB; ++z) C[(z * N + ky) * HH + kxl] = a[z];
+        }
+        __syncthreads();
+        // inverse y pass: column (z, kx), keep y < nb
+        for (int line = t; line < NB * nk; line += S::NT) {
+            const int kxl = line % nk, z = line / nk;
+            cplx<R> a[N];
+#pragma unroll
+            for (int ky = 0; ky < N; ++ky) a[ky] = C[(z * N + ky) * HH + kxl];
+            fft_reg<R, N, true>(a);
+#pragma unroll
+            for (int y = 0; y < NB; ++y) D[(z * NB + y) * H + k0 + kxl] = a[y];
+        }
+        __syncthreads();
+    }
+    // inverse x pass (complex-to-real): row (y, z), keep x < nb
+    double *out = dst + blk_off[b];
+    for (int line = t; line < NB * NB; line += S::NT) {
+        const int y = line % NB, z = line / NB;
+        cplx<R> a[N];
+        const cplx<R> *row = D + (z * NB + y) * H;
+#pragma unroll
+        for (int k = 0; k < H; ++k) a[k] = row[k];
+#pragma unroll
+        for (int k = 1; k < N / 2; ++k) a[N - k] = cmake<R>(row[k].x, -row[k].y);
+        fft_reg<R, N, true>(a);
+        double *o = out + ((size_t)z * NB + y) * NB;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) {
+            const double v = (double)a[x].x * scale;
+            o[x] = accumulate ? o[x] + v : v;
+        }
+    }
+}
+
+template <int NB, typename R>
+hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
+                      int64_t n_slots, double scale, hipStream_t s) {
+    if (n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks), dim3(256), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
+                       n_slots, scale);
+    return hipGetLastError();
+}
+
+template <int NB, typename R>
+hipError_t inv_launch(const void *Uhat, int64_t n_slots, const int *slot, const int64_t *blk_off, int n_blocks,
+                      double *dst, double scale, int accumulate, hipStream_t s) {
+    if (n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((inv_kernel<NB, R>), dim3(n_blocks), dim3(256), 0, s, (const cplx<R> *)Uhat, n_slots, slot,
+                       blk_off, dst, scale, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t *blk_off, const int *slot,
+                             int n_blocks, void *Fhat, int64_t n_slots, double scale, hipStream_t s) {
+    if (nb == 16)
+        return fp32 ? fwd_launch<16, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s)
+                    : fwd_launch<16, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s);
+    if (nb == 8)
+        return fp32 ? fwd_launch<8, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s)
+                    : fwd_launch<8, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, const int *slot,
+                             const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
+                             hipStream_t s) {
+    if (nb == 16)
+        return fp32 ? inv_launch<16, float>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s)
+                    : inv_launch<16, double>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s);
+    if (nb == 8)
+        return fp32 ? inv_launch<8, float>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s)
+                    : inv_launch<8, double>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lgf

@@ -1,0 +1,48 @@
+// Host-side launch entry points of the LGF device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lgf {
+
+// ---- table / spectra (lgf_table.hip) ----
+int lgf_table_nodes();
+// gcube: (R+1)^3 doubles; B: nodes*(R+1) doubles; w: nodes doubles.
+hipError_t build_lgf_table(double *gcube, double *B, double *w, hipStream_t s);
+hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int64_t n, hipStream_t s);
+// Spectra of every block offset in [-XH,XH] x [-YH,YH] x [-ZH,ZH] into
+// table[omega][dy+YH][dz+ZH][dx+XH] (complex float or double).
+hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bool fp32, void *table,
+                         void *scratch, size_t scratch_bytes, hipStream_t s);
+
+// ---- block FFTs (lgf_fft.hip) ----
+// Forward: for each listed block i, read the nb^3 float64 values at
+// src + blk_off[i] (elements), multiply by `scale`, zero-pad to (2nb)^3,
+// r2c-transform and store spectrum value omega at Fhat[omega * n_slots + slot[i]].
+hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t *blk_off, const int *slot,
+                             int n_blocks, void *Fhat, int64_t n_slots, double scale, hipStream_t s);
+// Inverse: for each listed block i, gather Uhat[omega * n_slots + slot[i]],
+// c2r-transform, keep the [0, nb)^3 corner, multiply by `scale` and write
+// (accumulate = 0) or add (accumulate = 1) into dst + blk_off[i].
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, const int *slot,
+                             const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
+                             hipStream_t s);
+
+// ---- spectral multiply-accumulate (lgf_smac.hip) ----
+struct SmacGeom {
+    int bx;                 // row length template (8, 16 or 32)
+    int ey, ez;             // padded box extent in blocks along y, z (slots)
+    int n_freq;
+    int64_t n_slots;        // bx * ey * ez
+    int XH, YH, ZH, XD, YD, ZD;   // spectra table half-widths and dims
+    int n_rows;             // source rows (sy, sz), serpentine order
+    int n_tiles;            // target tiles (ty0, tz0)
+};
+int smac_tile_y(int bx);
+int smac_tile_z(int bx);
+// Uhat[omega][t] = sum_s K[omega][t - s] * Fhat[omega][s] over every source row
+// and every target slot of each tile.
+hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
+                       const int2 *rows, const int2 *tiles, hipStream_t s);
+
+}  // namespace lgf

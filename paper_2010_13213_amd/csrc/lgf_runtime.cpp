@@ -1,0 +1,292 @@
+// Native runtime behind the C ABI of include/lgf.h: contexts (device LGF
+// table, spectra cache, HBM budget), plans (validated block lists, level
+// schedule, slot maps, work lists, workspaces) and the solve pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lgf.h"
+#include "lgf_device.hpp"
+#include "lgf_kernels.hpp"
+#include "lgf_runtime.hpp"
+
+namespace lgf {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+
+Failure::Failure(lgf_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw Failure(LGF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ memory
+
+DeviceBuffer::~DeviceBuffer() { release(); }
+
+void DeviceBuffer::release() {
+    if (ptr) {
+        (void)hipFree(ptr);
+        if (owner) owner->used -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void DeviceBuffer::alloc(lgf_context *ctx, size_t n, const char *what) {
+    release();
+    if (n == 0) return;
+    if (ctx->budget && ctx->used + n > ctx->budget)
+        throw Failure(LGF_E_NOMEM, std::string("HBM budget exceeded allocating ") + what);
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        throw Failure(LGF_E_NOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    bytes = n;
+    owner = ctx;
+    ctx->used += n;
+}
+
+// ------------------------------------------------------------------ timing
+
+StageTimer::StageTimer(lgf_context *c, int st, hipStream_t s_) : ctx(c), stage(st), s(s_) {
+    if (!ctx->timing) return;
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventRecord(a, s), "event record");
+}
+
+StageTimer::~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
+        ctx->pending.push_back(StageEvent{stage, a, b});
+    } else {
+        (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+}
+
+void resolve_stage_times(lgf_context *ctx, double *ms, int64_t *launches) {
+    for (int i = 0; i < 4; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto &e : ctx->pending) {
+        hip_check(hipEventSynchronize(e.b), "event sync");
+        float t = 0.f;
+        hip_check(hipEventElapsedTime(&t, e.a, e.b), "elapsed");
+        ms[e.stage] += t;
+        launches[e.stage] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    ctx->pending.clear();
+}
+
+// ------------------------------------------------------------------ context
+
+lgf_context_impl::lgf_context_impl(int dev, size_t budget_) : device(dev), budget(budget_) {}
+
+void build_context_table(lgf_context *ctx) {
+    const int S = kTableRadius + 1;
+    ctx->gcube.alloc(ctx, sizeof(double) * (size_t)S * S * S, "LGF table");
+    DeviceBuffer B, w;
+    const int nodes = lgf_table_nodes();
+    B.alloc(ctx, sizeof(double) * (size_t)nodes * S, "Bessel rows");
+    w.alloc(ctx, sizeof(double) * nodes, "quadrature weights");
+    hip_check(build_lgf_table((double *)ctx->gcube.ptr, (double *)B.ptr, (double *)w.ptr, ctx->stream),
+              "build_lgf_table");
+    hip_check(hipStreamSynchronize(ctx->stream), "table sync");
+}
+
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &t : ctx->tables)
+        if (t->nb == nb && t->fp32 == fp32 && t->XH >= XH && t->YH >= YH && t->ZH >= ZH) return t.get();
+    auto t = std::make_unique<SpecTable>();
+    t->nb = nb;
+    t->fp32 = fp32;
+    t->XH = XH;
+    t->YH = YH;
+    t->ZH = ZH;
+    const int N = 2 * nb;
+    t->n_freq = N * N * (nb + 1);
+    const size_t n_off = (size_t)(2 * XH + 1) * (2 * YH + 1) * (2 * ZH + 1);
+    const size_t elem = fp32 ? 8 : 16;
+    t->data.alloc(ctx, elem * n_off * t->n_freq, "LGF block spectra");
+    DeviceBuffer scratch;
+    const size_t per_off = (size_t)t->n_freq * 16;
+    const size_t want = std::min<size_t>(n_off, 2048) * per_off;
+    scratch.alloc(ctx, want, "spectra scratch");
+    hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, XH, YH, ZH, fp32, t->data.ptr, scratch.ptr,
+                            scratch.bytes, ctx->stream),
+              "build_spectra");
+    hip_check(hipStreamSynchronize(ctx->stream), "spectra sync");
+    ctx->tables.push_back(std::move(t));
+    return ctx->tables.back().get();
+}
+
+// ------------------------------------------------------------------ plan
+
+static int pick_bx(int ex) {
+    if (ex <= 8) return 8;
+    if (ex <= 16) return 16;
+    if (ex <= 32) return 32;
+    return -1;
+}
+
+static int roundup(int a, int m) { return (a + m - 1) / m * m; }
+
+// Build a convolution: sources `src` and targets `tgt` (block coords of one
+// level), field offsets (in elements, per component) of each block.
+void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32) {
+    lgf_context *ctx = plan->ctx;
+    const int nb = plan->nb;
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (const auto *v : {&src, &tgt})
+        for (const auto &b : *v)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], b.ijk[a]);
+                hi[a] = std::max(hi[a], b.ijk[a]);
+            }
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int bx = pick_bx(ex);
+    if (bx < 0 || ey > 64 || ez > 64)
+        throw Failure(LGF_E_UNSUPPORTED, "level extent above 32 blocks along x or 64 along y/z");
+    const int TY = smac_tile_y(bx), TZ = smac_tile_z(bx);
+    c.bx = bx;
+    c.ey = roundup(ey, TY);
+    c.ez = roundup(ez, TZ);
+    for (int a = 0; a < 3; ++a) c.lo[a] = lo[a];
+    c.n_slots = (int64_t)bx * c.ey * c.ez;
+    c.fp32 = fp32;
+    auto slot_of = [&](const Blk &b) -> int {
+        return ((b.ijk[2] - lo[2]) * c.ey + (b.ijk[1] - lo[1])) * bx + (b.ijk[0] - lo[0]);
+    };
+    std::vector<int> s_slot, t_slot;
+    std::vector<int64_t> s_off, t_off;
+    std::set<std::pair<int, int>> rowset;
+    std::set<std::pair<int, int>> tileset;
+    for (const auto &b : src) {
+        s_slot.push_back(slot_of(b));
+        s_off.push_back(b.off);
+        rowset.insert({b.ijk[2] - lo[2], b.ijk[1] - lo[1]});
+    }
+    for (const auto &b : tgt) {
+        t_slot.push_back(slot_of(b));
+        t_off.push_back(b.off);
+        tileset.insert({(b.ijk[2] - lo[2]) / TZ * TZ, (b.ijk[1] - lo[1]) / TY * TY});
+    }
+    // serpentine row order: z ascending, y alternating direction per z group
+    std::map<int, std::vector<int>> byz;
+    for (auto &r : rowset) byz[r.first].push_back(r.second);
+    std::vector<int2> rows;
+    int gi = 0;
+    for (auto &kv : byz) {
+        auto ys = kv.second;
+        std::sort(ys.begin(), ys.end());
+        if (gi & 1) std::reverse(ys.begin(), ys.end());
+        for (int y : ys) rows.push_back(make_int2(y, kv.first));
+        ++gi;
+    }
+    std::vector<int2> tiles;
+    for (auto &t : tileset) tiles.push_back(make_int2(t.second, t.first));
+    c.n_src = (int)src.size();
+    c.n_tgt = (int)tgt.size();
+    c.n_rows = (int)rows.size();
+    c.n_tiles = (int)tiles.size();
+    c.spec = get_spectra(ctx, nb, fp32, bx - 1, c.ey - 1, c.ez - 1);
+    c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
+    c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
+    c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
+    c.d_tgt_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, t_off.size()), "offsets");
+    c.d_rows.alloc(ctx, sizeof(int2) * std::max<size_t>(1, rows.size()), "rows");
+    c.d_tiles.alloc(ctx, sizeof(int2) * std::max<size_t>(1, tiles.size()), "tiles");
+    auto up = [&](DeviceBuffer &d, const void *h, size_t n) {
+        if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
+    };
+    up(c.d_src_slot, s_slot.data(), sizeof(int) * s_slot.size());
+    up(c.d_tgt_slot, t_slot.data(), sizeof(int) * t_slot.size());
+    up(c.d_src_off, s_off.data(), sizeof(int64_t) * s_off.size());
+    up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
+    up(c.d_rows, rows.data(), sizeof(int2) * rows.size());
+    up(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size());
+}
+
+SmacGeom conv_geom(const Conv &c) {
+    SmacGeom g;
+    g.bx = c.bx;
+    g.ey = c.ey;
+    g.ez = c.ez;
+    g.n_freq = c.spec->n_freq;
+    g.n_slots = c.n_slots;
+    g.XH = c.spec->XH;
+    g.YH = c.spec->YH;
+    g.ZH = c.spec->ZH;
+    g.XD = 2 * g.XH + 1;
+    g.YD = 2 * g.YH + 1;
+    g.ZD = 2 * g.ZH + 1;
+    g.n_rows = c.n_rows;
+    g.n_tiles = c.n_tiles;
+    return g;
+}
+
+// Spectral workspace large enough for every convolution of the plan.
+void plan_alloc_spectral(lgf_plan *plan) {
+    size_t need = 0;
+    for (auto &c : plan->convs) {
+        const size_t elem = c->fp32 ? 8 : 16;
+        need = std::max(need, elem * (size_t)c->spec->n_freq * (size_t)c->n_slots);
+    }
+    plan->Fhat.alloc(plan->ctx, need, "Fhat workspace");
+    plan->Uhat.alloc(plan->ctx, need, "Uhat workspace");
+}
+
+// Run one convolution: dst (+)= dx^2 * G * src on the conv's blocks.
+void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,
+              hipStream_t s) {
+    const int nb = plan->nb;
+    const double N3 = 8.0 * nb * nb * nb;
+    // empty slots of Fhat must read as zero; the forward FFT writes only
+    // occupied slots, so clear when another slot map used the buffer last
+    if (plan->fhat_conv != &c) {
+        hip_check(hipMemsetAsync(plan->Fhat.ptr, 0, plan->Fhat.bytes, s), "clear Fhat");
+        plan->fhat_conv = &c;
+    }
+    {
+        StageTimer t(plan->ctx, 0, s);
+        hip_check(block_fft_forward(nb, c.fp32, src, (const int64_t *)c.d_src_off.ptr,
+                                    (const int *)c.d_src_slot.ptr, c.n_src, plan->Fhat.ptr, c.n_slots, 1.0, s),
+                  "forward block FFT");
+    }
+    {
+        StageTimer t(plan->ctx, 1, s);
+        const SmacGeom g = conv_geom(c);
+        hip_check(smac_launch(g, c.fp32, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
+                              (const int2 *)c.d_rows.ptr, (const int2 *)c.d_tiles.ptr, s),
+                  "spectral MAC");
+    }
+    {
+        StageTimer t(plan->ctx, 2, s);
+        hip_check(block_fft_inverse(nb, c.fp32, plan->Uhat.ptr, c.n_slots, (const int *)c.d_tgt_slot.ptr,
+                                    (const int64_t *)c.d_tgt_off.ptr, c.n_tgt, dst, dx * dx / N3, accumulate, s),
+                  "inverse block FFT");
+    }
+}
+
+}  // namespace lgf

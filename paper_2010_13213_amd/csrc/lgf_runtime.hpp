@@ -1,0 +1,133 @@
+// Internal runtime types behind include/lgf.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lgf.h"
+#include "lgf_kernels.hpp"
+
+namespace lgf {
+
+extern thread_local std::string g_last_error;
+void set_error(const std::string &m);
+
+struct Failure : std::runtime_error {
+    lgf_status status;
+    Failure(lgf_status s, const std::string &m);
+};
+
+void hip_check(hipError_t e, const char *what);
+
+struct lgf_context_impl;
+}  // namespace lgf
+
+struct lgf_context;
+
+namespace lgf {
+
+// Device allocation accounted against a context's HBM budget.
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    lgf_context *owner = nullptr;
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer &) = delete;
+    DeviceBuffer &operator=(const DeviceBuffer &) = delete;
+    ~DeviceBuffer();
+    void alloc(lgf_context *ctx, size_t n, const char *what);
+    void release();
+};
+
+struct SpecTable {
+    int nb = 0;
+    bool fp32 = false;
+    int XH = 0, YH = 0, ZH = 0;
+    int n_freq = 0;
+    DeviceBuffer data;
+};
+
+// Event pair around one kernel launch, resolved lazily.
+struct StageEvent {
+    int stage;
+    hipEvent_t a, b;
+};
+
+struct lgf_context_impl {
+    int device;
+    bool timing = false;
+    std::vector<StageEvent> pending;
+    size_t budget;
+    size_t used = 0;
+    hipStream_t stream = nullptr;
+    DeviceBuffer gcube;
+    std::vector<std::unique_ptr<SpecTable>> tables;
+    std::mutex mu;
+    lgf_context_impl(int dev, size_t budget_);
+};
+
+// A block of one level: lattice block coordinates and the element offset of
+// its first cell inside one component's field (or a workspace field).
+struct Blk {
+    int ijk[3];
+    int64_t off;
+};
+
+// One blockwise LGF convolution on a level (sources -> targets).
+struct Conv {
+    int bx = 0, ey = 0, ez = 0;
+    int lo[3] = {0, 0, 0};
+    int64_t n_slots = 0;
+    bool fp32 = false;
+    int n_src = 0, n_tgt = 0, n_rows = 0, n_tiles = 0;
+    SpecTable *spec = nullptr;
+    DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off, d_rows, d_tiles;
+};
+
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
+SmacGeom conv_geom(const Conv &c);
+
+}  // namespace lgf
+
+struct lgf_context : lgf::lgf_context_impl {
+    using lgf::lgf_context_impl::lgf_context_impl;
+};
+
+struct lgf_plan {
+    lgf_context *ctx = nullptr;
+    int K = 1, nb = 16, nc = 1, prec = 0, ne = 1;
+    double dx0 = 1.0;
+    std::vector<std::vector<lgf::Blk>> levels;     // per level, offsets within one component
+    std::vector<int64_t> level_base;               // element offset of each level in a component
+    int64_t comp_len = 0;                          // elements per component
+    std::vector<std::unique_ptr<lgf::Conv>> convs;
+    lgf::DeviceBuffer Fhat, Uhat;
+    const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
+    size_t workspace_bytes() const;
+};
+
+namespace lgf {
+// Records an event before/after a stage launch when timing is on.
+struct StageTimer {
+    lgf_context *ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageTimer(lgf_context *c, int st, hipStream_t s_);
+    ~StageTimer();
+};
+void resolve_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
+void build_context_table(lgf_context *ctx);
+void build_schedule(lgf_plan *plan);
+void run_plan(lgf_plan *plan, const double *f, double *u, hipStream_t s, lgf_report *rep);
+void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
+               hipStream_t s, lgf_report *reps);
+void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32);
+void plan_alloc_spectral(lgf_plan *plan);
+void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,
+              hipStream_t s);
+}  // namespace lgf

@@ -1,0 +1,219 @@
+// Spectral multiply-accumulate of the blockwise LGF convolution (gfx950).
+//
+// After the forward block FFTs, the convolution of a level (paper Sec. 2.2,
+// eq. lgf_convolution; every block pair of the level, Sec. 5) is, at each
+// frequency omega, a convolution over the block lattice:
+//
+//     Uhat_t(omega) = sum_s Khat_{t-s}(omega) Fhat_s(omega).
+//
+// Data layout: slots s = (z * ey + y) * bx + x over a padded box of blocks,
+// Fhat / Uhat [omega][slot], spectra table K[omega][dy][dz][dx].
+//
+// One workgroup owns one frequency and one tile of TY x TZ target rows (a
+// row is the bx blocks along x at fixed (y, z)).  Lane (seg, ty, tz) keeps A
+// consecutive targets of its row in registers.  The workgroup walks the
+// source rows (sy, sz) in serpentine order; for each row every lane needs
+// the kernel row K[., ty - sy, tz - sz] (2 bx - 1 values along x), which
+// lives in an LDS ring buffer of (TY+1) x (TZ+1) kernel rows indexed by
+// (dy mod (TY+1), dz mod (TZ+1)).  A step of +-1 in sy or sz brings exactly
+// one new plane (TZ rows) or layer (TY rows); it is prefetched into
+// registers while the current row is computed and written to the free ring
+// slot, so each step costs one barrier.  Other jumps reload the window.
+// Inside a row the Toeplitz product U[i] += K[x0 + i - j] F[j] reuses each
+// loaded kernel value across the lane's A targets, and the source row F is
+// read by all lanes from one LDS address (broadcast).
+#include "lgf_device.hpp"
+#include "lgf_kernels.hpp"
+
+namespace lgf {
+
+namespace {
+
+__device__ __forceinline__ int pmod(int a, int m) {
+    const int r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+template <int BX, int A, int TY, int TZ> struct SmacCfg {
+    static constexpr int NSEG = BX / A;
+    static constexpr int NT = NSEG * TY * TZ;
+    static constexpr int KW = 2 * BX - 1;
+    static constexpr int SY = TY + 1, SZ = TZ + 1;
+    static constexpr int PLANE = (TY > TZ ? TY : TZ) * KW;    // max elements of a plane / layer
+    static constexpr int PER = (PLANE + NT - 1) / NT;          // per-lane prefetch slots
+};
+
+template <int BX, int A, int TY, int TZ, typename R>
+__global__ void __launch_bounds__((BX / A) * TY * TZ)
+    smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
+                const cplx<R> *__restrict__ Ktab, const int2 *__restrict__ rows, const int2 *__restrict__ tiles) {
+    using C = SmacCfg<BX, A, TY, TZ>;
+    constexpr int KW = C::KW, SY = C::SY, SZ = C::SZ, NT = C::NT;
+    __shared__ cplx<R> kbuf[SY * SZ * KW];
+    __shared__ cplx<R> frow[2][BX];
+
+    const int freq = blockIdx.x % g.n_freq;
+    const int tile = blockIdx.x / g.n_freq;
+    const int ty0 = tiles[tile].x, tz0 = tiles[tile].y;
+    const int l = threadIdx.x;
+    const int seg = l % C::NSEG;
+    const int r = l / C::NSEG;
+    const int tyl = r % TY, tzl = r / TY;
+    const int ty = ty0 + tyl, tz = tz0 + tzl;
+    const int x0 = seg * A;
+
+    const size_t kper = (size_t)g.XD * g.YD * g.ZD;
+    const cplx<R> *Kf = Ktab + (size_t)freq * kper;
+    const cplx<R> *Ff = Fhat + (size_t)freq * g.n_slots;
+
+    auto kidx = [&](int dy, int dz, int dxi) -> size_t {
+        // dxi in [0, KW): dx = dxi - (BX - 1)
+        return ((size_t)(dy + g.YH) * g.ZD + (dz + g.ZH)) * g.XD + (dxi - (BX - 1) + g.XH);
+    };
+    auto lds = [&](int dy, int dz, int dxi) -> int { return (pmod(dy, SY) * SZ + pmod(dz, SZ)) * KW + dxi; };
+
+    cplx<R> acc[A];
+#pragma unroll
+    for (int i = 0; i < A; ++i) acc[i] = cmake<R>((R)0, (R)0);
+
+    // full window load for row 0
+    int sy = rows[0].x, sz = rows[0].y;
+    {
+        const int dy0 = ty0 - sy, dz0 = tz0 - sz;
+        for (int e = l; e < TY * TZ * KW; e += NT) {
+            const int dxi = e % KW, q = e / KW;
+            const int dy = dy0 + q % TY, dz = dz0 + q / TY;
+            kbuf[lds(dy, dz, dxi)] = Kf[kidx(dy, dz, dxi)];
+        }
+        for (int e = l; e < BX; e += NT) frow[0][e] = Ff[((size_t)sz * g.ey + sy) * BX + e];
+    }
+    __syncthreads();
+
+    for (int ri = 0; ri < g.n_rows; ++ri) {
+        const int buf = ri & 1;
+        int nsy = sy, nsz = sz;
+        int kind = 0;   // 0: none, 1: plane (new dy), 2: layer (new dz), 3: full reload
+        int ndy = 0, ndz = 0;
+        if (ri + 1 < g.n_rows) {
+            nsy = rows[ri + 1].x;
+            nsz = rows[ri + 1].y;
+            const int ddy = nsy - sy, ddz = nsz - sz;
+            if (ddz == 0 && (ddy == 1 || ddy == -1)) {
+                kind = 1;
+                ndy = (ddy == 1) ? ty0 - nsy : ty0 - nsy + TY - 1;
+            } else if (ddy == 0 && (ddz == 1 || ddz == -1)) {
+                kind = 2;
+                ndz = (ddz == 1) ? tz0 - nsz : tz0 - nsz + TZ - 1;
+            } else {
+                kind = 3;
+            }
+        }
+        // prefetch the new plane / layer and the next F row into registers
+        cplx<R> pre[C::PER];
+        cplx<R> fpre = cmake<R>((R)0, (R)0);
+        if (kind == 1 || kind == 2) {
+            const int cnt = (kind == 1 ? TZ : TY) * KW;
+#pragma unroll
+            for (int p = 0; p < C::PER; ++p) {
+                const int e = l + p * NT;
+                if (e < cnt) {
+                    const int dxi = e % KW, q = e / KW;
+                    const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
+                    const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
+                    pre[p] = Kf[kidx(dy, dz, dxi)];
+                }
+            }
+            if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * BX + l];
+        }
+
+        // compute: U[i] += K[x0 + i - j] * F[j], with a sliding register
+        // window kw[i] = K[x0 + i - j] that gains one LDS value per step j
+        {
+            const cplx<R> *krow = &kbuf[lds(ty - sy, tz - sz, 0)] + x0 + BX - 1;
+            const cplx<R> *fr = frow[buf];
+            cplx<R> kw[A];
+#pragma unroll
+            for (int i = 0; i < A; ++i) kw[i] = krow[i];
+#pragma unroll
+            for (int j = 0; j < BX; ++j) {
+                const cplx<R> fj = fr[j];
+#pragma unroll
+                for (int i = 0; i < A; ++i) acc[i] = cmac(acc[i], kw[i], fj);
+                if (j + 1 < BX) {
+#pragma unroll
+                    for (int i = A - 1; i >= 1; --i) kw[i] = kw[i - 1];
+                    kw[0] = krow[-(j + 1)];
+                }
+            }
+        }
+
+        if (kind == 1 || kind == 2) {
+            const int cnt = (kind == 1 ? TZ : TY) * KW;
+#pragma unroll
+            for (int p = 0; p < C::PER; ++p) {
+                const int e = l + p * NT;
+                if (e < cnt) {
+                    const int dxi = e % KW, q = e / KW;
+                    const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
+                    const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
+                    kbuf[lds(dy, dz, dxi)] = pre[p];
+                }
+            }
+            if (l < BX) frow[buf ^ 1][l] = fpre;
+            __syncthreads();
+        } else if (kind == 3) {
+            __syncthreads();
+            const int dy0 = ty0 - nsy, dz0 = tz0 - nsz;
+            for (int e = l; e < TY * TZ * KW; e += NT) {
+                const int dxi = e % KW, q = e / KW;
+                const int dy = dy0 + q % TY, dz = dz0 + q / TY;
+                kbuf[lds(dy, dz, dxi)] = Kf[kidx(dy, dz, dxi)];
+            }
+            for (int e = l; e < BX; e += NT) frow[buf ^ 1][e] = Ff[((size_t)nsz * g.ey + nsy) * BX + e];
+            __syncthreads();
+        }
+        sy = nsy;
+        sz = nsz;
+    }
+
+    if (ty < g.ey && tz < g.ez) {
+        cplx<R> *Uf = Uhat + (size_t)freq * g.n_slots + ((size_t)tz * g.ey + ty) * BX + x0;
+#pragma unroll
+        for (int i = 0; i < A; ++i) Uf[i] = acc[i];
+    }
+}
+
+template <int BX, int A, int TY, int TZ, typename R>
+hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const int2 *rows,
+                      const int2 *tiles, hipStream_t s) {
+    using C = SmacCfg<BX, A, TY, TZ>;
+    if (g.n_rows <= 0 || g.n_tiles <= 0) return hipSuccess;
+    const int64_t nwg = (int64_t)g.n_freq * g.n_tiles;
+    hipLaunchKernelGGL((smac_kernel<BX, A, TY, TZ, R>), dim3((unsigned)nwg), dim3(C::NT), 0, s, g,
+                       (const cplx<R> *)F, (cplx<R> *)U, (const cplx<R> *)K, rows, tiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
+int smac_tile_z(int bx) { return bx == 8 ? 8 : (bx == 16 ? 16 : 8); }
+
+hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
+                       const int2 *rows, const int2 *tiles, hipStream_t s) {
+    switch (g.bx) {
+    case 8:
+        return fp32 ? launch_cfg<8, 8, 8, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
+                    : launch_cfg<8, 8, 8, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
+    case 16:
+        return fp32 ? launch_cfg<16, 8, 16, 16, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
+                    : launch_cfg<16, 8, 16, 16, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
+    case 32:
+        return fp32 ? launch_cfg<32, 16, 16, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
+                    : launch_cfg<32, 16, 16, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lgf

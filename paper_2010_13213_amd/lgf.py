@@ -1,0 +1,269 @@
+"""Thin ctypes binding of liblgf.so (C ABI in include/lgf.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.  If the
+library has not been built the first call raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblgf.so")
+
+LGF_OK, LGF_E_INVALID, LGF_E_NOMEM, LGF_E_DEVICE, LGF_E_UNSUPPORTED = range(5)
+LGF_FP64, LGF_FP32_REFINE = 0, 1
+_PREC = {"fp64": LGF_FP64, "fp32_refine": LGF_FP32_REFINE}
+
+EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "lgf_plan_create",
+            "lgf_problem_check",
+            "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
+            "lgf_solve", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
+            "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
+            "lgf_last_error", "lgf_status_string"]
+
+
+class LgfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("block_ijk", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("nb", ctypes.c_int32), ("dx0", ctypes.c_double),
+                ("n_components", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ne_blocks", ctypes.c_int32), ("levels", ctypes.POINTER(_Level))]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("device_ms", ctypes.c_double), ("refine_rel_l2", ctypes.c_double),
+                ("passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblgf.so; raise if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblgf.so is not built (python -m paper_2010_13213_amd.build); "
+                           "the LGF path has no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    L.lgf_context_create.argtypes = [ctypes.c_int, sz, ctypes.POINTER(vp)]
+    L.lgf_context_create.restype = ctypes.c_int
+    L.lgf_context_destroy.argtypes = [vp]
+    L.lgf_context_destroy.restype = None
+    L.lgf_context_bytes.argtypes = [vp]
+    L.lgf_context_bytes.restype = sz
+    L.lgf_plan_create.argtypes = [vp, ctypes.POINTER(_Problem), ctypes.POINTER(vp)]
+    L.lgf_plan_create.restype = ctypes.c_int
+    L.lgf_problem_check.argtypes = [ctypes.POINTER(_Problem)]
+    L.lgf_problem_check.restype = ctypes.c_int
+    L.lgf_plan_destroy.argtypes = [vp]
+    L.lgf_plan_destroy.restype = None
+    L.lgf_plan_workspace_bytes.argtypes = [vp]
+    L.lgf_plan_workspace_bytes.restype = sz
+    L.lgf_plan_cells.argtypes = [vp, ctypes.c_int]
+    L.lgf_plan_cells.restype = sz
+    L.lgf_plan_field_len.argtypes = [vp]
+    L.lgf_plan_field_len.restype = sz
+    L.lgf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Report)]
+    L.lgf_solve.restype = ctypes.c_int
+    L.lgf_solve_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), vp, ctypes.POINTER(Report)]
+    L.lgf_solve_batch.restype = ctypes.c_int
+    L.lgf_table_values.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_double)]
+    L.lgf_table_values.restype = ctypes.c_int
+    L.lgf_table_radius.argtypes = []
+    L.lgf_table_radius.restype = ctypes.c_int
+    L.lgf_block_spectrum.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double)]
+    L.lgf_block_spectrum.restype = ctypes.c_int
+    L.lgf_context_set_timing.argtypes = [vp, ctypes.c_int]
+    L.lgf_context_set_timing.restype = ctypes.c_int
+    L.lgf_context_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]
+    L.lgf_context_stage_times.restype = ctypes.c_int
+    L.lgf_last_error.argtypes = []
+    L.lgf_last_error.restype = ctypes.c_char_p
+    L.lgf_status_string.argtypes = [ctypes.c_int]
+    L.lgf_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _status_name(s):
+    try:
+        return lib().lgf_status_string(s).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def _check(status):
+    if status != LGF_OK:
+        raise LgfError(status, lib().lgf_last_error().decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Context:
+    """Device-resident LGF table and spectra cache on one GPU."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        h = ctypes.c_void_p()
+        _check(lib().lgf_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def bytes(self):
+        return int(lib().lgf_context_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lgf_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = ("fwd_fft", "smac", "inv_fft", "other")
+
+    def set_timing(self, enable=True):
+        _check(lib().lgf_context_set_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the last call; waits for the events."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(lib().lgf_context_stage_times(self._h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.STAGES)}
+
+    def table_values(self, ijk):
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+        out = np.empty(len(ijk))
+        _check(lib().lgf_table_values(self._h, len(ijk),
+                                      ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def block_spectrum(self, nb, d):
+        d = np.ascontiguousarray(d, dtype=np.int32).reshape(3)
+        N = 2 * nb
+        out = np.empty(2 * N * N * (nb + 1))
+        _check(lib().lgf_block_spectrum(self._h, int(nb),
+                                        d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return (out[0::2] + 1j * out[1::2]).reshape(N, N, nb + 1)
+
+
+def table_radius():
+    return int(lib().lgf_table_radius())
+
+
+def _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks):
+    blocks = [np.ascontiguousarray(b, dtype=np.int32).reshape(-1, 3) for b in level_blocks]
+    levels = (_Level * max(1, len(blocks)))()
+    for i, b in enumerate(blocks):
+        levels[i].n_blocks = len(b)
+        levels[i].block_ijk = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    prob = _Problem(len(blocks), int(nb), float(dx0), int(n_components),
+                    _PREC[precision] if isinstance(precision, str) else int(precision),
+                    int(ne_blocks), levels)
+    return prob, (blocks, levels)
+
+
+def problem_check(level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0):
+    """Host-only validation of a problem; returns (status, message)."""
+    prob, keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks)
+    st = lib().lgf_problem_check(ctypes.byref(prob))
+    return st, (lib().lgf_last_error().decode() if st != LGF_OK else "")
+
+
+class Plan:
+    """An immutable solve plan for one block support (all levels)."""
+
+    def __init__(self, ctx, level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0):
+        self.ctx = ctx
+        self.nb = int(nb)
+        self.n_components = int(n_components)
+        self.precision = precision
+        prob, self._keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks)
+        h = ctypes.c_void_p()
+        _check(lib().lgf_plan_create(ctx.handle, ctypes.byref(prob), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def for_problem(cls, ctx, problem, precision="fp64", ne_blocks=0):
+        return cls(ctx, [lv.blocks for lv in problem.levels], problem.nb, problem.dx0,
+                   problem.n_components, precision, ne_blocks)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def field_len(self):
+        return int(lib().lgf_plan_field_len(self._h))
+
+    def cells(self, level=0):
+        return int(lib().lgf_plan_cells(self._h, int(level)))
+
+    def workspace_bytes(self):
+        return int(lib().lgf_plan_workspace_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lgf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, f, u=None, stream=None, report=False):
+        """u = LGF solve of f (CUDA float64 tensors of field_len() elements)."""
+        import torch
+        n = self.field_len()
+        if f.dtype != torch.float64 or not f.is_cuda or f.numel() != n or not f.is_contiguous():
+            raise ValueError("f must be a contiguous CUDA float64 tensor of %d elements" % n)
+        if u is None:
+            u = torch.empty_like(f)
+        rep = Report() if report else None
+        _check(lib().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                               _stream_handle(stream), ctypes.byref(rep) if rep is not None else None))
+        return (u, rep) if report else u
+
+
+def solve_batch(ctx, plans, fs, us, stream=None, report=False):
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    U = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    reps = (Report * n)() if report else None
+    _check(lib().lgf_solve_batch(ctx.handle, n, P, F, U, _stream_handle(stream), reps))
+    return list(reps) if report else None

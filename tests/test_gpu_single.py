@@ -1,0 +1,180 @@
+"""GPU parity of the single-level LGF path against the CPU FP64 oracle.
+
+All calls go through the C ABI (liblgf.so).  Tolerance: relative L2 <= 1e-12
+on the float64 path (paper method reproduced exactly up to rounding: the
+blockwise FFT convolution is an exact linear convolution).
+"""
+import numpy as np
+import pytest
+
+from oracle import direct, lgf_table as T
+from paper_2010_13213_amd import inputs
+from helpers import gpu_solve, level_cells, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _problem(blocks, nb, values, dx=1.0, name="custom"):
+    blocks = np.asarray(blocks, dtype=np.int32).reshape(-1, 3)
+    v = np.asarray(values, dtype=np.float64).reshape(-1, len(blocks), nb, nb, nb)
+    return inputs.Problem(nb=nb, dx0=dx, levels=[inputs.Level(blocks=blocks, values=v)], name=name)
+
+
+def _cube(n, lo=(0, 0, 0)):
+    return np.array([(lo[0] + x, lo[1] + y, lo[2] + z) for z in range(n) for y in range(n)
+                     for x in range(n)])
+
+
+def test_device_table_matches_oracle(gpu_ctx):
+    rng = np.random.default_rng(11)
+    pts = np.concatenate([
+        np.array([[0, 0, 0], [1, 0, 0], [128, 5, 3], [129, 0, 0], [128, 128, 128], [-7, 3, -2],
+                  [300, 20, -40]]),
+        rng.integers(-140, 141, size=(400, 3)),
+        rng.integers(-30, 31, size=(200, 3))])
+    dev = gpu_ctx.table_values(pts)
+    ref = T.G(pts)
+    assert np.max(np.abs(dev - ref) / np.abs(ref)) < 5e-14
+    assert abs(dev[0] - T.watson_G0()) < 1e-14
+
+
+@pytest.mark.parametrize("nb,d", [(8, (0, 0, 0)), (8, (1, -2, 3)), (16, (2, 0, -1))])
+def test_block_spectrum_matches_library_fft(gpu_ctx, nb, d):
+    N = 2 * nb
+    idx = np.arange(N)
+    m = np.where(idx < nb, idx, idx - N)
+    Z, Y, X = np.meshgrid(m, m, m, indexing="ij")
+    n = np.stack([d[0] * nb + X, d[1] * nb + Y, d[2] * nb + Z], axis=-1)
+    w = T.G(n)
+    w[nb, :, :] = 0.0
+    w[:, nb, :] = 0.0
+    w[:, :, nb] = 0.0
+    ref = np.fft.rfftn(w)                       # axes (z, y, x) -> [kz][ky][kx]
+    got = gpu_ctx.block_spectrum(nb, d)
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+def test_gaussian_box_32_full_parity(gpu_ctx):
+    p = inputs.gaussian_box()                   # 4^3 blocks of 8^3, exp(-r^2/(2*4^2)) + noise
+    u = gpu_solve(gpu_ctx, p)[0]
+    c = level_cells(p)
+    ref = direct.direct_sum(c, p.flat_source(), c, p.dx0)
+    assert rel_l2(u, ref) < TOL64
+
+
+def test_point_source_reproduces_green_function(gpu_ctx):
+    nb, dx = 8, 0.25
+    blocks = _cube(3, lo=(-1, 0, 2))
+    c = inputs.cell_coords(blocks, nb)
+    f = np.zeros(len(c))
+    j = 1234
+    f[j] = 1.0
+    u = gpu_solve(gpu_ctx, _problem(blocks, nb, f, dx))[0]
+    ref = dx * dx * T.G(c - c[j])
+    assert np.max(np.abs(u - ref)) < 1e-13 * np.max(np.abs(ref))
+    assert rel_l2(u, ref) < TOL64
+
+
+def test_compact_potential_recovered_from_its_laplacian(gpu_ctx):
+    """omega = L_h Psi with compact Psi: the solve must return Psi itself."""
+    nb, dx = 8, 0.1
+    blocks = _cube(4)
+    c = inputs.cell_coords(blocks, nb).astype(np.float64)
+    ctr, R = np.array([15.7, 16.2, 15.9]), 13.0
+
+    def psi(p):
+        t2 = ((p - ctr) ** 2).sum(axis=-1) / R ** 2
+        out = np.zeros(t2.shape)
+        mk = t2 < 1
+        out[mk] = 1e3 * np.exp(-10.0 / (1.0 - t2[mk]))
+        return out
+    lap = -6.0 * psi(c)
+    for e in np.eye(3):
+        lap += psi(c + e) + psi(c - e)
+    omega = lap / dx ** 2
+    u = gpu_solve(gpu_ctx, _problem(blocks, nb, omega, dx))[0]
+    assert np.max(np.abs(u - psi(c))) < 1e-12 * np.max(np.abs(psi(c)))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ragged_sparse_support_full_parity(gpu_ctx, seed):
+    rng = np.random.default_rng(seed)
+    nb = 8
+    box = np.array([(x, y, z) for z in range(7) for y in range(5) for x in range(6)])
+    keep = rng.uniform(size=len(box)) < 0.4
+    blocks = box[keep] - np.array([3, -2, 5])
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    u = gpu_solve(gpu_ctx, _problem(blocks, nb, f, 0.7))[0]
+    ref = direct.direct_sum(c, f, c, 0.7)
+    assert rel_l2(u, ref) < TOL64
+
+
+def test_long_rows_use_the_wide_template(gpu_ctx):
+    nb = 8
+    blocks = np.array([(x, y, z) for z in range(2) for y in range(2) for x in range(20)])
+    rng = np.random.default_rng(3)
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    u = gpu_solve(gpu_ctx, _problem(blocks, nb, f))[0]
+    ref = direct.direct_sum(c, f, c, 1.0)
+    assert rel_l2(u, ref) < TOL64
+
+
+def test_single_block_and_repeat_is_bitwise_stable(gpu_ctx):
+    import torch
+    from paper_2010_13213_amd import lgf
+    nb = 16
+    blocks = np.array([[5, -3, 2]])
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal(nb ** 3)
+    p = _problem(blocks, nb, f)
+    plan = lgf.Plan.for_problem(gpu_ctx, p)
+    ft = torch.from_numpy(p.flat_source()).cuda()
+    u1 = plan.solve(ft).cpu().numpy()
+    u2 = plan.solve(ft).cpu().numpy()
+    assert np.array_equal(u1, u2)
+    c = level_cells(p)
+    assert rel_l2(u1, direct.direct_sum(c, f, c, 1.0)) < TOL64
+
+
+def test_translation_by_whole_blocks_is_exact(gpu_ctx):
+    nb = 8
+    rng = np.random.default_rng(5)
+    blocks = _cube(3)
+    f = rng.standard_normal(27 * nb ** 3)
+    a = gpu_solve(gpu_ctx, _problem(blocks, nb, f))[0]
+    b = gpu_solve(gpu_ctx, _problem(blocks + np.array([-40, 17, 3]), nb, f))[0]
+    assert np.array_equal(a, b)
+
+
+def _sampled(p, comp_vals, n_samples, seed):
+    rng = np.random.default_rng(seed)
+    c = level_cells(p)
+    idx = rng.choice(len(c), n_samples, replace=False)
+    return c, idx
+
+
+def test_vortex_ring_vector_sampled_parity(gpu_ctx):
+    p = inputs.single_ring()                    # R/32, 16^3 blocks, 208 blocks, 3 components
+    assert len(p.levels[0].blocks) == 208
+    u = gpu_solve(gpu_ctx, p)
+    c, idx = _sampled(p, None, 1200, 7)
+    for comp in range(2):                       # omega_z = 0 exactly
+        f = p.levels[0].values[comp].reshape(-1)
+        nz = f != 0
+        ref = direct.direct_sum(c[nz], f[nz], c[idx], p.dx0)
+        assert rel_l2(u[comp][idx], ref) < TOL64
+    assert np.all(u[2] == 0.0)
+
+
+def test_dense_256_box_sampled_parity(gpu_ctx):
+    p = inputs.mstar()                          # 4096 blocks of 16^3, dx = R/64
+    u = gpu_solve(gpu_ctx, p)[0]
+    c, idx = _sampled(p, None, 300, 8)
+    f = p.levels[0].values[0].reshape(-1)
+    nz = f != 0
+    ref = direct.direct_sum(c[nz], f[nz], c[idx], p.dx0)
+    assert rel_l2(u[idx], ref) < TOL64
