@@ -45,4 +45,25 @@ int smac_tile_z(int bx);
 hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
                        const int2 *rows, const int2 *tiles, hipStream_t s);
 
+// ---- composite-grid kernels (lgf_composite.hip) ----
+// dst block b = src block b with the octants flagged in cover[b] zeroed.
+hipError_t mask_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,
+                       const unsigned char *cover, int n_blocks, hipStream_t s);
+// coarse octant (octant[i]) of the block at coarse_off[i] = mean of 8 children
+// of the fine block at fine_off[i].
+hipError_t coarsen_mean8(int nb, const double *fine, double *coarse, const int64_t *fine_off,
+                         const int64_t *coarse_off, const unsigned char *octant, int n_pairs, hipStream_t s);
+hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,
+                       int n_blocks, hipStream_t s);
+struct CorrGeom {
+    double dxc, dxf;        // cell widths of levels k-1 and k
+    int mlo[3], mdim[3];    // dense map of psi_{k-1} blocks: index or -1
+};
+// For each level-k block fblk[b] (x,y,z): P psi_{k-1}, and S + F_k, S + f^_k
+// (F_k, f^_k read at own_off[b] when >= 0, else 0) into block b of the
+// compact outputs.
+hipError_t correction_source(int nb, const CorrGeom &g, const double *psi, const int *cmap, const int *fblk,
+                             const int64_t *own_off, const double *Fk, const double *fhk, double *Ppsi,
+                             double *SrcF, double *Srcf, int n_blocks, hipStream_t s);
+
 }  // namespace lgf

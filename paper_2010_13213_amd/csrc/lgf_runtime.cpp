@@ -249,7 +249,7 @@ SmacGeom conv_geom(const Conv &c) {
 // Spectral workspace large enough for every convolution of the plan.
 void plan_alloc_spectral(lgf_plan *plan) {
     size_t need = 0;
-    for (auto &c : plan->convs) {
+    for (const Conv *c : plan->convs_view) {
         const size_t elem = c->fp32 ? 8 : 16;
         need = std::max(need, elem * (size_t)c->spec->n_freq * (size_t)c->n_slots);
     }

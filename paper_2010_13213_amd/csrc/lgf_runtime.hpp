@@ -88,6 +88,22 @@ struct Conv {
     DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off, d_rows, d_tiles;
 };
 
+// Per-level schedule data of a composite plan.
+struct LevelSched {
+    int n_own = 0;
+    bool any_cover = false;
+    DeviceBuffer d_cover, d_own_off;                 // level blocks: octant cover bits, field offsets
+    int n_cf = 0;
+    DeviceBuffer d_cf_fine, d_cf_coarse, d_cf_oct;   // coarsening pairs from level k+1
+    int n_ext = 0;
+    DeviceBuffer d_fblk, d_ext_own;                  // R_k blocks and their own-level offsets (or -1)
+    int n_dom = 0;                                   // dom(psi_k) blocks
+    CorrGeom corr{};                                 // map of dom(psi_{k-1}) for this level's correction
+    DeviceBuffer d_cmap;
+    DeviceBuffer d_cu_src, d_cu_dst, d_cp_src, d_cp_dst;
+    std::unique_ptr<Conv> convF, convPsi;
+};
+
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
 SmacGeom conv_geom(const Conv &c);
 
@@ -104,7 +120,10 @@ struct lgf_plan {
     std::vector<std::vector<lgf::Blk>> levels;     // per level, offsets within one component
     std::vector<int64_t> level_base;               // element offset of each level in a component
     int64_t comp_len = 0;                          // elements per component
-    std::vector<std::unique_ptr<lgf::Conv>> convs;
+    std::vector<std::unique_ptr<lgf::Conv>> convs;          // single-level plans
+    std::vector<std::unique_ptr<lgf::LevelSched>> lv;       // composite plans
+    std::vector<const lgf::Conv *> convs_view;              // every convolution of the plan
+    lgf::DeviceBuffer ws_fhat, ws_F, ws_psi[2], ws_ppsi, ws_srcF, ws_srcf;
     lgf::DeviceBuffer Fhat, Uhat;
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     size_t workspace_bytes() const;

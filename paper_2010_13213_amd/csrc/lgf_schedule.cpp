@@ -2,26 +2,290 @@
 //
 // One level (paper Sec. 2.2): u = dx0^2 * G * f on the level's blocks, one
 // blockwise convolution per component.
+//
+// K levels (paper Sec. 3.4, revised FLGF-AMR, in the paper's order):
+//   f^_k  = f_k restricted to Omega_k (octants covered by level k+1 zeroed)
+//   F_k   = f^_k + P_{k+1->k} F_{k+1}                 (fine -> coarse, mean of 8)
+//   psi_0 = L_0^-1 f^_0 on dom(psi_0),  phi_0 = L_0^-1 F_0 on Omega_0
+//   k >= 1, on R_k = Omega_k u Omega_k^E (level-k blocks dilated by ne blocks):
+//     P psi_{k-1}, S_k = (P L_{k-1} - L_k P) psi_{k-1}
+//     phi_k = P psi_{k-1} + L_k^-1 (S_k + F_k)        on Omega_k
+//     psi_k = P psi_{k-1} + L_k^-1 (S_k + f^_k)       on dom(psi_k), k < K-1
+// dom(psi_{k-1}) = level-(k-1) blocks holding any coarse cell within two
+// cells of a parent of R_k (trilinear P and L_{k-1} each reach one cell).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lgf_runtime.hpp"
 
 namespace lgf {
 
+namespace {
+
+using Key = std::tuple<int, int, int>;
+
+int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+template <typename T> void upload(lgf_context *ctx, DeviceBuffer &d, const std::vector<T> &h, const char *what) {
+    d.alloc(ctx, sizeof(T) * std::max<size_t>(1, h.size()), what);
+    if (!h.empty()) hip_check(hipMemcpy(d.ptr, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice), "upload");
+}
+
+std::vector<Key> dilate(const std::vector<Key> &in, int layers) {
+    std::map<Key, int> seen;
+    std::vector<Key> out;
+    auto add = [&](Key k) {
+        if (seen.emplace(k, 0).second) out.push_back(k);
+    };
+    for (const Key &k : in) add(k);
+    for (const Key &k : in)
+        for (int dz = -layers; dz <= layers; ++dz)
+            for (int dy = -layers; dy <= layers; ++dy)
+                for (int dx = -layers; dx <= layers; ++dx)
+                    add(Key(std::get<0>(k) + dx, std::get<1>(k) + dy, std::get<2>(k) + dz));
+    return out;
+}
+
+}  // namespace
+
 void build_schedule(lgf_plan *p) {
-    if (p->K != 1) throw Failure(LGF_E_UNSUPPORTED, "composite (K > 1) plans are not served by this build yet");
     if (p->prec != LGF_FP64) throw Failure(LGF_E_UNSUPPORTED, "LGF_FP32_REFINE is not served by this build yet");
-    auto c = std::make_unique<Conv>();
-    build_conv(p, *c, p->levels[0], p->levels[0], false);
-    p->convs.push_back(std::move(c));
+    lgf_context *ctx = p->ctx;
+    const int nb = p->nb, K = p->K;
+    const int64_t nb3 = (int64_t)nb * nb * nb;
+    if (K == 1) {
+        auto c = std::make_unique<Conv>();
+        build_conv(p, *c, p->levels[0], p->levels[0], false);
+        p->convs_view.push_back(c.get());
+        p->convs.push_back(std::move(c));
+        plan_alloc_spectral(p);
+        return;
+    }
+    for (int k = 0; k < K; ++k) p->lv.push_back(std::make_unique<LevelSched>());
+    std::vector<std::map<Key, int>> index(K);
+    for (int k = 0; k < K; ++k)
+        for (size_t i = 0; i < p->levels[k].size(); ++i) {
+            const auto &b = p->levels[k][i];
+            index[k][Key(b.ijk[0], b.ijk[1], b.ijk[2])] = (int)i;
+        }
+    // cover bits and coarsening pairs
+    for (int k = 0; k < K; ++k) {
+        LevelSched &L = *p->lv[k];
+        const auto &B = p->levels[k];
+        std::vector<unsigned char> cover(B.size(), 0);
+        std::vector<int64_t> own(B.size());
+        for (size_t i = 0; i < B.size(); ++i) own[i] = B[i].off;
+        std::vector<int64_t> cf_f, cf_c;
+        std::vector<unsigned char> cf_o;
+        if (k + 1 < K) {
+            for (const auto &fb : p->levels[k + 1]) {
+                const int px = fdiv(fb.ijk[0], 2), py = fdiv(fb.ijk[1], 2), pz = fdiv(fb.ijk[2], 2);
+                const int ci = index[k].at(Key(px, py, pz));
+                const int oct = (fb.ijk[0] - 2 * px) | ((fb.ijk[1] - 2 * py) << 1) | ((fb.ijk[2] - 2 * pz) << 2);
+                cover[ci] |= (unsigned char)(1u << oct);
+                cf_f.push_back(fb.off);
+                cf_c.push_back(B[ci].off);
+                cf_o.push_back((unsigned char)oct);
+            }
+        }
+        L.n_own = (int)B.size();
+        L.any_cover = std::any_of(cover.begin(), cover.end(), [](unsigned char c) { return c != 0; });
+        upload(ctx, L.d_cover, cover, "cover bits");
+        upload(ctx, L.d_own_off, own, "offsets");
+        L.n_cf = (int)cf_f.size();
+        upload(ctx, L.d_cf_fine, cf_f, "coarsen pairs");
+        upload(ctx, L.d_cf_coarse, cf_c, "coarsen pairs");
+        upload(ctx, L.d_cf_oct, cf_o, "coarsen pairs");
+    }
+    // extension R_k (k >= 1) and psi domains dom(psi_{k-1})
+    std::vector<std::vector<Key>> ext(K), dom(K);
+    for (int k = 1; k < K; ++k) {
+        std::vector<Key> own;
+        for (const auto &b : p->levels[k]) own.push_back(Key(b.ijk[0], b.ijk[1], b.ijk[2]));
+        ext[k] = dilate(own, p->ne);
+        std::map<Key, int> dseen;
+        const int H = nb / 2;
+        for (const Key &f : ext[k]) {
+            int lo[3], hi[3];
+            const int fc[3] = {std::get<0>(f), std::get<1>(f), std::get<2>(f)};
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fdiv(fc[a] * H - 2, nb);
+                hi[a] = fdiv(fc[a] * H + H + 1, nb);
+            }
+            for (int z = lo[2]; z <= hi[2]; ++z)
+                for (int y = lo[1]; y <= hi[1]; ++y)
+                    for (int x = lo[0]; x <= hi[0]; ++x)
+                        if (dseen.emplace(Key(x, y, z), 0).second) dom[k - 1].push_back(Key(x, y, z));
+        }
+    }
+    // field layout helpers
+    auto as_blk = [&](const std::vector<Key> &ks) {
+        std::vector<Blk> v(ks.size());
+        for (size_t i = 0; i < ks.size(); ++i) {
+            v[i].ijk[0] = std::get<0>(ks[i]);
+            v[i].ijk[1] = std::get<1>(ks[i]);
+            v[i].ijk[2] = std::get<2>(ks[i]);
+            v[i].off = (int64_t)i * nb3;           // compact workspace offset
+        }
+        return v;
+    };
+    int64_t max_ext = 0, max_dom = 0;
+    for (int k = 0; k < K; ++k) {
+        LevelSched &L = *p->lv[k];
+        // convolution of the phi right-hand side: sources -> Omega_k targets
+        std::vector<Blk> src = (k == 0) ? p->levels[0] : as_blk(ext[k]);
+        L.convF = std::make_unique<Conv>();
+        build_conv(p, *L.convF, src, p->levels[k], false);
+        if (k + 1 < K) {
+            std::vector<Blk> tgt = as_blk(dom[k]);
+            L.convPsi = std::make_unique<Conv>();
+            build_conv(p, *L.convPsi, src, tgt, false);
+            L.n_dom = (int)dom[k].size();
+            max_dom = std::max<int64_t>(max_dom, L.n_dom);
+            // dense map of dom(psi_k) for the level-(k+1) correction
+            int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+            for (const Key &d : dom[k]) {
+                const int c[3] = {std::get<0>(d), std::get<1>(d), std::get<2>(d)};
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], c[a]);
+                    hi[a] = std::max(hi[a], c[a]);
+                }
+            }
+            CorrGeom &g = p->lv[k + 1]->corr;
+            g.dxc = p->dx0 / (double)(1 << k);
+            g.dxf = p->dx0 / (double)(1 << (k + 1));
+            for (int a = 0; a < 3; ++a) {
+                g.mlo[a] = lo[a];
+                g.mdim[a] = hi[a] - lo[a] + 1;
+            }
+            std::vector<int> map((size_t)g.mdim[0] * g.mdim[1] * g.mdim[2], -1);
+            for (size_t i = 0; i < dom[k].size(); ++i) {
+                const Key &d = dom[k][i];
+                map[((size_t)(std::get<2>(d) - lo[2]) * g.mdim[1] + (std::get<1>(d) - lo[1])) * g.mdim[0] +
+                    (std::get<0>(d) - lo[0])] = (int)i;
+            }
+            upload(ctx, p->lv[k + 1]->d_cmap, map, "psi block map");
+        }
+        if (k >= 1) {
+            L.n_ext = (int)ext[k].size();
+            max_ext = std::max<int64_t>(max_ext, L.n_ext);
+            std::vector<int> fblk;
+            std::vector<int64_t> own_off;
+            std::map<Key, int> eidx;
+            for (size_t e = 0; e < ext[k].size(); ++e) {
+                const Key &q = ext[k][e];
+                fblk.push_back(std::get<0>(q));
+                fblk.push_back(std::get<1>(q));
+                fblk.push_back(std::get<2>(q));
+                auto it = index[k].find(q);
+                own_off.push_back(it == index[k].end() ? -1 : p->levels[k][it->second].off);
+                eidx[q] = (int)e;
+            }
+            upload(ctx, L.d_fblk, fblk, "extension blocks");
+            upload(ctx, L.d_ext_own, own_off, "extension offsets");
+            // P psi_{k-1} copies: R_k -> Omega_k targets (in u) and R_k -> dom(psi_k)
+            std::vector<int64_t> cu_s, cu_d, cp_s, cp_d;
+            for (const auto &b : p->levels[k]) {
+                cu_s.push_back((int64_t)eidx.at(Key(b.ijk[0], b.ijk[1], b.ijk[2])) * nb3);
+                cu_d.push_back(b.off);
+            }
+            if (k + 1 < K)
+                for (size_t i = 0; i < dom[k].size(); ++i) {
+                    auto it = eidx.find(dom[k][i]);
+                    if (it == eidx.end())
+                        throw Failure(LGF_E_UNSUPPORTED, "psi domain leaves the extended region (nb < 4?)");
+                    cp_s.push_back((int64_t)it->second * nb3);
+                    cp_d.push_back((int64_t)i * nb3);
+                }
+            upload(ctx, L.d_cu_src, cu_s, "copy offsets");
+            upload(ctx, L.d_cu_dst, cu_d, "copy offsets");
+            upload(ctx, L.d_cp_src, cp_s, "copy offsets");
+            upload(ctx, L.d_cp_dst, cp_d, "copy offsets");
+        }
+    }
+    // workspaces (one component at a time)
+    p->ws_fhat.alloc(ctx, sizeof(double) * p->comp_len, "masked sources");
+    p->ws_F.alloc(ctx, sizeof(double) * p->comp_len, "cumulative sources");
+    p->ws_psi[0].alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_dom) * nb3, "psi");
+    p->ws_psi[1].alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_dom) * nb3, "psi");
+    p->ws_ppsi.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "P psi");
+    p->ws_srcF.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
+    p->ws_srcf.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
+    for (int k = 0; k < K; ++k) {
+        p->convs_view.push_back(p->lv[k]->convF.get());
+        if (p->lv[k]->convPsi) p->convs_view.push_back(p->lv[k]->convPsi.get());
+    }
     plan_alloc_spectral(p);
 }
 
+static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream_t s) {
+    const int K = p->K, nb = p->nb;
+    double *FH = (double *)p->ws_fhat.ptr, *FC = (double *)p->ws_F.ptr;
+    for (int comp = 0; comp < p->nc; ++comp) {
+        const double *fc = f + (size_t)comp * p->comp_len;
+        double *uc = u + (size_t)comp * p->comp_len;
+        StageTimer tm(p->ctx, 3, s);
+        // f^_k and F_k
+        for (int k = 0; k < K; ++k) {
+            const LevelSched &L = *p->lv[k];
+            hip_check(mask_blocks(nb, fc, FH, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
+                                  (const unsigned char *)L.d_cover.ptr, L.n_own, s),
+                      "mask sources");
+            hip_check(copy_blocks(nb, FH, FC, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
+                                  L.n_own, s),
+                      "copy sources");
+        }
+        for (int k = K - 2; k >= 0; --k) {
+            const LevelSched &L = *p->lv[k];
+            hip_check(coarsen_mean8(nb, FC, FC, (const int64_t *)L.d_cf_fine.ptr, (const int64_t *)L.d_cf_coarse.ptr,
+                                    (const unsigned char *)L.d_cf_oct.ptr, L.n_cf, s),
+                      "coarsen");
+        }
+        int cur = 0;   // psi ping-pong
+        for (int k = 0; k < K; ++k) {
+            const LevelSched &L = *p->lv[k];
+            const double dxk = p->dx0 / (double)(1 << k);
+            double *psi_prev = (double *)p->ws_psi[cur].ptr;
+            double *psi_next = (double *)p->ws_psi[cur ^ 1].ptr;
+            if (k == 0) {
+                run_conv(p, *L.convF, FC, uc, dxk, 0, s);
+                if (L.convPsi) run_conv(p, *L.convPsi, FH, psi_next, dxk, 0, s);
+            } else {
+                hip_check(correction_source(nb, L.corr, psi_prev, (const int *)L.d_cmap.ptr, (const int *)L.d_fblk.ptr,
+                                            (const int64_t *)L.d_ext_own.ptr, FC, FH, (double *)p->ws_ppsi.ptr,
+                                            (double *)p->ws_srcF.ptr, (double *)p->ws_srcf.ptr, L.n_ext, s),
+                          "correction source");
+                hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, uc, (const int64_t *)L.d_cu_src.ptr,
+                                      (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
+                          "P psi -> phi");
+                run_conv(p, *L.convF, (const double *)p->ws_srcF.ptr, uc, dxk, 1, s);
+                if (L.convPsi) {
+                    hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, psi_next,
+                                          (const int64_t *)L.d_cp_src.ptr, (const int64_t *)L.d_cp_dst.ptr, L.n_dom,
+                                          s),
+                              "P psi -> psi");
+                    run_conv(p, *L.convPsi, (const double *)p->ws_srcf.ptr, psi_next, dxk, 1, s);
+                }
+            }
+            if (L.any_cover)
+                hip_check(mask_blocks(nb, uc, uc, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
+                                      (const unsigned char *)L.d_cover.ptr, L.n_own, s),
+                          "restrict phi");
+            cur ^= 1;
+        }
+    }
+}
+
 static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
+    if (p->K > 1) {
+        enqueue_composite(p, f, u, s);
+        return;
+    }
     const Conv &c = *p->convs[0];
     for (int comp = 0; comp < p->nc; ++comp)
         run_conv(p, c, f + (size_t)comp * p->comp_len, u + (size_t)comp * p->comp_len, p->dx0, 0, s);
@@ -42,9 +306,9 @@ void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report
         hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         rep->device_ms = ms;
         rep->refine_rel_l2 = 0.0;
-        rep->passes = 1;
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        rep->passes = (int)(p->K == 1 ? 1 : p->convs_view.size());
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
     }
 }
 
