@@ -80,41 +80,58 @@ def main():
     nb = prob.nb
     n_blocks = len(prob.levels[0].blocks)
     cells = n_blocks * nb ** 3 * prob.n_components
-    t_plan = time.perf_counter()
-    plan = lgf.Plan.for_problem(ctx, prob, "fp64")
-    t_plan = time.perf_counter() - t_plan
     f = torch.from_numpy(prob.flat_source()).cuda()
-    u = torch.empty_like(f)
 
-    for _ in range(args.warmup):
-        plan.solve(f, u)
-    torch.cuda.synchronize()
+    def timed(precision):
+        t_plan = time.perf_counter()
+        plan = lgf.Plan.for_problem(ctx, prob, precision)
+        t_plan = time.perf_counter() - t_plan
+        u = torch.empty_like(f)
+        for _ in range(args.warmup):
+            plan.solve(f, u)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ctx.stage_times()
+        stream = torch.cuda.current_stream()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            plan.solve(f, u)
+            b.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = ctx.stage_times()
+        ctx.set_timing(False)
+        lat = [a.elapsed_time(b) for a, b in evs]
+        host = u.cpu().numpy()
+        plan.close()
+        return {"wall": t1 - t0, "lat": lat, "stages": st, "plan_s": t_plan, "u": host}
 
-    ctx.set_timing(True)
-    ctx.stage_times()
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
-        plan.solve(f, u)
-        b.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = ctx.stage_times()
-    ctx.set_timing(False)
-    lat = [a.elapsed_time(b) for a, b in evs]
+    r64 = timed("fp64")
+    r32 = timed("fp32_refine")
 
-    wall = t1 - t0
+    # error of each result against the oracle on a sample of targets
+    c = inputs.cell_coords(prob.levels[0].blocks, nb)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(len(c), 48, replace=False)
+    from oracle import direct
+    direct.build(force=False)
+    ref = direct.direct_sum(c, prob.levels[0].values[0].reshape(-1), c[idx], prob.dx0)
+
+    def err(u):
+        return float(np.linalg.norm(u[idx] - ref) / np.linalg.norm(ref))
+
+    wall = r64["wall"]
     ms_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall
 
     n_freq = (2 * nb) ** 2 * (nb + 1)
     pairs = n_blocks * n_blocks
     flops_mac = 8.0 * pairs * n_freq                       # one complex MAC = 8 flops
-    smac_ms, smac_n = st["smac"]
+    smac_ms, smac_n = r64["stages"]["smac"]
     smac_avg = smac_ms / max(1, smac_n)
     achieved = flops_mac / (smac_avg * 1e-3) / 1e12
 
@@ -132,10 +149,17 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "dense 256^3 box, 4096 blocks of 16^3, dx=R/64, ring x-vorticity, "
-                               "single level, scalar, FP64",
-                   "cells": cells, "block_pairs": pairs, "plan_s": round(t_plan, 3)},
-        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+                               "single level, scalar; value = FP64 path",
+                   "cells": cells, "block_pairs": pairs, "plan_s": round(r64["plan_s"], 3)},
+        "latency_ms": {"p50": _pct(r64["lat"], 50), "p99": _pct(r64["lat"], 99)},
+        "err_vs_oracle": {"fp64": err(r64["u"]), "fp32_refine": err(r32["u"]),
+                          "sample": "48 random target cells, relative L2"},
+        "fp32_refine": {"value": cells * args.steps / r32["wall"], "unit": "cells/s",
+                        "ms_per_step": 1e3 * r32["wall"] / args.steps,
+                        "latency_ms": {"p50": _pct(r32["lat"], 50), "p99": _pct(r32["lat"], 99)},
+                        "stages_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
+                        "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in r64["stages"].items()},
         "roofline": {"bound": "alu", "kernel": "smac_kernel<16,8,16,16,double>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
@@ -144,7 +168,6 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
-    plan.close()
     ctx.close()
 
 

@@ -74,7 +74,7 @@ typedef struct lgf_problem {
     int32_t n_levels;       /* K >= 1                                       */
     int32_t nb;             /* block edge in cells: 8 or 16                 */
     double dx0;             /* cell width of level 0 (> 0)                  */
-    int32_t n_components;   /* 1 (scalar) or 3 (vector Poisson)            */
+    int32_t n_components;   /* 1..8 fields on the same support (3: vector) */
     int32_t precision;      /* an lgf_precision value                       */
     int32_t ne_blocks;      /* extended-correction layers in blocks (>= 1;
                                0 selects the default 1, i.e. N_E = nb)       */

@@ -57,7 +57,7 @@ void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
     require(d->n_levels >= 1 && d->n_levels <= 8, "n_levels must be in [1, 8]");
     require(d->nb == 8 || d->nb == 16, "nb must be 8 or 16");
     require(d->dx0 > 0 && std::isfinite(d->dx0), "dx0 must be positive");
-    require(d->n_components == 1 || d->n_components == 3, "n_components must be 1 or 3");
+    require(d->n_components >= 1 && d->n_components <= 8, "n_components must be in [1, 8]");
     require(d->precision == LGF_FP64 || d->precision == LGF_FP32_REFINE, "unknown precision");
     require(d->ne_blocks >= 0 && d->ne_blocks <= 4, "ne_blocks must be in [0, 4]");
     require(d->levels != nullptr, "null levels");
@@ -103,7 +103,7 @@ void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
 
 size_t lgf_plan::workspace_bytes() const {
     size_t b = Fhat.bytes + Uhat.bytes + ws_fhat.bytes + ws_F.bytes + ws_psi[0].bytes + ws_psi[1].bytes +
-               ws_ppsi.bytes + ws_srcF.bytes + ws_srcf.bytes;
+               ws_ppsi.bytes + ws_srcF.bytes + ws_srcf.bytes + ws_ut.bytes + ws_ush.bytes + ws_rho.bytes;
     for (const Conv *c : convs_view)
         b += c->d_src_slot.bytes + c->d_tgt_slot.bytes + c->d_src_off.bytes + c->d_tgt_off.bytes +
              c->d_rows.bytes + c->d_tiles.bytes;
@@ -259,28 +259,33 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
     return guard([&] {
         require(ctx && d && out, "null arguments");
         require(nb == 8 || nb == 16, "nb must be 8 or 16");
-        const int XH = std::abs(d[0]), YH = std::abs(d[1]), ZH = std::abs(d[2]);
-        require(XH <= 64 && YH <= 64 && ZH <= 64, "offset too large");
+        const int ax = std::abs(d[0]), ay = std::abs(d[1]), az = std::abs(d[2]);
+        require(ax <= 64 && ay <= 64 && az <= 64, "offset too large");
         DeviceScope ds(ctx->device);
-        // build a private table for exactly this half-width box, copy one offset out
+        // octant table covering |d|, then the reflection rule of the MAC loader
         SpecTable t;
         const int N = 2 * nb, H = nb + 1;
         const size_t n_freq = (size_t)N * N * H;
-        const size_t n_off = (size_t)(2 * XH + 1) * (2 * YH + 1) * (2 * ZH + 1);
+        const size_t n_off = (size_t)(ax + 1) * (ay + 1) * (az + 1);
         t.data.alloc(ctx, 16 * n_off * n_freq, "spectrum");
         DeviceBuffer scratch;
         scratch.alloc(ctx, 16 * n_freq * std::min<size_t>(n_off, 512), "spectrum scratch");
-        hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, XH, YH, ZH, false, t.data.ptr, scratch.ptr,
+        hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, ax, ay, az, false, t.data.ptr, scratch.ptr,
                                 scratch.bytes, ctx->stream),
                   "build_spectra");
         hip_check(hipStreamSynchronize(ctx->stream), "sync");
-        const size_t o = ((size_t)(d[1] + YH) * (2 * ZH + 1) + (d[2] + ZH)) * (2 * XH + 1) + (d[0] + XH);
+        const size_t o = ((size_t)ay * (az + 1) + az) * (ax + 1) + ax;
         std::vector<double> all(2 * n_off * n_freq);
         hip_check(hipMemcpy(all.data(), t.data.ptr, all.size() * 8, hipMemcpyDeviceToHost), "download");
-        for (size_t w = 0; w < n_freq; ++w) {
-            out[2 * w] = all[2 * (w * n_off + o)];
-            out[2 * w + 1] = all[2 * (w * n_off + o) + 1];
-        }
+        const bool fx = d[0] < 0, fy = (d[1] < 0) != fx, fz = (d[2] < 0) != fx;
+        for (int kz = 0; kz < N; ++kz)
+            for (int ky = 0; ky < N; ++ky)
+                for (int kx = 0; kx < H; ++kx) {
+                    const int ky2 = fy ? (N - ky) % N : ky, kz2 = fz ? (N - kz) % N : kz;
+                    const size_t w = ((size_t)kz * N + ky) * H + kx, w2 = ((size_t)kz2 * N + ky2) * H + kx;
+                    out[2 * w] = all[2 * (w2 * n_off + o)];
+                    out[2 * w + 1] = fx ? -all[2 * (w2 * n_off + o) + 1] : all[2 * (w2 * n_off + o) + 1];
+                }
     });
 }
 

@@ -10,8 +10,9 @@ int lgf_table_nodes();
 // gcube: (R+1)^3 doubles; B: nodes*(R+1) doubles; w: nodes doubles.
 hipError_t build_lgf_table(double *gcube, double *B, double *w, hipStream_t s);
 hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int64_t n, hipStream_t s);
-// Spectra of every block offset in [-XH,XH] x [-YH,YH] x [-ZH,ZH] into
-// table[omega][dy+YH][dz+ZH][dx+XH] (complex float or double).
+// Spectra of every block offset in [0,XH] x [0,YH] x [0,ZH] into
+// table[omega][dy][dz][dx] (complex float or double); offsets with negative
+// components are served by reflection.
 hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bool fp32, void *table,
                          void *scratch, size_t scratch_bytes, hipStream_t s);
 
@@ -34,7 +35,8 @@ struct SmacGeom {
     int ey, ez;             // padded box extent in blocks along y, z (slots)
     int n_freq;
     int64_t n_slots;        // bx * ey * ez
-    int XH, YH, ZH, XD, YD, ZD;   // spectra table half-widths and dims
+    int XH, YH, ZH, XD, YD, ZD;   // octant spectra table extents (XD = XH + 1, ...)
+    int N;                        // FFT edge 2 nb (frequency index remap)
     int n_rows;             // source rows (sy, sz), serpentine order
     int n_tiles;            // target tiles (ty0, tz0)
 };
@@ -65,5 +67,22 @@ struct CorrGeom {
 hipError_t correction_source(int nb, const CorrGeom &g, const double *psi, const int *cmap, const int *fblk,
                              const int64_t *own_off, const double *Fk, const double *fhk, double *Ppsi,
                              double *SrcF, double *Srcf, int n_blocks, hipStream_t s);
+
+// ---- mixed-precision refinement (lgf_refine.hip) ----
+struct RefGeom {
+    double dx;
+    int lo[3], dim[3];      // dense block map of the target set T: T index or -1
+};
+// depth (L1 distance to the complement of T, capped at 4) of every cell of
+// the listed shell blocks
+hipError_t refine_depth(int nb, const RefGeom &g, const int *map, const int *shblk, unsigned char *depth, int n_sh,
+                        hipStream_t s);
+// rho = L_dx e^ on every T block (see lgf_refine.hip)
+hipError_t refine_residual(int nb, const RefGeom &g, const int *map, const int *tblk, const int *t2sh,
+                           const unsigned char *depth, const double *ut, const double *ush, const double *src,
+                           const int64_t *gofs, double *rho, int n_t, hipStream_t s);
+// dst (+)= exact values on shell blocks, float32 values on interior blocks
+hipError_t refine_assemble(int nb, const int *t2sh, const double *ut, const double *ush, const int64_t *dofs,
+                           double *dst, int accumulate, int n_t, hipStream_t s);
 
 }  // namespace lgf

@@ -126,7 +126,7 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     t->ZH = ZH;
     const int N = 2 * nb;
     t->n_freq = N * N * (nb + 1);
-    const size_t n_off = (size_t)(2 * XH + 1) * (2 * YH + 1) * (2 * ZH + 1);
+    const size_t n_off = (size_t)(XH + 1) * (YH + 1) * (ZH + 1);
     const size_t elem = fp32 ? 8 : 16;
     t->data.alloc(ctx, elem * n_off * t->n_freq, "LGF block spectra");
     DeviceBuffer scratch;
@@ -238,12 +238,149 @@ SmacGeom conv_geom(const Conv &c) {
     g.XH = c.spec->XH;
     g.YH = c.spec->YH;
     g.ZH = c.spec->ZH;
-    g.XD = 2 * g.XH + 1;
-    g.YD = 2 * g.YH + 1;
-    g.ZD = 2 * g.ZH + 1;
+    g.XD = g.XH + 1;
+    g.YD = g.YH + 1;
+    g.ZD = g.ZH + 1;
+    g.N = 2 * c.spec->nb;
     g.n_rows = c.n_rows;
     g.n_tiles = c.n_tiles;
     return g;
+}
+
+// ------------------------------------------------------------------ ops
+
+std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt,
+                                 bool refine) {
+    lgf_context *ctx = plan->ctx;
+    const int nb = plan->nb;
+    const int64_t nb3 = (int64_t)nb * nb * nb;
+    auto op = std::make_unique<ConvOp>();
+    using Key = std::tuple<int, int, int>;
+    std::map<Key, int> tix;
+    for (size_t i = 0; i < tgt.size(); ++i) tix[Key(tgt[i].ijk[0], tgt[i].ijk[1], tgt[i].ijk[2])] = (int)i;
+    std::vector<int> t2sh(tgt.size(), -1);
+    std::vector<Blk> sh, interior, tcomp(tgt.size());
+    int n_sh = 0;
+    for (size_t i = 0; i < tgt.size(); ++i) {
+        const auto &b = tgt[i];
+        bool shell = false;
+        for (int dz = -1; dz <= 1 && !shell; ++dz)
+            for (int dy = -1; dy <= 1 && !shell; ++dy)
+                for (int dx = -1; dx <= 1 && !shell; ++dx)
+                    if (!tix.count(Key(b.ijk[0] + dx, b.ijk[1] + dy, b.ijk[2] + dz))) shell = true;
+        tcomp[i] = b;
+        tcomp[i].off = (int64_t)i * nb3;
+        if (shell) {
+            Blk q = b;
+            q.off = (int64_t)n_sh * nb3;
+            sh.push_back(q);
+            t2sh[i] = n_sh++;
+        } else {
+            interior.push_back(b);
+        }
+    }
+    if (!refine || interior.empty()) {
+        op->c64 = std::make_unique<Conv>();
+        build_conv(plan, *op->c64, src, tgt, false);
+        plan->convs_view.push_back(op->c64.get());
+        return op;
+    }
+    op->refined = true;
+    op->n_t = (int)tgt.size();
+    op->n_sh = n_sh;
+    op->c32 = std::make_unique<Conv>();
+    build_conv(plan, *op->c32, src, tcomp, true);
+    op->c64 = std::make_unique<Conv>();
+    build_conv(plan, *op->c64, src, sh, false);
+    op->ccorr = std::make_unique<Conv>();
+    build_conv(plan, *op->ccorr, tcomp, interior, true);
+    for (const Conv *c : {op->c32.get(), op->c64.get(), op->ccorr.get()}) plan->convs_view.push_back(c);
+    // dense map of T over its bounding box
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (const auto &b : tgt)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], b.ijk[a]);
+            hi[a] = std::max(hi[a], b.ijk[a]);
+        }
+    RefGeom &g = op->geom;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = lo[a];
+        g.dim[a] = hi[a] - lo[a] + 1;
+    }
+    std::vector<int> map((size_t)g.dim[0] * g.dim[1] * g.dim[2], -1);
+    std::vector<int> tblk, shblk;
+    std::vector<int64_t> dofs;
+    for (size_t i = 0; i < tgt.size(); ++i) {
+        const auto &b = tgt[i];
+        map[((size_t)(b.ijk[2] - lo[2]) * g.dim[1] + (b.ijk[1] - lo[1])) * g.dim[0] + (b.ijk[0] - lo[0])] = (int)i;
+        for (int a = 0; a < 3; ++a) tblk.push_back(b.ijk[a]);
+        dofs.push_back(b.off);
+    }
+    for (const auto &b : sh)
+        for (int a = 0; a < 3; ++a) shblk.push_back(b.ijk[a]);
+    std::map<Key, int64_t> sof;
+    for (const auto &b : src) sof[Key(b.ijk[0], b.ijk[1], b.ijk[2])] = b.off;
+    std::vector<int64_t> gofs;
+    for (const auto &b : tgt) {
+        auto it = sof.find(Key(b.ijk[0], b.ijk[1], b.ijk[2]));
+        gofs.push_back(it == sof.end() ? -1 : it->second);
+    }
+    auto up = [&](DeviceBuffer &d, const void *h, size_t n, const char *what) {
+        d.alloc(ctx, std::max<size_t>(n, 8), what);
+        if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
+    };
+    up(op->d_map, map.data(), sizeof(int) * map.size(), "target map");
+    up(op->d_tblk, tblk.data(), sizeof(int) * tblk.size(), "target blocks");
+    up(op->d_t2sh, t2sh.data(), sizeof(int) * t2sh.size(), "shell index");
+    up(op->d_gofs, gofs.data(), sizeof(int64_t) * gofs.size(), "source offsets");
+    up(op->d_dofs, dofs.data(), sizeof(int64_t) * dofs.size(), "target offsets");
+    DeviceBuffer d_shblk;
+    up(d_shblk, shblk.data(), sizeof(int) * shblk.size(), "shell blocks");
+    op->d_depth.alloc(ctx, (size_t)std::max(1, n_sh) * nb3, "shell depth");
+    hip_check(refine_depth(nb, g, (const int *)op->d_map.ptr, (const int *)d_shblk.ptr,
+                           (unsigned char *)op->d_depth.ptr, n_sh, ctx->stream),
+              "shell depth");
+    hip_check(hipStreamSynchronize(ctx->stream), "depth sync");
+    return op;
+}
+
+void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
+            hipStream_t s) {
+    if (!op.refined) {
+        run_conv(plan, *op.c64, src, dst, dx, accumulate, s);
+        return;
+    }
+    const int nb = plan->nb;
+    double *ut = (double *)plan->ws_ut.ptr, *ush = (double *)plan->ws_ush.ptr, *rho = (double *)plan->ws_rho.ptr;
+    run_conv(plan, *op.c32, src, ut, dx, 0, s);
+    run_conv(plan, *op.c64, src, ush, dx, 0, s);
+    RefGeom g = op.geom;
+    g.dx = dx;
+    {
+        StageTimer t(plan->ctx, 3, s);
+        hip_check(refine_residual(nb, g, (const int *)op.d_map.ptr, (const int *)op.d_tblk.ptr,
+                                  (const int *)op.d_t2sh.ptr, (const unsigned char *)op.d_depth.ptr, ut, ush, src,
+                                  (const int64_t *)op.d_gofs.ptr, rho, op.n_t, s),
+                  "refinement residual");
+        hip_check(refine_assemble(nb, (const int *)op.d_t2sh.ptr, ut, ush, (const int64_t *)op.d_dofs.ptr, dst,
+                                  accumulate, op.n_t, s),
+                  "refinement assemble");
+    }
+    run_conv(plan, *op.ccorr, rho, dst, dx, 1, s);
+}
+
+void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {
+    int64_t nt = 0, nsh = 0;
+    for (const ConvOp *o : ops)
+        if (o && o->refined) {
+            nt = std::max<int64_t>(nt, o->n_t);
+            nsh = std::max<int64_t>(nsh, o->n_sh);
+        }
+    if (nt == 0) return;
+    const int64_t nb3 = (int64_t)plan->nb * plan->nb * plan->nb;
+    plan->ws_ut.alloc(plan->ctx, sizeof(double) * nt * nb3, "u float32 pass");
+    plan->ws_rho.alloc(plan->ctx, sizeof(double) * nt * nb3, "refinement residual");
+    plan->ws_ush.alloc(plan->ctx, sizeof(double) * std::max<int64_t>(1, nsh) * nb3, "shell values");
 }
 
 // Spectral workspace large enough for every convolution of the plan.

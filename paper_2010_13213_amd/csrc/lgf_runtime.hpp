@@ -88,6 +88,17 @@ struct Conv {
     DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off, d_rows, d_tiles;
 };
 
+// One L_dx^-1 application on a source and a target block set: a plain
+// float64 convolution, or the float32 + float64-refinement sequence.
+struct ConvOp {
+    bool refined = false;
+    std::unique_ptr<Conv> c64;                  // exact: all targets, or the shell blocks
+    std::unique_ptr<Conv> c32, ccorr;           // refined: u~ on T, correction onto the interior
+    int n_t = 0, n_sh = 0;
+    RefGeom geom{};
+    DeviceBuffer d_map, d_tblk, d_t2sh, d_depth, d_gofs, d_dofs;
+};
+
 // Per-level schedule data of a composite plan.
 struct LevelSched {
     int n_own = 0;
@@ -101,7 +112,7 @@ struct LevelSched {
     CorrGeom corr{};                                 // map of dom(psi_{k-1}) for this level's correction
     DeviceBuffer d_cmap;
     DeviceBuffer d_cu_src, d_cu_dst, d_cp_src, d_cp_dst;
-    std::unique_ptr<Conv> convF, convPsi;
+    std::unique_ptr<ConvOp> convF, convPsi;
 };
 
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
@@ -120,10 +131,11 @@ struct lgf_plan {
     std::vector<std::vector<lgf::Blk>> levels;     // per level, offsets within one component
     std::vector<int64_t> level_base;               // element offset of each level in a component
     int64_t comp_len = 0;                          // elements per component
-    std::vector<std::unique_ptr<lgf::Conv>> convs;          // single-level plans
+    std::unique_ptr<lgf::ConvOp> op0;                       // single-level plans
     std::vector<std::unique_ptr<lgf::LevelSched>> lv;       // composite plans
     std::vector<const lgf::Conv *> convs_view;              // every convolution of the plan
     lgf::DeviceBuffer ws_fhat, ws_F, ws_psi[2], ws_ppsi, ws_srcF, ws_srcf;
+    lgf::DeviceBuffer ws_ut, ws_ush, ws_rho;               // refinement workspaces
     lgf::DeviceBuffer Fhat, Uhat;
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     size_t workspace_bytes() const;
@@ -147,6 +159,10 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
                hipStream_t s, lgf_report *reps);
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32);
 void plan_alloc_spectral(lgf_plan *plan);
+std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool refine);
+void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops);
+void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
+            hipStream_t s);
 void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,
               hipStream_t s);
 }  // namespace lgf

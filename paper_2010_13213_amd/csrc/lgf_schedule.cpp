@@ -54,15 +54,13 @@ std::vector<Key> dilate(const std::vector<Key> &in, int layers) {
 }  // namespace
 
 void build_schedule(lgf_plan *p) {
-    if (p->prec != LGF_FP64) throw Failure(LGF_E_UNSUPPORTED, "LGF_FP32_REFINE is not served by this build yet");
     lgf_context *ctx = p->ctx;
+    const bool refine = p->prec == LGF_FP32_REFINE;
     const int nb = p->nb, K = p->K;
     const int64_t nb3 = (int64_t)nb * nb * nb;
     if (K == 1) {
-        auto c = std::make_unique<Conv>();
-        build_conv(p, *c, p->levels[0], p->levels[0], false);
-        p->convs_view.push_back(c.get());
-        p->convs.push_back(std::move(c));
+        p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
+        plan_alloc_refine(p, {p->op0.get()});
         plan_alloc_spectral(p);
         return;
     }
@@ -139,12 +137,10 @@ void build_schedule(lgf_plan *p) {
         LevelSched &L = *p->lv[k];
         // convolution of the phi right-hand side: sources -> Omega_k targets
         std::vector<Blk> src = (k == 0) ? p->levels[0] : as_blk(ext[k]);
-        L.convF = std::make_unique<Conv>();
-        build_conv(p, *L.convF, src, p->levels[k], false);
+        L.convF = build_op(p, src, p->levels[k], refine);
         if (k + 1 < K) {
             std::vector<Blk> tgt = as_blk(dom[k]);
-            L.convPsi = std::make_unique<Conv>();
-            build_conv(p, *L.convPsi, src, tgt, false);
+            L.convPsi = build_op(p, src, tgt, refine);
             L.n_dom = (int)dom[k].size();
             max_dom = std::max<int64_t>(max_dom, L.n_dom);
             // dense map of dom(psi_k) for the level-(k+1) correction
@@ -216,10 +212,12 @@ void build_schedule(lgf_plan *p) {
     p->ws_ppsi.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "P psi");
     p->ws_srcF.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
     p->ws_srcf.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
+    std::vector<const ConvOp *> ops;
     for (int k = 0; k < K; ++k) {
-        p->convs_view.push_back(p->lv[k]->convF.get());
-        if (p->lv[k]->convPsi) p->convs_view.push_back(p->lv[k]->convPsi.get());
+        ops.push_back(p->lv[k]->convF.get());
+        ops.push_back(p->lv[k]->convPsi.get());
     }
+    plan_alloc_refine(p, ops);
     plan_alloc_spectral(p);
 }
 
@@ -253,8 +251,8 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
             double *psi_prev = (double *)p->ws_psi[cur].ptr;
             double *psi_next = (double *)p->ws_psi[cur ^ 1].ptr;
             if (k == 0) {
-                run_conv(p, *L.convF, FC, uc, dxk, 0, s);
-                if (L.convPsi) run_conv(p, *L.convPsi, FH, psi_next, dxk, 0, s);
+                run_op(p, *L.convF, FC, uc, dxk, 0, s);
+                if (L.convPsi) run_op(p, *L.convPsi, FH, psi_next, dxk, 0, s);
             } else {
                 hip_check(correction_source(nb, L.corr, psi_prev, (const int *)L.d_cmap.ptr, (const int *)L.d_fblk.ptr,
                                             (const int64_t *)L.d_ext_own.ptr, FC, FH, (double *)p->ws_ppsi.ptr,
@@ -263,13 +261,13 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
                 hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, uc, (const int64_t *)L.d_cu_src.ptr,
                                       (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
                           "P psi -> phi");
-                run_conv(p, *L.convF, (const double *)p->ws_srcF.ptr, uc, dxk, 1, s);
+                run_op(p, *L.convF, (const double *)p->ws_srcF.ptr, uc, dxk, 1, s);
                 if (L.convPsi) {
                     hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, psi_next,
                                           (const int64_t *)L.d_cp_src.ptr, (const int64_t *)L.d_cp_dst.ptr, L.n_dom,
                                           s),
                               "P psi -> psi");
-                    run_conv(p, *L.convPsi, (const double *)p->ws_srcf.ptr, psi_next, dxk, 1, s);
+                    run_op(p, *L.convPsi, (const double *)p->ws_srcf.ptr, psi_next, dxk, 1, s);
                 }
             }
             if (L.any_cover)
@@ -286,9 +284,8 @@ static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
         enqueue_composite(p, f, u, s);
         return;
     }
-    const Conv &c = *p->convs[0];
     for (int comp = 0; comp < p->nc; ++comp)
-        run_conv(p, c, f + (size_t)comp * p->comp_len, u + (size_t)comp * p->comp_len, p->dx0, 0, s);
+        run_op(p, *p->op0, f + (size_t)comp * p->comp_len, u + (size_t)comp * p->comp_len, p->dx0, 0, s);
 }
 
 void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report *rep) {
@@ -306,7 +303,7 @@ void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report
         hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         rep->device_ms = ms;
         rep->refine_rel_l2 = 0.0;
-        rep->passes = (int)(p->K == 1 ? 1 : p->convs_view.size());
+        rep->passes = (int)p->convs_view.size();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }

@@ -7,7 +7,11 @@
 //     Uhat_t(omega) = sum_s Khat_{t-s}(omega) Fhat_s(omega).
 //
 // Data layout: slots s = (z * ey + y) * bx + x over a padded box of blocks,
-// Fhat / Uhat [omega][slot], spectra table K[omega][dy][dz][dx].
+// Fhat / Uhat [omega][slot], spectra table K[omega][dy][dz][dx] for
+// dx, dy, dz >= 0 only.  A negative dy (dz) reflects the window along y (z):
+// its spectrum is the stored one at ky -> -ky (kz -> -kz).  A negative dx
+// reflects along x, which the half spectrum in kx serves as the complex
+// conjugate at (ky, kz) -> (-ky, -kz).
 //
 // One workgroup owns one frequency and one tile of TY x TZ target rows (a
 // row is the bx blocks along x at fixed (y, z)).  Lane (seg, ty, tz) keeps A
@@ -63,12 +67,26 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ)
     const int x0 = seg * A;
 
     const size_t kper = (size_t)g.XD * g.YD * g.ZD;
-    const cplx<R> *Kf = Ktab + (size_t)freq * kper;
     const cplx<R> *Ff = Fhat + (size_t)freq * g.n_slots;
-
-    auto kidx = [&](int dy, int dz, int dxi) -> size_t {
-        // dxi in [0, KW): dx = dxi - (BX - 1)
-        return ((size_t)(dy + g.YH) * g.ZD + (dz + g.ZH)) * g.XD + (dxi - (BX - 1) + g.XH);
+    // the four frequency rows reached by reflections: [flip ky][flip kz]
+    const cplx<R> *Kf[2][2];
+    {
+        const int H = g.N / 2 + 1;
+        const int kx = freq % H, ky = (freq / H) % g.N, kz = freq / (H * g.N);
+        const int kyr = (g.N - ky) % g.N, kzr = (g.N - kz) % g.N;
+        Kf[0][0] = Ktab + ((size_t)(kz * g.N + ky) * H + kx) * kper;
+        Kf[1][0] = Ktab + ((size_t)(kz * g.N + kyr) * H + kx) * kper;
+        Kf[0][1] = Ktab + ((size_t)(kzr * g.N + ky) * H + kx) * kper;
+        Kf[1][1] = Ktab + ((size_t)(kzr * g.N + kyr) * H + kx) * kper;
+    }
+    // kernel value at offset (dxi - (BX - 1), dy, dz), dxi in [0, KW)
+    auto kload = [&](int dy, int dz, int dxi) -> cplx<R> {
+        const int dx = dxi - (BX - 1);
+        const bool fx = dx < 0;
+        const int fy = (dy < 0) != fx, fz = (dz < 0) != fx;
+        cplx<R> v = Kf[fy][fz][((size_t)abs(dy) * g.ZD + abs(dz)) * g.XD + abs(dx)];
+        if (fx) v.y = -v.y;
+        return v;
     };
     auto lds = [&](int dy, int dz, int dxi) -> int { return (pmod(dy, SY) * SZ + pmod(dz, SZ)) * KW + dxi; };
 
@@ -83,7 +101,7 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ)
         for (int e = l; e < TY * TZ * KW; e += NT) {
             const int dxi = e % KW, q = e / KW;
             const int dy = dy0 + q % TY, dz = dz0 + q / TY;
-            kbuf[lds(dy, dz, dxi)] = Kf[kidx(dy, dz, dxi)];
+            kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
         }
         for (int e = l; e < BX; e += NT) frow[0][e] = Ff[((size_t)sz * g.ey + sy) * BX + e];
     }
@@ -120,7 +138,7 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ)
                     const int dxi = e % KW, q = e / KW;
                     const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
                     const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
-                    pre[p] = Kf[kidx(dy, dz, dxi)];
+                    pre[p] = kload(dy, dz, dxi);
                 }
             }
             if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * BX + l];
@@ -167,7 +185,7 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ)
             for (int e = l; e < TY * TZ * KW; e += NT) {
                 const int dxi = e % KW, q = e / KW;
                 const int dy = dy0 + q % TY, dz = dz0 + q / TY;
-                kbuf[lds(dy, dz, dxi)] = Kf[kidx(dy, dz, dxi)];
+                kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
             }
             for (int e = l; e < BX; e += NT) frow[buf ^ 1][e] = Ff[((size_t)nsz * g.ey + nsy) * BX + e];
             __syncthreads();

@@ -25,8 +25,11 @@
 // Spectra (Sec. 2.2 convolution evaluated blockwise): for a block offset d the
 // kernel window K_d(m) = G(d nb + m), m in [-(nb-1), nb-1]^3, is laid on a
 // (2nb)^3 grid circularly (index m mod 2nb; the index nb stays 0) and
-// transformed with a real-to-complex FFT.  The spectra of all offsets of a
-// table are stored frequency-major: tab[omega][dy][dz][dx].
+// transformed with a real-to-complex FFT.  G is even in every coordinate, so
+// only offsets with dx, dy, dz >= 0 are stored (frequency-major,
+// tab[omega][dy][dz][dx]); a reflection of the offset is a reflection of the
+// window, i.e. a sign flip of the matching frequency index (see the loader
+// in lgf_smac.hip).
 #include <math.h>
 
 #include "lgf_device.hpp"
@@ -123,10 +126,10 @@ struct SpecGeom {
 };
 
 __device__ __forceinline__ void offset_of(const SpecGeom &g, int o, int &dx, int &dy, int &dz) {
-    // linear offset o -> (dx, dy, dz); table order is [dy][dz][dx]
-    dx = o % g.XD - g.XH;
-    dz = (o / g.XD) % g.ZD - g.ZH;
-    dy = o / (g.XD * g.ZD) - g.YH;
+    // linear offset o -> (dx, dy, dz) >= 0; table order is [dy][dz][dx]
+    dx = o % g.XD;
+    dz = (o / g.XD) % g.ZD;
+    dy = o / (g.XD * g.ZD);
 }
 
 template <int N> __device__ __forceinline__ int circ(int i) {
@@ -206,9 +209,9 @@ hipError_t build_spectra_n(const double *gc, int nb, int XH, int YH, int ZH, voi
     g.XH = XH;
     g.YH = YH;
     g.ZH = ZH;
-    g.XD = 2 * XH + 1;
-    g.YD = 2 * YH + 1;
-    g.ZD = 2 * ZH + 1;
+    g.XD = XH + 1;
+    g.YD = YH + 1;
+    g.ZD = ZH + 1;
     const int n_off = g.XD * g.YD * g.ZD;
     const size_t per_off = (size_t)N * N * H * sizeof(cplx<double>);
     const int chunk = (int)std::min<size_t>((size_t)n_off, scratch_bytes / per_off);

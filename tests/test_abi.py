@@ -56,7 +56,7 @@ def test_problem_check_rejects_malformed_problems(case):
     elif case == "dx":
         args["dx0"] = -1.0
     elif case == "comp":
-        args["n_components"] = 2
+        args["n_components"] = 9
     elif case == "nest":
         args["level_blocks"] = [_cube(2), np.array([[9, 0, 0]])]
     elif case == "empty":
