@@ -64,6 +64,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["both", "fp64", "fp32_refine"], default="both",
+                    help="which precision paths to time (profiling runs use one)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (counter calibration reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LGF path here runs on a single MI355X and has no "
@@ -81,6 +87,12 @@ def main():
     n_blocks = len(prob.levels[0].blocks)
     cells = n_blocks * nb ** 3 * prob.n_components
     f = torch.from_numpy(prob.flat_source()).cuda()
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def timed(precision):
         t_plan = time.perf_counter()
@@ -110,8 +122,10 @@ def main():
         plan.close()
         return {"wall": t1 - t0, "lat": lat, "stages": st, "plan_s": t_plan, "u": host}
 
-    r64 = timed("fp64")
-    r32 = timed("fp32_refine")
+    r64 = timed("fp64") if args.only in ("both", "fp64") else None
+    r32 = timed("fp32_refine") if args.only in ("both", "fp32_refine") else None
+    if r64 is None:
+        r64 = r32
 
     # error of each result against the oracle on a sample of targets
     c = inputs.cell_coords(prob.levels[0].blocks, nb)
@@ -152,19 +166,38 @@ def main():
                                "single level, scalar; value = FP64 path",
                    "cells": cells, "block_pairs": pairs, "plan_s": round(r64["plan_s"], 3)},
         "latency_ms": {"p50": _pct(r64["lat"], 50), "p99": _pct(r64["lat"], 99)},
-        "err_vs_oracle": {"fp64": err(r64["u"]), "fp32_refine": err(r32["u"]),
+        "err_vs_oracle": {"fp64": err(r64["u"]),
+                          "fp32_refine": err(r32["u"]) if r32 else None,
                           "sample": "48 random target cells, relative L2"},
-        "fp32_refine": {"value": cells * args.steps / r32["wall"], "unit": "cells/s",
-                        "ms_per_step": 1e3 * r32["wall"] / args.steps,
-                        "latency_ms": {"p50": _pct(r32["lat"], 50), "p99": _pct(r32["lat"], 99)},
-                        "stages_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
-                        "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
+        "fp32_refine": None if r32 is None else {
+            "value": cells * args.steps / r32["wall"], "unit": "cells/s",
+            "ms_per_step": 1e3 * r32["wall"] / args.steps,
+            "latency_ms": {"p50": _pct(r32["lat"], 50), "p99": _pct(r32["lat"], 99)},
+            "stages_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
+            "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in r64["stages"].items()},
         "roofline": {"bound": "alu", "kernel": "smac_kernel<16,8,16,16,double>",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "algorithmic_flops_per_launch": flops_mac, "avg_launch_ms": smac_avg},
     }
+    if not args.no_serving:
+        from paper_2010_13213_amd import serve
+        reqs = inputs.served_stream(args.serve_requests)
+        pool = serve.PlanPool(ctx)
+        serve.serve(ctx, reqs[:32], None, pool=pool)
+        cap = serve.serve(ctx, reqs, None, pool=pool)
+        run = serve.serve(ctx, reqs, 0.9 * cap["requests_per_s"], pool=pool)
+        pool.close()
+        out["serving"] = {
+            "workload": "%d independent dense-cube solves, side 16..128 cells (8^3 blocks), 1-4 Gaussian "
+                        "blobs, half FP64 / half FP32+refine, Poisson arrivals at 0.9 x capacity"
+                        % len(reqs),
+            "capacity_requests_per_s": cap["requests_per_s"],
+            "rate_requests_per_s": run["rate_req_per_s"],
+            "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"],
+            "throughput_cells_per_s": run["throughput_cells_per_s"],
+            "mean_batch": run["mean_batch"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

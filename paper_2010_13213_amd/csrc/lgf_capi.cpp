@@ -131,6 +131,7 @@ lgf_status lgf_context_create(int device, size_t hbm_budget_bytes, lgf_context *
         ctx = new lgf_context(device, hbm_budget_bytes);
         hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "hipStreamCreate");
         build_context_table(ctx);
+        ring_init(ctx);
     });
     if (st != LGF_OK) {
         if (ctx) lgf_context_destroy(ctx);
@@ -152,6 +153,7 @@ void lgf_context_destroy(lgf_context *ctx) {
         (void)hipEventDestroy(e.b);
     }
     ctx->pending.clear();
+    ring_free(ctx);
     ctx->tables.clear();
     ctx->gcube.release();
     if (ctx->stream) hipStreamDestroy(ctx->stream);

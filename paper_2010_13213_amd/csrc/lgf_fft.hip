@@ -28,14 +28,13 @@ template <int NB, typename R> struct FftShape {
 };
 
 template <int NB, typename R>
-__global__ void __launch_bounds__(256) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
-                                                  const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
-                                                  int64_t n_slots, double scale) {
+__device__ __forceinline__ void fwd_body(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
+                                         const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t n_slots,
+                                         double scale, int b) {
     using S = FftShape<NB, R>;
     constexpr int N = S::N, H = S::H, HH = S::HH;
     __shared__ cplx<R> A[S::A_ELEMS];
     __shared__ cplx<R> B[S::B_ELEMS];
-    const int b = blockIdx.x;
     const double *in = src + blk_off[b];
     const int64_t sl = slot[b];
     const int t = threadIdx.x;
@@ -86,14 +85,36 @@ __global__ void __launch_bounds__(256) fwd_kernel(const double *__restrict__ src
 }
 
 template <int NB, typename R>
-__global__ void __launch_bounds__(256) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
-                                                  const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
-                                                  double *__restrict__ dst, double scale, int accumulate) {
+__global__ void __launch_bounds__(256) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
+                                                  const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
+                                                  int64_t n_slots, double scale) {
+    fwd_body<NB, R>(src, blk_off, slot, Fhat, n_slots, scale, blockIdx.x);
+}
+
+__device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].blk_begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NB, typename R>
+__global__ void __launch_bounds__(256) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
+    const FftJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, blockIdx.x - j.blk_begin);
+}
+
+template <int NB, typename R>
+__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+                                         const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
+                                         double *__restrict__ dst, double scale, int accumulate, int b) {
     using S = FftShape<NB, R>;
     constexpr int N = S::N, H = S::H, HH = S::HH;
     __shared__ cplx<R> D[S::A_ELEMS];   // [z][y][kx] after the z and y passes
     __shared__ cplx<R> C[S::B_ELEMS];   // [z][ky][kxl]
-    const int b = blockIdx.x;
     const int64_t sl = slot[b];
     const int t = threadIdx.x;
 
@@ -148,6 +169,30 @@ __global__ void __launch_bounds__(256) inv_kernel(const cplx<R> *__restrict__ Uh
 }
 
 template <int NB, typename R>
+__global__ void __launch_bounds__(256) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+                                                  const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
+                                                  double *__restrict__ dst, double scale, int accumulate) {
+    inv_body<NB, R>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, blockIdx.x);
+}
+
+template <int NB, typename R>
+__global__ void __launch_bounds__(256) inv_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
+    const FftJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    inv_body<NB, R>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
+                    blockIdx.x - j.blk_begin);
+}
+
+template <int NB, typename R>
+hipError_t batch_launch(bool inverse, const FftJob *jobs, int n_jobs, int total_blocks, hipStream_t s) {
+    if (n_jobs <= 0 || total_blocks <= 0) return hipSuccess;
+    if (inverse)
+        hipLaunchKernelGGL((inv_batch_kernel<NB, R>), dim3(total_blocks), dim3(256), 0, s, jobs, n_jobs);
+    else
+        hipLaunchKernelGGL((fwd_batch_kernel<NB, R>), dim3(total_blocks), dim3(256), 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
+template <int NB, typename R>
 hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
                       int64_t n_slots, double scale, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
@@ -175,6 +220,28 @@ hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t
     if (nb == 8)
         return fp32 ? fwd_launch<8, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s)
                     : fwd_launch<8, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t block_fft_forward_batch(int nb, bool fp32, const FftJob *jobs, int n_jobs, int total_blocks,
+                                   hipStream_t s) {
+    if (nb == 16)
+        return fp32 ? batch_launch<16, float>(false, jobs, n_jobs, total_blocks, s)
+                    : batch_launch<16, double>(false, jobs, n_jobs, total_blocks, s);
+    if (nb == 8)
+        return fp32 ? batch_launch<8, float>(false, jobs, n_jobs, total_blocks, s)
+                    : batch_launch<8, double>(false, jobs, n_jobs, total_blocks, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t block_fft_inverse_batch(int nb, bool fp32, const FftJob *jobs, int n_jobs, int total_blocks,
+                                   hipStream_t s) {
+    if (nb == 16)
+        return fp32 ? batch_launch<16, float>(true, jobs, n_jobs, total_blocks, s)
+                    : batch_launch<16, double>(true, jobs, n_jobs, total_blocks, s);
+    if (nb == 8)
+        return fp32 ? batch_launch<8, float>(true, jobs, n_jobs, total_blocks, s)
+                    : batch_launch<8, double>(true, jobs, n_jobs, total_blocks, s);
     return hipErrorInvalidValue;
 }
 

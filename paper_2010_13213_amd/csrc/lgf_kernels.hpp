@@ -29,6 +29,21 @@ hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slot
                              const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
                              hipStream_t s);
 
+// Batched block FFTs: job i covers blocks [blk_begin, next blk_begin) of the grid.
+struct FftJob {
+    const double *src;      // forward: source field base;     inverse: unused
+    double *dst;            // inverse: destination field base; forward: unused
+    const int64_t *blk_off; // per block: element offset in src / dst
+    const int *slot;        // per block: slot in the spectral workspace
+    void *spec;             // forward: Fhat; inverse: Uhat
+    int64_t n_slots;
+    double scale;
+    int accumulate;
+    int blk_begin;
+};
+hipError_t block_fft_forward_batch(int nb, bool fp32, const FftJob *jobs, int n_jobs, int total_blocks, hipStream_t s);
+hipError_t block_fft_inverse_batch(int nb, bool fp32, const FftJob *jobs, int n_jobs, int total_blocks, hipStream_t s);
+
 // ---- spectral multiply-accumulate (lgf_smac.hip) ----
 struct SmacGeom {
     int bx;                 // row length template (8, 16 or 32)
@@ -40,6 +55,17 @@ struct SmacGeom {
     int n_rows;             // source rows (sy, sz), serpentine order
     int n_tiles;            // target tiles (ty0, tz0)
 };
+// One convolution of a batched spectral-MAC launch (device-resident table).
+struct SmacJob {
+    SmacGeom g;
+    const void *F;
+    void *U;
+    const void *K;
+    const int2 *rows;
+    const int2 *tiles;
+    int64_t wg_begin;       // first workgroup of this job in the batched grid
+};
+hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s);
 int smac_tile_y(int bx);
 int smac_tile_z(int bx);
 // Uhat[omega][t] = sum_s K[omega][t - s] * Fhat[omega][s] over every source row

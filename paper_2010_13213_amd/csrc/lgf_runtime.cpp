@@ -98,6 +98,30 @@ void resolve_stage_times(lgf_context *ctx, double *ms, int64_t *launches) {
     ctx->pending.clear();
 }
 
+// ------------------------------------------------------------------ job ring
+
+void ring_init(lgf_context *ctx) {
+    JobRing &r = ctx->ring;
+    const size_t n = JobRing::kSlots * JobRing::kSlotBytes;
+    hip_check(hipHostMalloc(&r.host, n, hipHostMallocDefault), "hipHostMalloc job ring");
+    hip_check(hipMalloc(&r.dev, n), "hipMalloc job ring");
+    for (int i = 0; i < JobRing::kSlots; ++i)
+        hip_check(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming), "ring event");
+}
+
+void ring_free(lgf_context *ctx) {
+    JobRing &r = ctx->ring;
+    for (int i = 0; i < JobRing::kSlots; ++i)
+        if (r.done[i]) {
+            (void)hipEventSynchronize(r.done[i]);
+            (void)hipEventDestroy(r.done[i]);
+            r.done[i] = nullptr;
+        }
+    if (r.host) (void)hipHostFree(r.host);
+    if (r.dev) (void)hipFree(r.dev);
+    r.host = r.dev = nullptr;
+}
+
 // ------------------------------------------------------------------ context
 
 lgf_context_impl::lgf_context_impl(int dev, size_t budget_) : device(dev), budget(budget_) {}
@@ -344,29 +368,32 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
     return op;
 }
 
+void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
+                   hipStream_t s) {
+    const int nb = plan->nb;
+    double *ut = (double *)plan->ws_ut.ptr, *ush = (double *)plan->ws_ush.ptr, *rho = (double *)plan->ws_rho.ptr;
+    RefGeom g = op.geom;
+    g.dx = dx;
+    StageTimer t(plan->ctx, 3, s);
+    hip_check(refine_residual(nb, g, (const int *)op.d_map.ptr, (const int *)op.d_tblk.ptr, (const int *)op.d_t2sh.ptr,
+                              (const unsigned char *)op.d_depth.ptr, ut, ush, src, (const int64_t *)op.d_gofs.ptr, rho,
+                              op.n_t, s),
+              "refinement residual");
+    hip_check(refine_assemble(nb, (const int *)op.d_t2sh.ptr, ut, ush, (const int64_t *)op.d_dofs.ptr, dst,
+                              accumulate, op.n_t, s),
+              "refinement assemble");
+}
+
 void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
             hipStream_t s) {
     if (!op.refined) {
         run_conv(plan, *op.c64, src, dst, dx, accumulate, s);
         return;
     }
-    const int nb = plan->nb;
-    double *ut = (double *)plan->ws_ut.ptr, *ush = (double *)plan->ws_ush.ptr, *rho = (double *)plan->ws_rho.ptr;
-    run_conv(plan, *op.c32, src, ut, dx, 0, s);
-    run_conv(plan, *op.c64, src, ush, dx, 0, s);
-    RefGeom g = op.geom;
-    g.dx = dx;
-    {
-        StageTimer t(plan->ctx, 3, s);
-        hip_check(refine_residual(nb, g, (const int *)op.d_map.ptr, (const int *)op.d_tblk.ptr,
-                                  (const int *)op.d_t2sh.ptr, (const unsigned char *)op.d_depth.ptr, ut, ush, src,
-                                  (const int64_t *)op.d_gofs.ptr, rho, op.n_t, s),
-                  "refinement residual");
-        hip_check(refine_assemble(nb, (const int *)op.d_t2sh.ptr, ut, ush, (const int64_t *)op.d_dofs.ptr, dst,
-                                  accumulate, op.n_t, s),
-                  "refinement assemble");
-    }
-    run_conv(plan, *op.ccorr, rho, dst, dx, 1, s);
+    run_conv(plan, *op.c32, src, (double *)plan->ws_ut.ptr, dx, 0, s);
+    run_conv(plan, *op.c64, src, (double *)plan->ws_ush.ptr, dx, 0, s);
+    refine_middle(plan, op, src, dst, dx, accumulate, s);
+    run_conv(plan, *op.ccorr, (const double *)plan->ws_rho.ptr, dst, dx, 1, s);
 }
 
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {

@@ -57,9 +57,21 @@ struct StageEvent {
     hipEvent_t a, b;
 };
 
+// Pinned-host / device staging ring for the job tables of batched launches.
+struct JobRing {
+    static constexpr int kSlots = 32;
+    static constexpr size_t kSlotBytes = 256 << 10;
+    std::mutex mu;
+    void *host = nullptr;           // hipHostMalloc, kSlots * kSlotBytes
+    void *dev = nullptr;            // hipMalloc, same size
+    hipEvent_t done[kSlots] = {};
+    int next = 0;
+};
+
 struct lgf_context_impl {
     int device;
     bool timing = false;
+    JobRing ring;
     std::vector<StageEvent> pending;
     size_t budget;
     size_t used = 0;
@@ -152,6 +164,8 @@ struct StageTimer {
     ~StageTimer();
 };
 void resolve_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
+void ring_init(lgf_context *ctx);
+void ring_free(lgf_context *ctx);
 void build_context_table(lgf_context *ctx);
 void build_schedule(lgf_plan *plan);
 void run_plan(lgf_plan *plan, const double *f, double *u, hipStream_t s, lgf_report *rep);
@@ -161,6 +175,8 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
 void plan_alloc_spectral(lgf_plan *plan);
 std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool refine);
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops);
+void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
+                   hipStream_t s);
 void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
             hipStream_t s);
 void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,

@@ -16,7 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -309,10 +311,191 @@ void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report
     }
 }
 
+namespace {
+
+// One convolution of a batch: plan workspace, sources -> destination.
+struct ConvCall {
+    lgf_plan *p;
+    const Conv *c;
+    const double *src;
+    double *dst;
+    double dx;
+    int accumulate;
+};
+
+// Copy a job table into the next ring slot (pinned host -> device, on s).
+template <typename T> const T *stage_jobs(lgf_context *ctx, const std::vector<T> &jobs, hipStream_t s, int &slot) {
+    JobRing &r = ctx->ring;
+    const size_t bytes = sizeof(T) * jobs.size();
+    if (bytes > JobRing::kSlotBytes) throw Failure(LGF_E_UNSUPPORTED, "batch job table larger than 256 KiB");
+    std::lock_guard<std::mutex> lk(r.mu);
+    const int k = r.next;
+    r.next = (r.next + 1) % JobRing::kSlots;
+    hip_check(hipEventSynchronize(r.done[k]), "ring slot wait");
+    char *h = (char *)r.host + (size_t)k * JobRing::kSlotBytes;
+    char *d = (char *)r.dev + (size_t)k * JobRing::kSlotBytes;
+    std::memcpy(h, jobs.data(), bytes);
+    hip_check(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s), "job table copy");
+    slot = k;
+    return (const T *)d;
+}
+
+// The slot may be reused once the launch that reads it has completed.
+void ring_mark(lgf_context *ctx, int slot, hipStream_t s) {
+    JobRing &r = ctx->ring;
+    std::lock_guard<std::mutex> lk(r.mu);
+    hip_check(hipEventRecord(r.done[slot], s), "ring event record");
+}
+
+// Every call runs its forward FFTs, spectral MAC and inverse FFTs; calls with
+// the same block size / row template / precision share one launch per stage.
+void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStream_t s) {
+    if (calls.empty()) return;
+    for (const ConvCall &k : calls)
+        if (k.p->fhat_conv != k.c) {
+            hip_check(hipMemsetAsync(k.p->Fhat.ptr, 0, k.p->Fhat.bytes, s), "clear Fhat");
+            k.p->fhat_conv = k.c;
+        }
+    const int nb = calls[0].p->nb;
+    for (const ConvCall &k : calls)
+        if (k.p->nb != nb) throw Failure(LGF_E_INVALID, "internal: mixed block sizes in one batch group");
+    const double N3 = 8.0 * nb * nb * nb;
+    for (int fp = 0; fp < 2; ++fp) {
+        std::vector<FftJob> fj;
+        int total = 0;
+        for (const ConvCall &k : calls) {
+            if ((int)k.c->fp32 != fp || k.c->n_src == 0) continue;
+            FftJob j{};
+            j.src = k.src;
+            j.blk_off = (const int64_t *)k.c->d_src_off.ptr;
+            j.slot = (const int *)k.c->d_src_slot.ptr;
+            j.spec = k.p->Fhat.ptr;
+            j.n_slots = k.c->n_slots;
+            j.scale = 1.0;
+            j.blk_begin = total;
+            total += k.c->n_src;
+            fj.push_back(j);
+        }
+        if (fj.empty()) continue;
+        StageTimer t(ctx, 0, s);
+        int slot = 0;
+        hip_check(block_fft_forward_batch(nb, fp == 1, stage_jobs(ctx, fj, s, slot), (int)fj.size(), total, s),
+                  "batched forward FFT");
+        ring_mark(ctx, slot, s);
+    }
+    for (int fp = 0; fp < 2; ++fp)
+        for (int bx : {8, 16, 32}) {
+            std::vector<SmacJob> sj;
+            int64_t total = 0;
+            for (const ConvCall &k : calls) {
+                if ((int)k.c->fp32 != fp || k.c->bx != bx || k.c->n_rows == 0 || k.c->n_tiles == 0) continue;
+                SmacJob j{};
+                j.g = conv_geom(*k.c);
+                j.F = k.p->Fhat.ptr;
+                j.U = k.p->Uhat.ptr;
+                j.K = k.c->spec->data.ptr;
+                j.rows = (const int2 *)k.c->d_rows.ptr;
+                j.tiles = (const int2 *)k.c->d_tiles.ptr;
+                j.wg_begin = total;
+                total += (int64_t)j.g.n_freq * j.g.n_tiles;
+                sj.push_back(j);
+            }
+            if (sj.empty()) continue;
+            StageTimer t(ctx, 1, s);
+            int slot = 0;
+            hip_check(smac_batch_launch(bx, fp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(), total, s),
+                      "batched spectral MAC");
+            ring_mark(ctx, slot, s);
+        }
+    for (int fp = 0; fp < 2; ++fp) {
+        std::vector<FftJob> fj;
+        int total = 0;
+        for (const ConvCall &k : calls) {
+            if ((int)k.c->fp32 != fp || k.c->n_tgt == 0) continue;
+            FftJob j{};
+            j.dst = k.dst;
+            j.blk_off = (const int64_t *)k.c->d_tgt_off.ptr;
+            j.slot = (const int *)k.c->d_tgt_slot.ptr;
+            j.spec = k.p->Uhat.ptr;
+            j.n_slots = k.c->n_slots;
+            j.scale = k.dx * k.dx / N3;
+            j.accumulate = k.accumulate;
+            j.blk_begin = total;
+            total += k.c->n_tgt;
+            fj.push_back(j);
+        }
+        if (fj.empty()) continue;
+        StageTimer t(ctx, 2, s);
+        int slot = 0;
+        hip_check(block_fft_inverse_batch(nb, fp == 1, stage_jobs(ctx, fj, s, slot), (int)fj.size(), total, s),
+                  "batched inverse FFT");
+        ring_mark(ctx, slot, s);
+    }
+}
+
+}  // namespace
+
 void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
                hipStream_t s, lgf_report *reps) {
-    (void)ctx;
-    for (int i = 0; i < n; ++i) run_plan(plans[i], f[i], u[i], s, reps ? &reps[i] : nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (reps) {
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        hip_check(hipEventRecord(e0, s), "event record");
+    }
+    // composite plans run one after another; single-level plans are batched
+    std::map<int, std::vector<int>> by_nb;
+    for (int i = 0; i < n; ++i) {
+        if (plans[i]->K > 1) {
+            enqueue(plans[i], f[i], u[i], s);
+            continue;
+        }
+        by_nb[plans[i]->nb].push_back(i);
+    }
+    for (auto &kv : by_nb) {
+        const std::vector<int> &ids = kv.second;
+        int max_nc = 0;
+        for (int i : ids) max_nc = std::max(max_nc, plans[i]->nc);
+        for (int comp = 0; comp < max_nc; ++comp) {
+            std::vector<ConvCall> a1, a2, c;
+            for (int i : ids) {
+                lgf_plan *p = plans[i];
+                if (comp >= p->nc) continue;
+                const double *src = f[i] + (size_t)comp * p->comp_len;
+                double *dst = u[i] + (size_t)comp * p->comp_len;
+                const ConvOp &op = *p->op0;
+                if (!op.refined) {
+                    a1.push_back(ConvCall{p, op.c64.get(), src, dst, p->dx0, 0});
+                } else {
+                    a1.push_back(ConvCall{p, op.c32.get(), src, (double *)p->ws_ut.ptr, p->dx0, 0});
+                    a2.push_back(ConvCall{p, op.c64.get(), src, (double *)p->ws_ush.ptr, p->dx0, 0});
+                    c.push_back(ConvCall{p, op.ccorr.get(), (const double *)p->ws_rho.ptr, dst, p->dx0, 1});
+                }
+            }
+            run_conv_batch(ctx, a1, s);
+            run_conv_batch(ctx, a2, s);
+            for (int i : ids) {
+                lgf_plan *p = plans[i];
+                if (comp >= p->nc || !p->op0->refined) continue;
+                refine_middle(p, *p->op0, f[i] + (size_t)comp * p->comp_len, u[i] + (size_t)comp * p->comp_len,
+                              p->dx0, 0, s);
+            }
+            run_conv_batch(ctx, c, s);
+        }
+    }
+    if (reps) {
+        hip_check(hipEventRecord(e1, s), "event record");
+        hip_check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        for (int i = 0; i < n; ++i) {
+            reps[i].device_ms = ms;
+            reps[i].refine_rel_l2 = 0.0;
+            reps[i].passes = (int)plans[i]->convs_view.size();
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
 }
 
 }  // namespace lgf

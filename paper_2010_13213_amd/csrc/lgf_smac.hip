@@ -48,16 +48,16 @@ template <int BX, int A, int TY, int TZ> struct SmacCfg {
 };
 
 template <int BX, int A, int TY, int TZ, typename R>
-__global__ void __launch_bounds__((BX / A) * TY * TZ)
-    smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
-                const cplx<R> *__restrict__ Ktab, const int2 *__restrict__ rows, const int2 *__restrict__ tiles) {
+__device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__restrict__ Fhat,
+                                          cplx<R> *__restrict__ Uhat, const cplx<R> *__restrict__ Ktab,
+                                          const int2 *__restrict__ rows, const int2 *__restrict__ tiles, int64_t wg) {
     using C = SmacCfg<BX, A, TY, TZ>;
     constexpr int KW = C::KW, SY = C::SY, SZ = C::SZ, NT = C::NT;
     __shared__ cplx<R> kbuf[SY * SZ * KW];
     __shared__ cplx<R> frow[2][BX];
 
-    const int freq = blockIdx.x % g.n_freq;
-    const int tile = blockIdx.x / g.n_freq;
+    const int freq = (int)(wg % g.n_freq);
+    const int tile = (int)(wg / g.n_freq);
     const int ty0 = tiles[tile].x, tz0 = tiles[tile].y;
     const int l = threadIdx.x;
     const int seg = l % C::NSEG;
@@ -202,6 +202,29 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ)
 }
 
 template <int BX, int A, int TY, int TZ, typename R>
+__global__ void __launch_bounds__((BX / A) * TY * TZ)
+    smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
+                const cplx<R> *__restrict__ Ktab, const int2 *__restrict__ rows, const int2 *__restrict__ tiles) {
+    smac_body<BX, A, TY, TZ, R>(g, Fhat, Uhat, Ktab, rows, tiles, blockIdx.x);
+}
+
+// Several independent convolutions of one template in one grid: workgroup w
+// belongs to the job with wg_begin <= w < next job's wg_begin.
+template <int BX, int A, int TY, int TZ, typename R>
+__global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const SmacJob *__restrict__ jobs, int n_jobs) {
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].wg_begin <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const SmacJob &j = jobs[lo];
+    smac_body<BX, A, TY, TZ, R>(j.g, (const cplx<R> *)j.F, (cplx<R> *)j.U, (const cplx<R> *)j.K, j.rows, j.tiles,
+                                w - j.wg_begin);
+}
+
+template <int BX, int A, int TY, int TZ, typename R>
 hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const int2 *rows,
                       const int2 *tiles, hipStream_t s) {
     using C = SmacCfg<BX, A, TY, TZ>;
@@ -212,7 +235,32 @@ hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, 
     return hipGetLastError();
 }
 
+template <int BX, int A, int TY, int TZ, typename R>
+hipError_t launch_batch_cfg(const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s) {
+    using C = SmacCfg<BX, A, TY, TZ>;
+    if (n_jobs <= 0 || total_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL((smac_batch_kernel<BX, A, TY, TZ, R>), dim3((unsigned)total_wg), dim3(C::NT), 0, s, jobs,
+                       n_jobs);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s) {
+    switch (bx) {
+    case 8:
+        return fp32 ? launch_batch_cfg<8, 8, 8, 8, float>(jobs, n_jobs, total_wg, s)
+                    : launch_batch_cfg<8, 8, 8, 8, double>(jobs, n_jobs, total_wg, s);
+    case 16:
+        return fp32 ? launch_batch_cfg<16, 8, 16, 16, float>(jobs, n_jobs, total_wg, s)
+                    : launch_batch_cfg<16, 8, 16, 16, double>(jobs, n_jobs, total_wg, s);
+    case 32:
+        return fp32 ? launch_batch_cfg<32, 16, 16, 8, float>(jobs, n_jobs, total_wg, s)
+                    : launch_batch_cfg<32, 16, 16, 8, double>(jobs, n_jobs, total_wg, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
 
 int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
 int smac_tile_z(int bx) { return bx == 8 ? 8 : (bx == 16 ? 16 : 8); }

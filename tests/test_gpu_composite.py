@@ -116,3 +116,33 @@ def test_half_resolution_two_level_ring_parity(gpu_ctx):
     got = _gpu(gpu_ctx, 8, p.dx0, blocks, [fk[None] for fk in f])
     for k in range(2):
         assert rel_l2(got[k][0][sample[k]], ref[k][sample[k]]) < TOL64, k
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_refine", 1e-10)])
+def test_full_size_two_level_ring_against_stored_oracle(gpu_ctx, precision, tol):
+    """Coarse R/32 ring support (208 blocks of 16^3) plus R/64 blocks within
+    3 sigma of the perturbed core (320 blocks); omega_x and omega_y.  The
+    expected values on 600 sampled cells per level were written by
+    tests/golden/make_two_level_ring.py, which calls only the oracle."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "two_level_ring_samples.npz"))
+    p = inputs.two_level_ring(components=(0, 1))
+    assert len(p.levels[0].blocks) == int(gold["n_blocks0"])
+    assert len(p.levels[1].blocks) == int(gold["n_blocks1"])
+    fields = [lv.values.reshape(2, -1) for lv in p.levels]
+    got = _gpu(gpu_ctx, p.nb, p.dx0, [lv.blocks for lv in p.levels], fields) if precision == "fp64" \
+        else _gpu_prec(gpu_ctx, p, precision)
+    for c in range(2):
+        for k in range(2):
+            idx = gold["sample%d" % k]
+            assert rel_l2(got[k][c][idx], gold["phi%d_c%d" % (k, c)]) < tol, (c, k)
+
+
+def _gpu_prec(ctx, p, precision):
+    import torch
+    from paper_2010_13213_amd import lgf
+    plan = lgf.Plan.for_problem(ctx, p, precision)
+    u = plan.solve(torch.from_numpy(p.flat_source()).cuda()).cpu().numpy().reshape(p.n_components, -1)
+    plan.close()
+    n0 = len(p.levels[0].blocks) * p.nb ** 3
+    return [u[:, :n0], u[:, n0:]]
