@@ -52,6 +52,7 @@ struct SmacGeom {
     int64_t n_slots;        // bx * ey * ez
     int XH, YH, ZH, XD, YD, ZD;   // octant spectra table extents (XD = XH + 1, ...)
     int N;                        // FFT edge 2 nb (frequency index remap)
+    const int *perm;              // frequency order: reflection partners adjacent
     int n_rows;             // source rows (sy, sz), serpentine order
     int n_tiles;            // target tiles (ty0, tz0)
 };

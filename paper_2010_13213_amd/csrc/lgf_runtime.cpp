@@ -161,6 +161,29 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
                             scratch.bytes, ctx->stream),
               "build_spectra");
     hip_check(hipStreamSynchronize(ctx->stream), "spectra sync");
+    {
+        // omega = (kz N + ky) H + kx; its partners (kx, -ky, kz), (kx, ky, -kz),
+        // (kx, -ky, -kz) read the same octant rows of the table
+        const int H = nb + 1;
+        std::vector<int> perm;
+        std::vector<char> seen(t->n_freq, 0);
+        for (int w = 0; w < t->n_freq; ++w) {
+            if (seen[w]) continue;
+            const int kx = w % H, ky = (w / H) % N, kz = w / (H * N);
+            const int kys[2] = {ky, (N - ky) % N}, kzs[2] = {kz, (N - kz) % N};
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const int v = (kzs[b] * N + kys[a]) * H + kx;
+                    if (!seen[v]) {
+                        seen[v] = 1;
+                        perm.push_back(v);
+                    }
+                }
+        }
+        t->perm.alloc(ctx, sizeof(int) * perm.size(), "frequency order");
+        hip_check(hipMemcpy(t->perm.ptr, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice),
+                  "upload frequency order");
+    }
     ctx->tables.push_back(std::move(t));
     return ctx->tables.back().get();
 }
@@ -266,6 +289,7 @@ SmacGeom conv_geom(const Conv &c) {
     g.YD = g.YH + 1;
     g.ZD = g.ZH + 1;
     g.N = 2 * c.spec->nb;
+    g.perm = (const int *)c.spec->perm.ptr;
     g.n_rows = c.n_rows;
     g.n_tiles = c.n_tiles;
     return g;

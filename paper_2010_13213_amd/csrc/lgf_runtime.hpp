@@ -49,6 +49,7 @@ struct SpecTable {
     int XH = 0, YH = 0, ZH = 0;
     int n_freq = 0;
     DeviceBuffer data;
+    DeviceBuffer perm;      // frequency order grouping (ky, kz) reflection partners
 };
 
 // Event pair around one kernel launch, resolved lazily.

@@ -33,6 +33,14 @@ namespace lgf {
 
 namespace {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (hardware id b lands
+// on XCD b mod 8); renumber them so that consecutive logical ids run on the
+// same XCD and share its L2.  A bijection on [0, n) for any n.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n) {
+    const int64_t xcd = b % 8, idx = b / 8, per = n / 8, rem = n % 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 __device__ __forceinline__ int pmod(int a, int m) {
     const int r = a % m;
     return r < 0 ? r + m : r;
@@ -56,7 +64,9 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     __shared__ cplx<R> kbuf[SY * SZ * KW];
     __shared__ cplx<R> frow[2][BX];
 
-    const int freq = (int)(wg % g.n_freq);
+    // consecutive work items share a group of four frequencies whose
+    // reflected offsets read the same spectra-table rows
+    const int freq = g.perm[wg % g.n_freq];
     const int tile = (int)(wg / g.n_freq);
     const int ty0 = tiles[tile].x, tz0 = tiles[tile].y;
     const int l = threadIdx.x;
@@ -205,14 +215,14 @@ template <int BX, int A, int TY, int TZ, typename R>
 __global__ void __launch_bounds__((BX / A) * TY * TZ)
     smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
                 const cplx<R> *__restrict__ Ktab, const int2 *__restrict__ rows, const int2 *__restrict__ tiles) {
-    smac_body<BX, A, TY, TZ, R>(g, Fhat, Uhat, Ktab, rows, tiles, blockIdx.x);
+    smac_body<BX, A, TY, TZ, R>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
 }
 
 // Several independent convolutions of one template in one grid: workgroup w
 // belongs to the job with wg_begin <= w < next job's wg_begin.
 template <int BX, int A, int TY, int TZ, typename R>
 __global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const SmacJob *__restrict__ jobs, int n_jobs) {
-    const int64_t w = blockIdx.x;
+    const int64_t w = xcd_order(blockIdx.x, gridDim.x);
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) / 2;

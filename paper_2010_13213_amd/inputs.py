@@ -18,6 +18,7 @@ Workloads (shapes follow the paper's vortex-ring experiments, Sec. 6-7):
                          perturbed core.
 * ``mstar``           -- dense 256^3 box at dx = R/64 over [-2R, 2R]^3,
                          16^3 blocks, x-vorticity of the ring.
+* ``colliding_rings`` -- three levels around two tilted, perturbed rings.
 * ``served_stream``   -- independent dense-cube requests with Gaussian blobs.
 """
 from dataclasses import dataclass, field
@@ -190,6 +191,113 @@ def two_level_ring(nb=16, dx0=1.0 / 32, k_coarse=8.0, k_fine=3.0, seed=3,
     lv1 = _level_from_fn(fine_blocks, nb, dx1, lo, fn, len(comps))
     return Problem(nb=nb, dx0=dx0, levels=[lv0, lv1], name="two_level_ring",
                    meta={"origin": lo})
+
+
+def _rot_y(deg):
+    a = np.deg2rad(deg)
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+
+
+def _ring_frames(sep=3.0, tilt=15.0):
+    """Two coaxial rings at z = -+sep/2, each tilted about y toward the other."""
+    return [(np.array([0.0, 0.0, -sep / 2]), _rot_y(-tilt)), (np.array([0.0, 0.0, sep / 2]), _rot_y(tilt))]
+
+
+def two_ring_distance(p, dRs, R=1.0):
+    """Distance to the nearer of the two (perturbed, tilted) ring cores."""
+    d = None
+    for (ctr, Q), dR in zip(_ring_frames(), dRs):
+        loc = (p - ctr) @ Q            # into the ring's own frame (axis z)
+        s, _ = ring_core_distance(loc, R, dR)
+        d = s if d is None else np.minimum(d, s)
+    return d
+
+
+def two_ring_vorticity(p, dRs, R=1.0, sigma=0.1):
+    """Sum of the two rings' azimuthal Gaussian-core vorticity (world frame)."""
+    w = 0.0
+    for (ctr, Q), dR in zip(_ring_frames(), dRs):
+        loc = (p - ctr) @ Q
+        wl = ring_vorticity(loc, R, sigma, dR)            # (3, ...) in the ring frame
+        w = w + np.einsum("ij,j...->i...", Q, wl)
+    return w
+
+
+def _blocks_within(nb, dx, lo, hi, dist_fn, cutoff, bound_fn=None, slack=0.0):
+    """Blocks of the box [lo, hi) with any cell centre within `cutoff`.
+
+    A block can only qualify if its centre is within cutoff plus the
+    centre-to-corner-cell distance, so candidates are prefiltered at block
+    centres.  If `bound_fn` differs from `dist_fn` by at most `slack`
+    everywhere, blocks it decides clearly are settled without `dist_fn`.
+    """
+    lo_b = np.floor(np.asarray(lo) / (nb * dx)).astype(int)
+    hi_b = np.ceil(np.asarray(hi) / (nb * dx)).astype(int)
+    axes = [np.arange(lo_b[a], hi_b[a]) for a in range(3)]
+    BZ, BY, BX = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    cand = np.stack([BX.ravel(), BY.ravel(), BZ.ravel()], axis=1)
+    ctr = (cand + 0.5) * nb * dx
+    reach = cutoff + slack + np.sqrt(3.0) * 0.5 * (nb - 1) * dx + 1e-12
+    cand = cand[(bound_fn or dist_fn)(ctr) <= reach]
+    r = (np.arange(nb) + 0.5) * dx
+    out = []
+    for b in cand:
+        X, Y, Z = np.meshgrid(b[0] * nb * dx + r, b[1] * nb * dx + r, b[2] * nb * dx + r, indexing="ij")
+        pts = np.stack([X, Y, Z], axis=-1)
+        if bound_fn is not None:
+            m = bound_fn(pts).min()
+            if m > cutoff + slack:
+                continue
+            if m <= cutoff - slack:
+                out.append((int(b[0]), int(b[1]), int(b[2])))
+                continue
+        if dist_fn(pts).min() <= cutoff:
+            out.append((int(b[0]), int(b[1]), int(b[2])))
+    return out
+
+
+def colliding_rings(nb=16, dx0=1.0 / 32, k_fine=4.0, k_coarse=8.0, seeds=(5, 6), components=(0, 1, 2),
+                    with_values=True):
+    """Three levels around two colliding rings (R = 1, sigma = 0.1 R).
+
+    Finest level (dx0/4): blocks within k_fine sigma of either perturbed core.
+    Level 1 (dx0/2): parents of the finest blocks dilated by one block.
+    Level 0 (dx0): blocks within k_coarse sigma, plus the parents of level 1
+    dilated by one block.  Block coordinates are on the lattice with origin 0.
+    """
+    dRs = [ring_radius_perturbation(sd) for sd in seeds]
+    dist = lambda p: two_ring_distance(p, dRs)
+    # the unperturbed distance differs from the perturbed one by at most
+    # max|dR| = 0.01 R (the core moves by dR within its plane)
+    bound = lambda p: two_ring_distance(p, [None, None])
+    ext = (np.array([-2.4, -2.4, -3.0]), np.array([2.4, 2.4, 3.0]))
+    fine = _blocks_within(nb, dx0 / 4, ext[0], ext[1], dist, k_fine * 0.1, bound, 0.0100001)
+
+    def parents_dilated(blocks):
+        par = {(b[0] // 2, b[1] // 2, b[2] // 2) for b in blocks}
+        out = set(par)
+        for b in par:
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dxb in (-1, 0, 1):
+                        out.add((b[0] + dxb, b[1] + dy, b[2] + dz))
+        return out
+    mid = sorted(parents_dilated(fine), key=lambda t: (t[2], t[1], t[0]))
+    coarse = set(_blocks_within(nb, dx0, ext[0], ext[1], dist, k_coarse * 0.1, bound, 0.0100001)) | \
+        parents_dilated(mid)
+    coarse = sorted(coarse, key=lambda t: (t[2], t[1], t[0]))
+    comps = list(components)
+    fn = lambda q: two_ring_vorticity(q, dRs)[comps]
+    levels = []
+    for k, blocks in enumerate([coarse, mid, fine]):
+        b = np.asarray(blocks, dtype=np.int32).reshape(-1, 3)
+        if with_values:
+            levels.append(_level_from_fn(b, nb, dx0 / 2 ** k, (0.0, 0.0, 0.0), fn, len(comps)))
+        else:
+            levels.append(Level(blocks=b, values=np.zeros((0, len(b), nb, nb, nb))))
+    return Problem(nb=nb, dx0=dx0, levels=levels, name="colliding_rings",
+                   meta={"origin": (0.0, 0.0, 0.0)})
 
 
 def mstar(components=(0,)):
