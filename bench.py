@@ -23,8 +23,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "target cells solved/s at 256^3, FP32+refine vs FP64; p50/p99 solve latency"
+MAC_KERNEL = "smac_kernel<16,8,16,8,double>"
+# HBM bytes of one launch of the MAC kernel, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE counters (scaled by a 1 GiB copy); valid only for the kernel
+# sources whose hash the summary records
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "smac_fp64_dense256_traffic.txt")
+MAC_SOURCES = ["lgf_smac.hip", "lgf_device.hpp", "lgf_kernels.hpp"]
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X FP64 vector FMA: 256 CU * 4 SIMD * 16 lanes * 2 * 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+
+
+def mac_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in MAC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_13213_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Counter-measured bytes per MAC launch, or None when the summary is
+    missing or was taken for other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l[1:].split(":", 1) for l in fh if l.startswith("@") and ":" in l)
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("mac_source_sha256") != mac_source_hash():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
 def _pct(xs, q):
@@ -68,9 +97,14 @@ def main():
                     help="which precision paths to time (profiling runs use one)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--print-mac-hash", action="store_true",
+                    help="print the hash of the MAC kernel sources and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration reference)")
     args = ap.parse_args()
+    if args.print_mac_hash:
+        print(mac_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the LGF path here runs on a single MI355X and has no "
               "multi-GPU implementation (requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -176,9 +210,10 @@ def main():
             "stages_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
             "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in r64["stages"].items()},
-        "roofline": {"bound": "alu", "kernel": "smac_kernel<16,8,16,16,double>",
+        "roofline": {"bound": "alu", "kernel": MAC_KERNEL,
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (HBM, counters)",
                      "algorithmic_flops_per_launch": flops_mac, "avg_launch_ms": smac_avg},
     }
     if not args.no_serving:

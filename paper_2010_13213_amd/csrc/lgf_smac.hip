@@ -26,6 +26,13 @@
 // Inside a row the Toeplitz product U[i] += K[x0 + i - j] F[j] reuses each
 // loaded kernel value across the lane's A targets, and the source row F is
 // read by all lanes from one LDS address (broadcast).
+//
+// Occupancy: the ring is (TY+1)(TZ+1)(2 bx - 1) complex values.  For bx = 16
+// in float64 a 16 x 8 tile needs 76 KB, so two workgroups share a CU's
+// 160 KB and one's barrier is covered by the other's arithmetic.  The LDS
+// reads of each step are issued two steps ahead of their use, which spreads
+// a row's reads over its arithmetic instead of queueing all of them behind
+// the barrier.
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -64,10 +71,11 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     __shared__ cplx<R> kbuf[SY * SZ * KW];
     __shared__ cplx<R> frow[2][BX];
 
-    // consecutive work items share a group of four frequencies whose
-    // reflected offsets read the same spectra-table rows
-    const int freq = g.perm[wg % g.n_freq];
-    const int tile = (int)(wg / g.n_freq);
+    // the tiles of one frequency are consecutive work items, and consecutive
+    // frequencies form groups of four whose reflected offsets read the same
+    // spectra-table rows: both then meet in the L2 of one XCD
+    const int freq = g.perm[wg / g.n_tiles];
+    const int tile = (int)(wg % g.n_tiles);
     const int ty0 = tiles[tile].x, tz0 = tiles[tile].y;
     const int l = threadIdx.x;
     const int seg = l % C::NSEG;
@@ -78,26 +86,28 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
 
     const size_t kper = (size_t)g.XD * g.YD * g.ZD;
     const cplx<R> *Ff = Fhat + (size_t)freq * g.n_slots;
-    // the four frequency rows reached by reflections: [flip ky][flip kz]
-    const cplx<R> *Kf[2][2];
-    {
-        const int H = g.N / 2 + 1;
-        const int kx = freq % H, ky = (freq / H) % g.N, kz = freq / (H * g.N);
-        const int kyr = (g.N - ky) % g.N, kzr = (g.N - kz) % g.N;
-        Kf[0][0] = Ktab + ((size_t)(kz * g.N + ky) * H + kx) * kper;
-        Kf[1][0] = Ktab + ((size_t)(kz * g.N + kyr) * H + kx) * kper;
-        Kf[0][1] = Ktab + ((size_t)(kzr * g.N + ky) * H + kx) * kper;
-        Kf[1][1] = Ktab + ((size_t)(kzr * g.N + kyr) * H + kx) * kper;
-    }
-    // kernel value at offset (dxi - (BX - 1), dy, dz), dxi in [0, KW)
-    auto kload = [&](int dy, int dz, int dxi) -> cplx<R> {
+    // frequency rows reached by reflections (flip ky, flip kz): element
+    // offsets into the table, selected arithmetically so that no array of
+    // pointers lands in private memory
+    const int H = g.N / 2 + 1;
+    const int kx = freq % H, ky = (freq / H) % g.N, kz = freq / (H * g.N);
+    const int kyr = (g.N - ky) % g.N, kzr = (g.N - kz) % g.N;
+    auto frow_off = [&](int fy, int fz) -> size_t {
+        return ((size_t)((fz ? kzr : kz) * g.N + (fy ? kyr : ky)) * H + kx) * kper;
+    };
+    // raw table value for offset (dxi - (BX - 1), dy, dz), dxi in [0, KW);
+    // a negative dx also needs the conjugate, applied by kfix
+    auto kraw = [&](int dy, int dz, int dxi) -> cplx<R> {
         const int dx = dxi - (BX - 1);
         const bool fx = dx < 0;
         const int fy = (dy < 0) != fx, fz = (dz < 0) != fx;
-        cplx<R> v = Kf[fy][fz][((size_t)abs(dy) * g.ZD + abs(dz)) * g.XD + abs(dx)];
-        if (fx) v.y = -v.y;
+        return Ktab[frow_off(fy, fz) + ((size_t)abs(dy) * g.ZD + abs(dz)) * g.XD + abs(dx)];
+    };
+    auto kfix = [&](cplx<R> v, int dxi) -> cplx<R> {
+        if (dxi < BX - 1) v.y = -v.y;
         return v;
     };
+    auto kload = [&](int dy, int dz, int dxi) -> cplx<R> { return kfix(kraw(dy, dz, dxi), dxi); };
     auto lds = [&](int dy, int dz, int dxi) -> int { return (pmod(dy, SY) * SZ + pmod(dz, SZ)) * KW + dxi; };
 
     cplx<R> acc[A];
@@ -148,30 +158,49 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     const int dxi = e % KW, q = e / KW;
                     const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
                     const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
-                    pre[p] = kload(dy, dz, dxi);
+                    pre[p] = kraw(dy, dz, dxi);
                 }
             }
             if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * BX + l];
         }
 
         // compute: U[i] += K[x0 + i - j] * F[j], with a sliding register
-        // window kw[i] = K[x0 + i - j] that gains one LDS value per step j
+        // window kw[i] = K[x0 + i - j] that gains one LDS value per step j;
+        // the LDS reads of step j + 2 are issued at step j, so the reads of
+        // all waves spread over the row instead of bunching after the barrier
         {
             const cplx<R> *krow = &kbuf[lds(ty - sy, tz - sz, 0)] + x0 + BX - 1;
-            const cplx<R> *fr = frow[buf];
+            // a per-lane base register for the broadcast F row, so that its
+            // sixteen reads use immediate offsets from one address
+            int vzero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+            const cplx<R> *fr = frow[buf] + vzero;
             cplx<R> kw[A];
 #pragma unroll
             for (int i = 0; i < A; ++i) kw[i] = krow[i];
+            cplx<R> fj = fr[0];
+            cplx<R> kn1 = krow[-1], fn1 = fr[1];
+            cplx<R> kn2 = kn1, fn2 = fn1;
 #pragma unroll
             for (int j = 0; j < BX; ++j) {
-                const cplx<R> fj = fr[j];
+                if (j + 2 < BX) {
+                    kn2 = krow[-(j + 2)];
+                    fn2 = fr[j + 2];
+                }
 #pragma unroll
                 for (int i = 0; i < A; ++i) acc[i] = cmac(acc[i], kw[i], fj);
                 if (j + 1 < BX) {
 #pragma unroll
                     for (int i = A - 1; i >= 1; --i) kw[i] = kw[i - 1];
-                    kw[0] = krow[-(j + 1)];
+                    kw[0] = kn1;
+                    fj = fn1;
+                    kn1 = kn2;
+                    fn1 = fn2;
                 }
+                // keep each step's products here (IR passes would otherwise
+                // sink them below the prefetch stores)
+#pragma unroll
+                for (int i = 0; i < A; ++i) asm volatile("" : "+v"(acc[i].x), "+v"(acc[i].y)::"memory");
             }
         }
 
@@ -184,7 +213,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     const int dxi = e % KW, q = e / KW;
                     const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
                     const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
-                    kbuf[lds(dy, dz, dxi)] = pre[p];
+                    kbuf[lds(dy, dz, dxi)] = kfix(pre[p], dxi);
                 }
             }
             if (l < BX) frow[buf ^ 1][l] = fpre;
@@ -262,8 +291,8 @@ hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs,
         return fp32 ? launch_batch_cfg<8, 8, 8, 8, float>(jobs, n_jobs, total_wg, s)
                     : launch_batch_cfg<8, 8, 8, 8, double>(jobs, n_jobs, total_wg, s);
     case 16:
-        return fp32 ? launch_batch_cfg<16, 8, 16, 16, float>(jobs, n_jobs, total_wg, s)
-                    : launch_batch_cfg<16, 8, 16, 16, double>(jobs, n_jobs, total_wg, s);
+        return fp32 ? launch_batch_cfg<16, 8, 16, 8, float>(jobs, n_jobs, total_wg, s)
+                    : launch_batch_cfg<16, 8, 16, 8, double>(jobs, n_jobs, total_wg, s);
     case 32:
         return fp32 ? launch_batch_cfg<32, 16, 16, 8, float>(jobs, n_jobs, total_wg, s)
                     : launch_batch_cfg<32, 16, 16, 8, double>(jobs, n_jobs, total_wg, s);
@@ -272,8 +301,8 @@ hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs,
     }
 }
 
-int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
-int smac_tile_z(int bx) { return bx == 8 ? 8 : (bx == 16 ? 16 : 8); }
+int smac_tile_y(int bx) { return bx == 8 ? 8 : (bx == 16 ? 16 : 16); }
+int smac_tile_z(int bx) { return bx == 8 ? 8 : (bx == 16 ? 8 : 8); }
 
 hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
                        const int2 *rows, const int2 *tiles, hipStream_t s) {
@@ -282,8 +311,8 @@ hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uha
         return fp32 ? launch_cfg<8, 8, 8, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
                     : launch_cfg<8, 8, 8, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
     case 16:
-        return fp32 ? launch_cfg<16, 8, 16, 16, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
-                    : launch_cfg<16, 8, 16, 16, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
+        return fp32 ? launch_cfg<16, 8, 16, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
+                    : launch_cfg<16, 8, 16, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
     case 32:
         return fp32 ? launch_cfg<32, 16, 16, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
                     : launch_cfg<32, 16, 16, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
