@@ -45,6 +45,13 @@ hipError_t block_fft_forward_batch(int nb, bool fp32, const FftJob *jobs, int n_
 hipError_t block_fft_inverse_batch(int nb, bool fp32, const FftJob *jobs, int n_jobs, int total_blocks, hipStream_t s);
 
 // ---- spectral multiply-accumulate (lgf_smac.hip) ----
+// A source row of one convolution: (y, z) in blocks of the padded box and
+// the mask of its occupied x positions (bit x set: a source block sits at x).
+struct SmacRow {
+    int y, z;
+    unsigned mask;
+    int pad;
+};
 struct SmacGeom {
     int bx;                 // row length template (8, 16 or 32)
     int ey, ez;             // padded box extent in blocks along y, z (slots)
@@ -62,17 +69,19 @@ struct SmacJob {
     const void *F;
     void *U;
     const void *K;
-    const int2 *rows;
+    const SmacRow *rows;
     const int2 *tiles;
     int64_t wg_begin;       // first workgroup of this job in the batched grid
 };
-hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s);
+hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs, int64_t total_wg,
+                             hipStream_t s);
 int smac_tile_y(int bx);
 int smac_tile_z(int bx);
 // Uhat[omega][t] = sum_s K[omega][t - s] * Fhat[omega][s] over every source row
-// and every target slot of each tile.
-hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
-                       const int2 *rows, const int2 *tiles, hipStream_t s);
+// and every target slot of each tile; source positions outside a row's mask
+// are skipped when `sparse` (their Fhat must be zero either way).
+hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
+                       const SmacRow *rows, const int2 *tiles, hipStream_t s);
 
 // ---- composite-grid kernels (lgf_composite.hip) ----
 // dst block b = src block b with the octants flagged in cover[b] zeroed.
@@ -100,16 +109,16 @@ struct RefGeom {
     double dx;
     int lo[3], dim[3];      // dense block map of the target set T: T index or -1
 };
-// depth (L1 distance to the complement of T, capped at 4) of every cell of
+// depth (L1 distance to the complement of T, capped at 3) of every cell of
 // the listed shell blocks
 hipError_t refine_depth(int nb, const RefGeom &g, const int *map, const int *shblk, unsigned char *depth, int n_sh,
                         hipStream_t s);
-// rho = L_dx e^ on every T block (see lgf_refine.hip)
+// On every T block: w = u~ where depth >= 2 else 0; dst (+)= w; rho = src -
+// L_dx w split into rin (depth >= 3, per T block) and rcut (depth <= 2, per
+// shell block).  See lgf_refine.hip.
 hipError_t refine_residual(int nb, const RefGeom &g, const int *map, const int *tblk, const int *t2sh,
-                           const unsigned char *depth, const double *ut, const double *ush, const double *src,
-                           const int64_t *gofs, double *rho, int n_t, hipStream_t s);
-// dst (+)= exact values on shell blocks, float32 values on interior blocks
-hipError_t refine_assemble(int nb, const int *t2sh, const double *ut, const double *ush, const int64_t *dofs,
-                           double *dst, int accumulate, int n_t, hipStream_t s);
+                           const unsigned char *depth, const double *ut, const double *src, const int64_t *gofs,
+                           const int64_t *dofs, double *dst, int accumulate, double *rin, double *rcut, int n_t,
+                           hipStream_t s);
 
 }  // namespace lgf

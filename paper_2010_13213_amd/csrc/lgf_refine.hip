@@ -1,25 +1,29 @@
 // Mixed-precision refinement of one blockwise LGF convolution (gfx950).
 //
-// u = L_dx^-1 g on the target set T is first computed with float32 spectra,
-// FFTs and products (u~, relative error ~1e-7).  The error e = u - u~ is not
-// recoverable from a residual on T alone: its discrete-harmonic part is
-// fixed by values on the boundary of T.  So exact float64 values are taken
-// on the shell blocks of T (blocks with any of their 26 neighbours outside
-// T), and with depth(c) = L1 distance from cell c to the complement of T the
-// function
+// Wanted: u = L_dx^-1 g on the target set T (g: the source, on its own
+// blocks).  The lattice Green's function inverts L_dx exactly on compactly
+// supported functions, so for ANY w supported on T
 //
-//     e^ = e on cells of depth >= 3,  0 elsewhere
+//     L_dx^-1 g = w + L_dx^-1 (g - L_dx w).
 //
-// is compactly supported, hence e^ = L_dx^-1 (L_dx e^) exactly (the lattice
-// Green's function inverts L on compactly supported functions).  L_dx e^ is
-// known in float64:
-//     depth >= 4:  g - L_dx u~
-//     depth == 3:  g - L_dx u~ - dx^-2 sum_{nbr depth 2} e(nbr)
-//     depth == 2:  dx^-2 sum_{nbr depth 3} e(nbr)
-//     depth <= 1:  0
-// with e = u_exact - u~ on depths 2 and 3 (shell blocks).  One more float32
-// convolution of this residual gives e^ with error ~1e-7 |e^| ~ 1e-14 |u|.
-// The result is u_exact on shell blocks and u~ + e^ on the interior blocks.
+// Take u~ = a float32 solve on T (relative error ~1e-7) and, with depth(c)
+// the L1 distance from cell c to the complement of T,
+//
+//     w = u~ on cells of depth >= 2,   0 elsewhere.
+//
+// rho = g - L_dx w is then small (float32 noise of u~) on cells of depth >= 3,
+// where every stencil point sees w = u~; on depths 1 and 2 (the cut, which
+// lies in the shell blocks of T) and on source blocks outside T it is of the
+// size of g and u.  So
+//
+//     u = w + L_dx^-1 (rho on the cut + g outside T)      float64 convolution
+//           + L_dx^-1 (rho on depth >= 3)                  float32 convolution
+//
+// The first convolution has only the cut and the outside sources as
+// sources (a thin set, handled by the MAC's sparse rows); the second one's
+// source is ~1e-7 of g, so float32 leaves ~1e-14 relative error.  Float64 is
+// used for the Green's function table, the residual, the cut convolution and
+// the accumulation.
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -39,6 +43,8 @@ struct Lookup {
     }
 };
 
+// depth of every cell of the listed shell blocks: L1 distance to the
+// complement of T, capped at 3
 template <int NB>
 __global__ void __launch_bounds__(256) depth_kernel(RefGeom g, const int *__restrict__ map,
                                                     const int *__restrict__ shblk, unsigned char *__restrict__ depth) {
@@ -47,12 +53,12 @@ __global__ void __launch_bounds__(256) depth_kernel(RefGeom g, const int *__rest
     const int Bx = shblk[3 * b], By = shblk[3 * b + 1], Bz = shblk[3 * b + 2];
     for (int i = threadIdx.x; i < NB * NB * NB; i += 256) {
         const int x = Bx * NB + i % NB, y = By * NB + (i / NB) % NB, z = Bz * NB + i / (NB * NB);
-        int d = 4;
-        for (int ox = -3; ox <= 3; ++ox)
-            for (int oy = -3; oy <= 3; ++oy)
-                for (int oz = -3; oz <= 3; ++oz) {
+        int d = 3;
+        for (int ox = -2; ox <= 2; ++ox)
+            for (int oy = -2; oy <= 2; ++oy)
+                for (int oz = -2; oz <= 2; ++oz) {
                     const int l1 = abs(ox) + abs(oy) + abs(oz);
-                    if (l1 == 0 || l1 > 3 || l1 >= d) continue;
+                    if (l1 == 0 || l1 >= d) continue;
                     if (L.tidx(fdiv_d(x + ox, NB), fdiv_d(y + oy, NB), fdiv_d(z + oz, NB)) < 0) d = l1;
                 }
         depth[(size_t)b * NB * NB * NB + i] = (unsigned char)d;
@@ -63,69 +69,45 @@ template <int NB>
 __global__ void __launch_bounds__(256) residual_kernel(RefGeom g, const int *__restrict__ map,
                                                        const int *__restrict__ tblk, const int *__restrict__ t2sh,
                                                        const unsigned char *__restrict__ depth,
-                                                       const double *__restrict__ ut, const double *__restrict__ ush,
-                                                       const double *__restrict__ src,
-                                                       const int64_t *__restrict__ gofs, double *__restrict__ rho) {
+                                                       const double *__restrict__ ut, const double *__restrict__ src,
+                                                       const int64_t *__restrict__ gofs,
+                                                       const int64_t *__restrict__ dofs, double *__restrict__ dst,
+                                                       int accumulate, double *__restrict__ rin,
+                                                       double *__restrict__ rcut) {
     constexpr int NB3 = NB * NB * NB;
     const int b = blockIdx.x;
     Lookup L{g, map};
     const int Bx = tblk[3 * b], By = tblk[3 * b + 1], Bz = tblk[3 * b + 2];
+    const int sh_b = t2sh[b];
     const double idx2 = 1.0 / (g.dx * g.dx);
-    // (T index, local cell) of a lattice cell; T index -1 outside T
-    auto locate = [&](int x, int y, int z, int &li) -> int {
+    // w at a lattice cell: u~ where depth >= 2, else 0 (also outside T)
+    auto w_at = [&](int x, int y, int z) -> double {
         const int bx = fdiv_d(x, NB), by = fdiv_d(y, NB), bz = fdiv_d(z, NB);
-        li = ((z - bz * NB) * NB + (y - by * NB)) * NB + (x - bx * NB);
-        return L.tidx(bx, by, bz);
-    };
-    auto depth_of = [&](int t, int li) -> int {
-        if (t < 0) return 0;
+        const int li = ((z - bz * NB) * NB + (y - by * NB)) * NB + (x - bx * NB);
+        const int t = L.tidx(bx, by, bz);
+        if (t < 0) return 0.0;
         const int sh = t2sh[t];
-        return sh < 0 ? 4 : depth[(size_t)sh * NB3 + li];
+        if (sh >= 0 && depth[(size_t)sh * NB3 + li] < 2) return 0.0;
+        return ut[(size_t)t * NB3 + li];
     };
-    auto err = [&](int t, int li) -> double {   // u_exact - u~ (shell cells only)
-        return ush[(size_t)t2sh[t] * NB3 + li] - ut[(size_t)t * NB3 + li];
-    };
-    const int nbr[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
     for (int i = threadIdx.x; i < NB3; i += 256) {
         const int x = Bx * NB + i % NB, y = By * NB + (i / NB) % NB, z = Bz * NB + i / (NB * NB);
-        const int d = depth_of(b, i);
-        double r = 0.0;
-        if (d == 2) {
-            double acc = 0.0;
-            for (int q = 0; q < 6; ++q) {
-                int li;
-                const int t = locate(x + nbr[q][0], y + nbr[q][1], z + nbr[q][2], li);
-                if (depth_of(t, li) == 3) acc += err(t, li);
-            }
-            r = idx2 * acc;
-        } else if (d >= 3) {
-            double lap = -6.0 * ut[(size_t)b * NB3 + i];
-            double e2 = 0.0;
-            for (int q = 0; q < 6; ++q) {
-                int li;
-                const int t = locate(x + nbr[q][0], y + nbr[q][1], z + nbr[q][2], li);
-                lap += ut[(size_t)t * NB3 + li];
-                if (d == 3 && depth_of(t, li) == 2) e2 += err(t, li);
-            }
-            const double gv = gofs[b] >= 0 ? src[gofs[b] + i] : 0.0;
-            r = gv - idx2 * lap - idx2 * e2;
+        const int d = sh_b >= 0 ? depth[(size_t)sh_b * NB3 + i] : 3;
+        const double wc = d >= 2 ? ut[(size_t)b * NB3 + i] : 0.0;
+        const double lap = w_at(x + 1, y, z) + w_at(x - 1, y, z) + w_at(x, y + 1, z) + w_at(x, y - 1, z) +
+                           w_at(x, y, z + 1) + w_at(x, y, z - 1) - 6.0 * wc;
+        const double gv = gofs[b] >= 0 ? src[gofs[b] + i] : 0.0;
+        const double r = gv - idx2 * lap;
+        double *dp = dst + dofs[b] + i;
+        *dp = accumulate ? *dp + wc : wc;
+        if (d <= 2) {
+            rcut[(size_t)sh_b * NB3 + i] = r;
+            rin[(size_t)b * NB3 + i] = 0.0;
+        } else {
+            rin[(size_t)b * NB3 + i] = r;
+            if (sh_b >= 0) rcut[(size_t)sh_b * NB3 + i] = 0.0;
         }
-        rho[(size_t)b * NB3 + i] = r;
     }
-}
-
-// dst block (per T block b) (+)= ush (shell) or ut (interior)
-template <int NB>
-__global__ void __launch_bounds__(256) assemble_kernel(const int *__restrict__ t2sh, const double *__restrict__ ut,
-                                                       const double *__restrict__ ush,
-                                                       const int64_t *__restrict__ dofs, double *__restrict__ dst,
-                                                       int accumulate) {
-    constexpr int NB3 = NB * NB * NB;
-    const int b = blockIdx.x;
-    const int sh = t2sh[b];
-    const double *s = sh >= 0 ? ush + (size_t)sh * NB3 : ut + (size_t)b * NB3;
-    double *d = dst + dofs[b];
-    for (int i = threadIdx.x; i < NB3; i += 256) d[i] = accumulate ? d[i] + s[i] : s[i];
 }
 
 }  // namespace
@@ -143,27 +125,16 @@ hipError_t refine_depth(int nb, const RefGeom &g, const int *map, const int *shb
 }
 
 hipError_t refine_residual(int nb, const RefGeom &g, const int *map, const int *tblk, const int *t2sh,
-                           const unsigned char *depth, const double *ut, const double *ush, const double *src,
-                           const int64_t *gofs, double *rho, int n_t, hipStream_t s) {
+                           const unsigned char *depth, const double *ut, const double *src, const int64_t *gofs,
+                           const int64_t *dofs, double *dst, int accumulate, double *rin, double *rcut, int n_t,
+                           hipStream_t s) {
     if (n_t <= 0) return hipSuccess;
     if (nb == 16)
-        hipLaunchKernelGGL(residual_kernel<16>, dim3(n_t), dim3(256), 0, s, g, map, tblk, t2sh, depth, ut, ush, src,
-                           gofs, rho);
+        hipLaunchKernelGGL(residual_kernel<16>, dim3(n_t), dim3(256), 0, s, g, map, tblk, t2sh, depth, ut, src, gofs,
+                           dofs, dst, accumulate, rin, rcut);
     else if (nb == 8)
-        hipLaunchKernelGGL(residual_kernel<8>, dim3(n_t), dim3(256), 0, s, g, map, tblk, t2sh, depth, ut, ush, src,
-                           gofs, rho);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-hipError_t refine_assemble(int nb, const int *t2sh, const double *ut, const double *ush, const int64_t *dofs,
-                           double *dst, int accumulate, int n_t, hipStream_t s) {
-    if (n_t <= 0) return hipSuccess;
-    if (nb == 16)
-        hipLaunchKernelGGL(assemble_kernel<16>, dim3(n_t), dim3(256), 0, s, t2sh, ut, ush, dofs, dst, accumulate);
-    else if (nb == 8)
-        hipLaunchKernelGGL(assemble_kernel<8>, dim3(n_t), dim3(256), 0, s, t2sh, ut, ush, dofs, dst, accumulate);
+        hipLaunchKernelGGL(residual_kernel<8>, dim3(n_t), dim3(256), 0, s, g, map, tblk, t2sh, depth, ut, src, gofs,
+                           dofs, dst, accumulate, rin, rcut);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

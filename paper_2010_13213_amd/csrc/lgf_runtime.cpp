@@ -227,12 +227,12 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     };
     std::vector<int> s_slot, t_slot;
     std::vector<int64_t> s_off, t_off;
-    std::set<std::pair<int, int>> rowset;
+    std::map<std::pair<int, int>, unsigned> rowmask;
     std::set<std::pair<int, int>> tileset;
     for (const auto &b : src) {
         s_slot.push_back(slot_of(b));
         s_off.push_back(b.off);
-        rowset.insert({b.ijk[2] - lo[2], b.ijk[1] - lo[1]});
+        rowmask[{b.ijk[2] - lo[2], b.ijk[1] - lo[1]}] |= 1u << (b.ijk[0] - lo[0]);
     }
     for (const auto &b : tgt) {
         t_slot.push_back(slot_of(b));
@@ -241,14 +241,14 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     }
     // serpentine row order: z ascending, y alternating direction per z group
     std::map<int, std::vector<int>> byz;
-    for (auto &r : rowset) byz[r.first].push_back(r.second);
-    std::vector<int2> rows;
+    for (auto &r : rowmask) byz[r.first.first].push_back(r.first.second);
+    std::vector<SmacRow> rows;
     int gi = 0;
     for (auto &kv : byz) {
         auto ys = kv.second;
         std::sort(ys.begin(), ys.end());
         if (gi & 1) std::reverse(ys.begin(), ys.end());
-        for (int y : ys) rows.push_back(make_int2(y, kv.first));
+        for (int y : ys) rows.push_back(SmacRow{y, kv.first, rowmask[{kv.first, y}], 0});
         ++gi;
     }
     std::vector<int2> tiles;
@@ -257,12 +257,15 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     c.n_tgt = (int)tgt.size();
     c.n_rows = (int)rows.size();
     c.n_tiles = (int)tiles.size();
+    // skipping empty source positions costs a branch per position: worth it
+    // once more than a few percent of the rows' positions are empty
+    c.sparse = (int64_t)src.size() * 10 < (int64_t)rows.size() * bx * 9;
     c.spec = get_spectra(ctx, nb, fp32, bx - 1, c.ey - 1, c.ez - 1);
     c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
     c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
     c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
     c.d_tgt_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, t_off.size()), "offsets");
-    c.d_rows.alloc(ctx, sizeof(int2) * std::max<size_t>(1, rows.size()), "rows");
+    c.d_rows.alloc(ctx, sizeof(SmacRow) * std::max<size_t>(1, rows.size()), "rows");
     c.d_tiles.alloc(ctx, sizeof(int2) * std::max<size_t>(1, tiles.size()), "tiles");
     auto up = [&](DeviceBuffer &d, const void *h, size_t n) {
         if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
@@ -271,7 +274,7 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     up(c.d_tgt_slot, t_slot.data(), sizeof(int) * t_slot.size());
     up(c.d_src_off, s_off.data(), sizeof(int64_t) * s_off.size());
     up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
-    up(c.d_rows, rows.data(), sizeof(int2) * rows.size());
+    up(c.d_rows, rows.data(), sizeof(SmacRow) * rows.size());
     up(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size());
 }
 
@@ -336,12 +339,25 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
     op->refined = true;
     op->n_t = (int)tgt.size();
     op->n_sh = n_sh;
+    // float64 sources: the shell blocks (cut residual), then the source
+    // blocks outside T (copied from the source field at solve time)
+    std::vector<Blk> cut = sh;
+    std::vector<int64_t> out_src, out_dst;
+    for (const auto &b : src)
+        if (!tix.count(Key(b.ijk[0], b.ijk[1], b.ijk[2]))) {
+            Blk q = b;
+            q.off = (int64_t)(n_sh + (int)out_src.size()) * nb3;
+            out_src.push_back(b.off);
+            out_dst.push_back(q.off);
+            cut.push_back(q);
+        }
+    op->n_out = (int)out_src.size();
     op->c32 = std::make_unique<Conv>();
     build_conv(plan, *op->c32, src, tcomp, true);
     op->c64 = std::make_unique<Conv>();
-    build_conv(plan, *op->c64, src, sh, false);
+    build_conv(plan, *op->c64, cut, tgt, false);
     op->ccorr = std::make_unique<Conv>();
-    build_conv(plan, *op->ccorr, tcomp, interior, true);
+    build_conv(plan, *op->ccorr, tcomp, tgt, true);
     for (const Conv *c : {op->c32.get(), op->c64.get(), op->ccorr.get()}) plan->convs_view.push_back(c);
     // dense map of T over its bounding box
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -382,6 +398,8 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
     up(op->d_t2sh, t2sh.data(), sizeof(int) * t2sh.size(), "shell index");
     up(op->d_gofs, gofs.data(), sizeof(int64_t) * gofs.size(), "source offsets");
     up(op->d_dofs, dofs.data(), sizeof(int64_t) * dofs.size(), "target offsets");
+    up(op->d_out_src, out_src.data(), sizeof(int64_t) * out_src.size(), "outside sources");
+    up(op->d_out_dst, out_dst.data(), sizeof(int64_t) * out_dst.size(), "outside sources");
     DeviceBuffer d_shblk;
     up(d_shblk, shblk.data(), sizeof(int) * shblk.size(), "shell blocks");
     op->d_depth.alloc(ctx, (size_t)std::max(1, n_sh) * nb3, "shell depth");
@@ -395,17 +413,18 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
 void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
                    hipStream_t s) {
     const int nb = plan->nb;
-    double *ut = (double *)plan->ws_ut.ptr, *ush = (double *)plan->ws_ush.ptr, *rho = (double *)plan->ws_rho.ptr;
+    double *ut = (double *)plan->ws_ut.ptr, *cut = (double *)plan->ws_ush.ptr, *rin = (double *)plan->ws_rho.ptr;
     RefGeom g = op.geom;
     g.dx = dx;
     StageTimer t(plan->ctx, 3, s);
     hip_check(refine_residual(nb, g, (const int *)op.d_map.ptr, (const int *)op.d_tblk.ptr, (const int *)op.d_t2sh.ptr,
-                              (const unsigned char *)op.d_depth.ptr, ut, ush, src, (const int64_t *)op.d_gofs.ptr, rho,
-                              op.n_t, s),
+                              (const unsigned char *)op.d_depth.ptr, ut, src, (const int64_t *)op.d_gofs.ptr,
+                              (const int64_t *)op.d_dofs.ptr, dst, accumulate, rin, cut, op.n_t, s),
               "refinement residual");
-    hip_check(refine_assemble(nb, (const int *)op.d_t2sh.ptr, ut, ush, (const int64_t *)op.d_dofs.ptr, dst,
-                              accumulate, op.n_t, s),
-              "refinement assemble");
+    if (op.n_out > 0)
+        hip_check(copy_blocks(nb, src, cut, (const int64_t *)op.d_out_src.ptr, (const int64_t *)op.d_out_dst.ptr,
+                              op.n_out, s),
+                  "outside sources");
 }
 
 void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
@@ -415,23 +434,23 @@ void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, do
         return;
     }
     run_conv(plan, *op.c32, src, (double *)plan->ws_ut.ptr, dx, 0, s);
-    run_conv(plan, *op.c64, src, (double *)plan->ws_ush.ptr, dx, 0, s);
     refine_middle(plan, op, src, dst, dx, accumulate, s);
+    run_conv(plan, *op.c64, (const double *)plan->ws_ush.ptr, dst, dx, 1, s);
     run_conv(plan, *op.ccorr, (const double *)plan->ws_rho.ptr, dst, dx, 1, s);
 }
 
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {
-    int64_t nt = 0, nsh = 0;
+    int64_t nt = 0, ncut = 0;
     for (const ConvOp *o : ops)
         if (o && o->refined) {
             nt = std::max<int64_t>(nt, o->n_t);
-            nsh = std::max<int64_t>(nsh, o->n_sh);
+            ncut = std::max<int64_t>(ncut, (int64_t)o->n_sh + o->n_out);
         }
     if (nt == 0) return;
     const int64_t nb3 = (int64_t)plan->nb * plan->nb * plan->nb;
     plan->ws_ut.alloc(plan->ctx, sizeof(double) * nt * nb3, "u float32 pass");
     plan->ws_rho.alloc(plan->ctx, sizeof(double) * nt * nb3, "refinement residual");
-    plan->ws_ush.alloc(plan->ctx, sizeof(double) * std::max<int64_t>(1, nsh) * nb3, "shell values");
+    plan->ws_ush.alloc(plan->ctx, sizeof(double) * std::max<int64_t>(1, ncut) * nb3, "cut residual");
 }
 
 // Spectral workspace large enough for every convolution of the plan.
@@ -465,8 +484,8 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, dou
     {
         StageTimer t(plan->ctx, 1, s);
         const SmacGeom g = conv_geom(c);
-        hip_check(smac_launch(g, c.fp32, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
-                              (const int2 *)c.d_rows.ptr, (const int2 *)c.d_tiles.ptr, s),
+        hip_check(smac_launch(g, c.fp32, c.sparse, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
+                              (const SmacRow *)c.d_rows.ptr, (const int2 *)c.d_tiles.ptr, s),
                   "spectral MAC");
     }
     {

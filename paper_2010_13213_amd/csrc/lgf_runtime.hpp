@@ -96,6 +96,7 @@ struct Conv {
     int lo[3] = {0, 0, 0};
     int64_t n_slots = 0;
     bool fp32 = false;
+    bool sparse = false;    // source rows have holes: the MAC skips empty positions
     int n_src = 0, n_tgt = 0, n_rows = 0, n_tiles = 0;
     SpecTable *spec = nullptr;
     DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off, d_rows, d_tiles;
@@ -105,11 +106,14 @@ struct Conv {
 // float64 convolution, or the float32 + float64-refinement sequence.
 struct ConvOp {
     bool refined = false;
-    std::unique_ptr<Conv> c64;                  // exact: all targets, or the shell blocks
-    std::unique_ptr<Conv> c32, ccorr;           // refined: u~ on T, correction onto the interior
-    int n_t = 0, n_sh = 0;
+    // plain: sources -> targets.  refined: the cut (depth <= 2 cells of the
+    // shell blocks) and the sources outside T -> targets, in float64
+    std::unique_ptr<Conv> c64;
+    // refined: u~ (sources -> T) and the float32 residual (T -> targets)
+    std::unique_ptr<Conv> c32, ccorr;
+    int n_t = 0, n_sh = 0, n_out = 0;
     RefGeom geom{};
-    DeviceBuffer d_map, d_tblk, d_t2sh, d_depth, d_gofs, d_dofs;
+    DeviceBuffer d_map, d_tblk, d_t2sh, d_depth, d_gofs, d_dofs, d_out_src, d_out_dst;
 };
 
 // Per-level schedule data of a composite plan.

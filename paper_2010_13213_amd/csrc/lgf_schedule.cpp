@@ -384,29 +384,32 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
         ring_mark(ctx, slot, s);
     }
     for (int fp = 0; fp < 2; ++fp)
-        for (int bx : {8, 16, 32}) {
-            std::vector<SmacJob> sj;
-            int64_t total = 0;
-            for (const ConvCall &k : calls) {
-                if ((int)k.c->fp32 != fp || k.c->bx != bx || k.c->n_rows == 0 || k.c->n_tiles == 0) continue;
-                SmacJob j{};
-                j.g = conv_geom(*k.c);
-                j.F = k.p->Fhat.ptr;
-                j.U = k.p->Uhat.ptr;
-                j.K = k.c->spec->data.ptr;
-                j.rows = (const int2 *)k.c->d_rows.ptr;
-                j.tiles = (const int2 *)k.c->d_tiles.ptr;
-                j.wg_begin = total;
-                total += (int64_t)j.g.n_freq * j.g.n_tiles;
-                sj.push_back(j);
+        for (int bx : {8, 16, 32})
+            for (int sp = 0; sp < 2; ++sp) {
+                std::vector<SmacJob> sj;
+                int64_t total = 0;
+                for (const ConvCall &k : calls) {
+                    if ((int)k.c->fp32 != fp || k.c->bx != bx || (int)k.c->sparse != sp || k.c->n_rows == 0 ||
+                        k.c->n_tiles == 0)
+                        continue;
+                    SmacJob j{};
+                    j.g = conv_geom(*k.c);
+                    j.F = k.p->Fhat.ptr;
+                    j.U = k.p->Uhat.ptr;
+                    j.K = k.c->spec->data.ptr;
+                    j.rows = (const SmacRow *)k.c->d_rows.ptr;
+                    j.tiles = (const int2 *)k.c->d_tiles.ptr;
+                    j.wg_begin = total;
+                    total += (int64_t)j.g.n_freq * j.g.n_tiles;
+                    sj.push_back(j);
+                }
+                if (sj.empty()) continue;
+                StageTimer t(ctx, 1, s);
+                int slot = 0;
+                hip_check(smac_batch_launch(bx, fp == 1, sp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(), total, s),
+                          "batched spectral MAC");
+                ring_mark(ctx, slot, s);
             }
-            if (sj.empty()) continue;
-            StageTimer t(ctx, 1, s);
-            int slot = 0;
-            hip_check(smac_batch_launch(bx, fp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(), total, s),
-                      "batched spectral MAC");
-            ring_mark(ctx, slot, s);
-        }
     for (int fp = 0; fp < 2; ++fp) {
         std::vector<FftJob> fj;
         int total = 0;
@@ -457,7 +460,9 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         int max_nc = 0;
         for (int i : ids) max_nc = std::max(max_nc, plans[i]->nc);
         for (int comp = 0; comp < max_nc; ++comp) {
-            std::vector<ConvCall> a1, a2, c;
+            // a: plain solves and the float32 pass of refined ones; then the
+            // refined ones' residual, cut (b1) and float32 residual (b2) passes
+            std::vector<ConvCall> a, b1, b2;
             for (int i : ids) {
                 lgf_plan *p = plans[i];
                 if (comp >= p->nc) continue;
@@ -465,22 +470,22 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
                 double *dst = u[i] + (size_t)comp * p->comp_len;
                 const ConvOp &op = *p->op0;
                 if (!op.refined) {
-                    a1.push_back(ConvCall{p, op.c64.get(), src, dst, p->dx0, 0});
+                    a.push_back(ConvCall{p, op.c64.get(), src, dst, p->dx0, 0});
                 } else {
-                    a1.push_back(ConvCall{p, op.c32.get(), src, (double *)p->ws_ut.ptr, p->dx0, 0});
-                    a2.push_back(ConvCall{p, op.c64.get(), src, (double *)p->ws_ush.ptr, p->dx0, 0});
-                    c.push_back(ConvCall{p, op.ccorr.get(), (const double *)p->ws_rho.ptr, dst, p->dx0, 1});
+                    a.push_back(ConvCall{p, op.c32.get(), src, (double *)p->ws_ut.ptr, p->dx0, 0});
+                    b1.push_back(ConvCall{p, op.c64.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
+                    b2.push_back(ConvCall{p, op.ccorr.get(), (const double *)p->ws_rho.ptr, dst, p->dx0, 1});
                 }
             }
-            run_conv_batch(ctx, a1, s);
-            run_conv_batch(ctx, a2, s);
+            run_conv_batch(ctx, a, s);
             for (int i : ids) {
                 lgf_plan *p = plans[i];
                 if (comp >= p->nc || !p->op0->refined) continue;
                 refine_middle(p, *p->op0, f[i] + (size_t)comp * p->comp_len, u[i] + (size_t)comp * p->comp_len,
                               p->dx0, 0, s);
             }
-            run_conv_batch(ctx, c, s);
+            run_conv_batch(ctx, b1, s);
+            run_conv_batch(ctx, b2, s);
         }
     }
     if (reps) {

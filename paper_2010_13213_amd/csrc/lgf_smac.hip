@@ -33,6 +33,8 @@
 // reads of each step are issued two steps ahead of their use, which spreads
 // a row's reads over its arithmetic instead of queueing all of them behind
 // the barrier.
+#include <type_traits>
+
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -62,10 +64,10 @@ template <int BX, int A, int TY, int TZ> struct SmacCfg {
     static constexpr int PER = (PLANE + NT - 1) / NT;          // per-lane prefetch slots
 };
 
-template <int BX, int A, int TY, int TZ, typename R>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__restrict__ Fhat,
                                           cplx<R> *__restrict__ Uhat, const cplx<R> *__restrict__ Ktab,
-                                          const int2 *__restrict__ rows, const int2 *__restrict__ tiles, int64_t wg) {
+                                          const SmacRow *__restrict__ rows, const int2 *__restrict__ tiles, int64_t wg) {
     using C = SmacCfg<BX, A, TY, TZ>;
     constexpr int KW = C::KW, SY = C::SY, SZ = C::SZ, NT = C::NT;
     __shared__ cplx<R> kbuf[SY * SZ * KW];
@@ -115,7 +117,8 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     for (int i = 0; i < A; ++i) acc[i] = cmake<R>((R)0, (R)0);
 
     // full window load for row 0
-    int sy = rows[0].x, sz = rows[0].y;
+    int sy = rows[0].y, sz = rows[0].z;
+    unsigned msk = rows[0].mask;
     {
         const int dy0 = ty0 - sy, dz0 = tz0 - sz;
         for (int e = l; e < TY * TZ * KW; e += NT) {
@@ -130,11 +133,13 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     for (int ri = 0; ri < g.n_rows; ++ri) {
         const int buf = ri & 1;
         int nsy = sy, nsz = sz;
+        unsigned nmsk = 0;
         int kind = 0;   // 0: none, 1: plane (new dy), 2: layer (new dz), 3: full reload
         int ndy = 0, ndz = 0;
         if (ri + 1 < g.n_rows) {
-            nsy = rows[ri + 1].x;
-            nsz = rows[ri + 1].y;
+            nsy = rows[ri + 1].y;
+            nsz = rows[ri + 1].z;
+            nmsk = rows[ri + 1].mask;
             const int ddy = nsy - sy, ddz = nsz - sz;
             if (ddz == 0 && (ddy == 1 || ddy == -1)) {
                 kind = 1;
@@ -187,8 +192,12 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     kn2 = krow[-(j + 2)];
                     fn2 = fr[j + 2];
                 }
+                // on sparse rows a source position without a block is
+                // skipped (uniform branch; dense rows take no branch)
+                if (!SPARSE || ((msk >> j) & 1u)) {
 #pragma unroll
-                for (int i = 0; i < A; ++i) acc[i] = cmac(acc[i], kw[i], fj);
+                    for (int i = 0; i < A; ++i) acc[i] = cmac(acc[i], kw[i], fj);
+                }
                 if (j + 1 < BX) {
 #pragma unroll
                     for (int i = A - 1; i >= 1; --i) kw[i] = kw[i - 1];
@@ -231,6 +240,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
         }
         sy = nsy;
         sz = nsz;
+        msk = nmsk;
     }
 
     if (ty < g.ey && tz < g.ez) {
@@ -240,16 +250,16 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     }
 }
 
-template <int BX, int A, int TY, int TZ, typename R>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 __global__ void __launch_bounds__((BX / A) * TY * TZ)
     smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
-                const cplx<R> *__restrict__ Ktab, const int2 *__restrict__ rows, const int2 *__restrict__ tiles) {
-    smac_body<BX, A, TY, TZ, R>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
+                const cplx<R> *__restrict__ Ktab, const SmacRow *__restrict__ rows, const int2 *__restrict__ tiles) {
+    smac_body<BX, A, TY, TZ, R, SPARSE>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
 }
 
 // Several independent convolutions of one template in one grid: workgroup w
 // belongs to the job with wg_begin <= w < next job's wg_begin.
-template <int BX, int A, int TY, int TZ, typename R>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 __global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const SmacJob *__restrict__ jobs, int n_jobs) {
     const int64_t w = xcd_order(blockIdx.x, gridDim.x);
     int lo = 0, hi = n_jobs - 1;
@@ -259,66 +269,92 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const Sm
         else hi = mid - 1;
     }
     const SmacJob &j = jobs[lo];
-    smac_body<BX, A, TY, TZ, R>(j.g, (const cplx<R> *)j.F, (cplx<R> *)j.U, (const cplx<R> *)j.K, j.rows, j.tiles,
+    smac_body<BX, A, TY, TZ, R, SPARSE>(j.g, (const cplx<R> *)j.F, (cplx<R> *)j.U, (const cplx<R> *)j.K, j.rows, j.tiles,
                                 w - j.wg_begin);
 }
 
-template <int BX, int A, int TY, int TZ, typename R>
-hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const int2 *rows,
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
+hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const SmacRow *rows,
                       const int2 *tiles, hipStream_t s) {
     using C = SmacCfg<BX, A, TY, TZ>;
     if (g.n_rows <= 0 || g.n_tiles <= 0) return hipSuccess;
     const int64_t nwg = (int64_t)g.n_freq * g.n_tiles;
-    hipLaunchKernelGGL((smac_kernel<BX, A, TY, TZ, R>), dim3((unsigned)nwg), dim3(C::NT), 0, s, g,
+    hipLaunchKernelGGL((smac_kernel<BX, A, TY, TZ, R, SPARSE>), dim3((unsigned)nwg), dim3(C::NT), 0, s, g,
                        (const cplx<R> *)F, (cplx<R> *)U, (const cplx<R> *)K, rows, tiles);
     return hipGetLastError();
 }
 
-template <int BX, int A, int TY, int TZ, typename R>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 hipError_t launch_batch_cfg(const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s) {
     using C = SmacCfg<BX, A, TY, TZ>;
     if (n_jobs <= 0 || total_wg <= 0) return hipSuccess;
-    hipLaunchKernelGGL((smac_batch_kernel<BX, A, TY, TZ, R>), dim3((unsigned)total_wg), dim3(C::NT), 0, s, jobs,
-                       n_jobs);
+    hipLaunchKernelGGL((smac_batch_kernel<BX, A, TY, TZ, R, SPARSE>), dim3((unsigned)total_wg), dim3(C::NT), 0, s,
+                       jobs, n_jobs);
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t smac_batch_launch(int bx, bool fp32, const SmacJob *jobs, int n_jobs, int64_t total_wg, hipStream_t s) {
+// Template per row length: (A, TY, TZ) = (8, 8, 8) for bx = 8, (8, 16, 8) for
+// bx = 16 and (16, 16, 8) for bx = 32.
+template <typename F> hipError_t dispatch(int bx, bool fp32, bool sparse, const F &f) {
+    auto pick = [&](auto bxc, auto ac, auto tyc, auto tzc) -> hipError_t {
+        constexpr int BX = decltype(bxc)::value, A = decltype(ac)::value, TY = decltype(tyc)::value,
+                      TZ = decltype(tzc)::value;
+        if (fp32)
+            return sparse ? f.template operator()<BX, A, TY, TZ, float, true>()
+                          : f.template operator()<BX, A, TY, TZ, float, false>();
+        return sparse ? f.template operator()<BX, A, TY, TZ, double, true>()
+                      : f.template operator()<BX, A, TY, TZ, double, false>();
+    };
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
     switch (bx) {
-    case 8:
-        return fp32 ? launch_batch_cfg<8, 8, 8, 8, float>(jobs, n_jobs, total_wg, s)
-                    : launch_batch_cfg<8, 8, 8, 8, double>(jobs, n_jobs, total_wg, s);
-    case 16:
-        return fp32 ? launch_batch_cfg<16, 8, 16, 8, float>(jobs, n_jobs, total_wg, s)
-                    : launch_batch_cfg<16, 8, 16, 8, double>(jobs, n_jobs, total_wg, s);
-    case 32:
-        return fp32 ? launch_batch_cfg<32, 16, 16, 8, float>(jobs, n_jobs, total_wg, s)
-                    : launch_batch_cfg<32, 16, 16, 8, double>(jobs, n_jobs, total_wg, s);
-    default:
-        return hipErrorInvalidValue;
+    case 8: return pick(I8{}, I8{}, I8{}, I8{});
+    case 16: return pick(I16{}, I8{}, I16{}, I8{});
+    case 32: return pick(I32{}, I16{}, I16{}, I8{});
+    default: return hipErrorInvalidValue;
     }
 }
 
-int smac_tile_y(int bx) { return bx == 8 ? 8 : (bx == 16 ? 16 : 16); }
-int smac_tile_z(int bx) { return bx == 8 ? 8 : (bx == 16 ? 8 : 8); }
-
-hipError_t smac_launch(const SmacGeom &g, bool fp32, const void *Fhat, void *Uhat, const void *Ktab,
-                       const int2 *rows, const int2 *tiles, hipStream_t s) {
-    switch (g.bx) {
-    case 8:
-        return fp32 ? launch_cfg<8, 8, 8, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
-                    : launch_cfg<8, 8, 8, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
-    case 16:
-        return fp32 ? launch_cfg<16, 8, 16, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
-                    : launch_cfg<16, 8, 16, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
-    case 32:
-        return fp32 ? launch_cfg<32, 16, 16, 8, float>(g, Fhat, Uhat, Ktab, rows, tiles, s)
-                    : launch_cfg<32, 16, 16, 8, double>(g, Fhat, Uhat, Ktab, rows, tiles, s);
-    default:
-        return hipErrorInvalidValue;
+struct BatchLaunch {
+    const SmacJob *jobs;
+    int n_jobs;
+    int64_t total_wg;
+    hipStream_t s;
+    template <int BX, int A, int TY, int TZ, typename R, bool SP> hipError_t operator()() const {
+        return launch_batch_cfg<BX, A, TY, TZ, R, SP>(jobs, n_jobs, total_wg, s);
     }
+};
+
+struct SingleLaunch {
+    const SmacGeom &g;
+    const void *F;
+    void *U;
+    const void *K;
+    const SmacRow *rows;
+    const int2 *tiles;
+    hipStream_t s;
+    template <int BX, int A, int TY, int TZ, typename R, bool SP> hipError_t operator()() const {
+        return launch_cfg<BX, A, TY, TZ, R, SP>(g, F, U, K, rows, tiles, s);
+    }
+};
+
+}  // namespace
+
+hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs, int64_t total_wg,
+                             hipStream_t s) {
+    return dispatch(bx, fp32, sparse, BatchLaunch{jobs, n_jobs, total_wg, s});
+}
+
+int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
+int smac_tile_z(int bx) {
+    (void)bx;
+    return 8;
+}
+
+hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
+                       const SmacRow *rows, const int2 *tiles, hipStream_t s) {
+    return dispatch(g.bx, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, s});
 }
 
 }  // namespace lgf
