@@ -56,6 +56,73 @@ def measured_traffic():
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
+def config_table(ctx, reps=3):
+    """Every workload of the hot path, FP64 and FP32+refine: plan time, median
+    solve time, target cells/s and the error against stored oracle samples
+    (tests/golden, written by scripts that call only the oracle) where such
+    samples exist, else the difference to the FP64 result."""
+    import numpy as np
+    import torch
+    from paper_2010_13213_amd import inputs, lgf
+
+    gold = os.path.join(ROOT, "tests", "golden")
+    cases = [
+        ("gaussian_box_32^3", lambda: inputs.gaussian_box(), None),
+        ("ring_128^3_vector", lambda: inputs.single_ring(), None),
+        ("two_level_ring", lambda: inputs.two_level_ring(components=(0, 1)),
+         os.path.join(gold, "two_level_ring_samples.npz")),
+        ("colliding_rings_quarter", lambda: inputs.colliding_rings(nb=8, dx0=1.0 / 8, components=(0, 2)),
+         os.path.join(gold, "colliding_rings_quarter_samples.npz")),
+        ("colliding_rings", lambda: inputs.colliding_rings(), None),
+    ]
+    table = {}
+    for name, make, gpath in cases:
+        prob = make()
+        f = torch.from_numpy(prob.flat_source()).cuda()
+        cells = prob.n_cells() * prob.n_components
+        row = {"blocks_per_level": [len(lv.blocks) for lv in prob.levels], "nb": prob.nb,
+               "components": prob.n_components, "target_cells": cells}
+        res = {}
+        for prec in ("fp64", "fp32_refine"):
+            t0 = time.perf_counter()
+            plan = lgf.Plan.for_problem(ctx, prob, prec)
+            t_plan = time.perf_counter() - t0
+            u = torch.empty_like(f)
+            plan.solve(f, u)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                plan.solve(f, u)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            plan.close()
+            res[prec] = u.cpu().numpy().reshape(prob.n_components, -1)
+            ms = 1e3 * float(np.median(ts))
+            row[prec] = {"plan_s": round(t_plan, 3), "solve_ms": ms, "cells_per_s": cells / (ms * 1e-3)}
+        if gpath is not None:
+            g = np.load(gpath)
+            for prec in ("fp64", "fp32_refine"):
+                errs = []
+                base = 0
+                for k, lv in enumerate(prob.levels):
+                    n = len(lv.blocks) * prob.nb ** 3
+                    idx = g["sample%d" % k]
+                    for c in range(prob.n_components):
+                        ref = g["phi%d_c%d" % (k, c)]
+                        got = res[prec][c][base:base + n][idx]
+                        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+                    base += n
+                row[prec]["err_vs_oracle_max_rel_l2"] = max(errs)
+        d = res["fp32_refine"] - res["fp64"]
+        row["fp32_refine"]["rel_l2_vs_fp64"] = float(np.linalg.norm(d) / np.linalg.norm(res["fp64"]))
+        row["fp32_refine"]["ratio_vs_fp64"] = row["fp64"]["solve_ms"] / row["fp32_refine"]["solve_ms"]
+        table[name] = row
+        print("config %s: %s" % (name, json.dumps(row)), file=sys.stderr, flush=True)
+        del f, res
+    return table
+
+
 def _pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -97,6 +164,8 @@ def main():
                     help="which precision paths to time (profiling runs use one)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--configs", action="store_true",
+                    help="also time every workload (FP64 and FP32+refine) into a 'configs' entry")
     ap.add_argument("--print-mac-hash", action="store_true",
                     help="print the hash of the MAC kernel sources and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -233,6 +302,8 @@ def main():
             "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"],
             "throughput_cells_per_s": run["throughput_cells_per_s"],
             "mean_batch": run["mean_batch"]}
+    if args.configs:
+        out["configs"] = config_table(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
