@@ -151,4 +151,12 @@ __device__ __forceinline__ double lgf_G(const double *__restrict__ gc, int nx, i
     return lgf_far((double)a, (double)b, (double)c);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (hardware id b lands
+// on XCD b mod 8); renumber them so that consecutive logical ids run on the
+// same XCD and share its L2.  A bijection on [0, n) for any n.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t n) {
+    const int64_t xcd = b % 8, idx = b / 8, per = n / 8, rem = n % 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 }  // namespace lgf

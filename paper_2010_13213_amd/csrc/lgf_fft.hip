@@ -11,6 +11,11 @@
 //   z: N (N/2+1) columns, zero-padded to N -> written frequency-major to HBM
 // The zero half of the input is never loaded.  Inverse runs the same stages
 // backwards and keeps only the [0, nb)^3 corner of the result.
+//
+// A block's spectrum is one 16-byte (8 in float32) entry per frequency row
+// of the frequency-major arrays, so neighbouring slots share HBM lines;
+// blocks are renumbered so that consecutive blocks (consecutive slots) run
+// at the same time on one XCD and meet in its L2.
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -88,7 +93,7 @@ template <int NB, typename R>
 __global__ void __launch_bounds__(256) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                                   const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
                                                   int64_t n_slots, double scale) {
-    fwd_body<NB, R>(src, blk_off, slot, Fhat, n_slots, scale, blockIdx.x);
+    fwd_body<NB, R>(src, blk_off, slot, Fhat, n_slots, scale, (int)xcd_order(blockIdx.x, gridDim.x));
 }
 
 __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
@@ -103,8 +108,9 @@ __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_j
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(256) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
-    const FftJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
-    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, blockIdx.x - j.blk_begin);
+    const int b = (int)xcd_order(blockIdx.x, gridDim.x);
+    const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
+    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, b - j.blk_begin);
 }
 
 template <int NB, typename R>
@@ -172,14 +178,15 @@ template <int NB, typename R>
 __global__ void __launch_bounds__(256) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
                                                   const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
                                                   double *__restrict__ dst, double scale, int accumulate) {
-    inv_body<NB, R>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, blockIdx.x);
+    inv_body<NB, R>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, (int)xcd_order(blockIdx.x, gridDim.x));
 }
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(256) inv_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
-    const FftJob &j = jobs[find_job(jobs, n_jobs, blockIdx.x)];
+    const int b = (int)xcd_order(blockIdx.x, gridDim.x);
+    const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
     inv_body<NB, R>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
-                    blockIdx.x - j.blk_begin);
+                    b - j.blk_begin);
 }
 
 template <int NB, typename R>
