@@ -104,9 +104,10 @@ void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
 size_t lgf_plan::workspace_bytes() const {
     size_t b = Fhat.bytes + Uhat.bytes + ws_fhat.bytes + ws_F.bytes + ws_psi[0].bytes + ws_psi[1].bytes +
                ws_ppsi.bytes + ws_srcF.bytes + ws_srcf.bytes + ws_ut.bytes + ws_ush.bytes + ws_rho.bytes;
-    for (const Conv *c : convs_view)
-        b += c->d_src_slot.bytes + c->d_tgt_slot.bytes + c->d_src_off.bytes + c->d_tgt_off.bytes +
-             c->d_rows.bytes + c->d_tiles.bytes;
+    for (const Conv *c : convs_view) {
+        b += c->d_src_slot.bytes + c->d_tgt_slot.bytes + c->d_src_off.bytes + c->d_tgt_off.bytes;
+        for (const auto &p : c->parts) b += p->d_rows.bytes + p->d_tiles.bytes + p->d_lanes.bytes;
+    }
     for (const auto &L : lv)
         b += L->d_cover.bytes + L->d_own_off.bytes + L->d_cf_fine.bytes + L->d_cf_coarse.bytes + L->d_cf_oct.bytes +
              L->d_fblk.bytes + L->d_ext_own.bytes + L->d_cmap.bytes + L->d_cu_src.bytes + L->d_cu_dst.bytes +

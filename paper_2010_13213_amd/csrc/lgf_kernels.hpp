@@ -52,8 +52,16 @@ struct SmacRow {
     unsigned mask;
     int pad;
 };
+// A work tile of one convolution: a TY x TZ rectangle of target rows at
+// (ty0, tz0) and the lanes that run on it, lanes[lane_off + l] for
+// l < n_lanes, each packed as seg | tyl << 8 | tzl << 16 (the lane's A
+// targets start at x = seg * A of row (ty0 + tyl, tz0 + tzl)).  Only
+// x-segments that hold targets get a lane.
+struct SmacTile {
+    int ty0, tz0, lane_off, n_lanes;
+};
 struct SmacGeom {
-    int bx;                 // row length template (8, 16 or 32)
+    int bx;                 // row length template (8 or 16)
     int ey, ez;             // padded box extent in blocks along y, z (slots)
     int n_freq;
     int64_t n_slots;        // bx * ey * ez
@@ -61,7 +69,11 @@ struct SmacGeom {
     int N;                        // FFT edge 2 nb (frequency index remap)
     const int *perm;              // frequency order: reflection partners adjacent
     int n_rows;             // source rows (sy, sz), serpentine order
-    int n_tiles;            // target tiles (ty0, tz0)
+    int n_tiles;            // work tiles
+    const int *lanes;       // packed lane table of the tiles
+    int rs;                 // slots per row of the padded box (multiple of bx)
+    int tx0, sx0;           // x offsets of this part's target / source segment
+    int accum;              // add into Uhat instead of storing
 };
 // One convolution of a batched spectral-MAC launch (device-resident table).
 struct SmacJob {
@@ -70,18 +82,19 @@ struct SmacJob {
     void *U;
     const void *K;
     const SmacRow *rows;
-    const int2 *tiles;
+    const SmacTile *tiles;
     int64_t wg_begin;       // first workgroup of this job in the batched grid
 };
 hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs, int64_t total_wg,
                              hipStream_t s);
 int smac_tile_y(int bx);
 int smac_tile_z(int bx);
+int smac_seg_len(int bx);   // A: targets per lane
 // Uhat[omega][t] = sum_s K[omega][t - s] * Fhat[omega][s] over every source row
 // and every target slot of each tile; source positions outside a row's mask
 // are skipped when `sparse` (their Fhat must be zero either way).
 hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
-                       const SmacRow *rows, const int2 *tiles, hipStream_t s);
+                       const SmacRow *rows, const SmacTile *tiles, hipStream_t s);
 
 // ---- composite-grid kernels (lgf_composite.hip) ----
 // dst block b = src block b with the octants flagged in cover[b] zeroed.

@@ -190,17 +190,17 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
 
 // ------------------------------------------------------------------ plan
 
-static int pick_bx(int ex) {
-    if (ex <= 8) return 8;
-    if (ex <= 16) return 16;
-    if (ex <= 32) return 32;
-    return -1;
-}
-
 static int roundup(int a, int m) { return (a + m - 1) / m * m; }
 
 // Build a convolution: sources `src` and targets `tgt` (block coords of one
 // level), field offsets (in elements, per component) of each block.
+//
+// Rows longer than 16 blocks are cut into 16-wide x-segments; every pair
+// (target segment, source segment) with targets and sources is one part,
+// run by the 16-wide MAC template.  Part (ts, ss) runs in phase
+// (ss - ts) mod n_seg, so the parts of one target segment never run in the
+// same launch; the first of them stores into Uhat, later ones add.  Empty
+// source segments of a row and empty target segments of a tile cost nothing.
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32) {
     lgf_context *ctx = plan->ctx;
     const int nb = plan->nb;
@@ -212,73 +212,115 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
                 hi[a] = std::max(hi[a], b.ijk[a]);
             }
     const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-    const int bx = pick_bx(ex);
-    if (bx < 0 || ey > 64 || ez > 64)
-        throw Failure(LGF_E_UNSUPPORTED, "level extent above 32 blocks along x or 64 along y/z");
+    if (ex > 64 || ey > 64 || ez > 64)
+        throw Failure(LGF_E_UNSUPPORTED, "level extent above 64 blocks along an axis");
+    const int bx = ex <= 8 ? 8 : 16;
+    const int rs = roundup(ex, bx);
+    const int n_seg = rs / bx;
     const int TY = smac_tile_y(bx), TZ = smac_tile_z(bx);
     c.bx = bx;
+    c.rs = rs;
     c.ey = roundup(ey, TY);
     c.ez = roundup(ez, TZ);
     for (int a = 0; a < 3; ++a) c.lo[a] = lo[a];
-    c.n_slots = (int64_t)bx * c.ey * c.ez;
+    c.n_slots = (int64_t)rs * c.ey * c.ez;
     c.fp32 = fp32;
     auto slot_of = [&](const Blk &b) -> int {
-        return ((b.ijk[2] - lo[2]) * c.ey + (b.ijk[1] - lo[1])) * bx + (b.ijk[0] - lo[0]);
+        return ((b.ijk[2] - lo[2]) * c.ey + (b.ijk[1] - lo[1])) * rs + (b.ijk[0] - lo[0]);
     };
     std::vector<int> s_slot, t_slot;
     std::vector<int64_t> s_off, t_off;
-    std::map<std::pair<int, int>, unsigned> rowmask;
-    std::set<std::pair<int, int>> tileset;
+    // per source segment: row -> occupancy mask; per target segment: tile ->
+    // occupied x-segments of A targets
+    const int A = smac_seg_len(bx), NSEG = bx / A, NT = NSEG * TY * TZ;
+    std::vector<std::map<std::pair<int, int>, unsigned>> rowmask(n_seg);
+    std::vector<std::map<std::pair<int, int>, std::set<int>>> tileseg(n_seg);
     for (const auto &b : src) {
         s_slot.push_back(slot_of(b));
         s_off.push_back(b.off);
-        rowmask[{b.ijk[2] - lo[2], b.ijk[1] - lo[1]}] |= 1u << (b.ijk[0] - lo[0]);
+        const int x = b.ijk[0] - lo[0];
+        rowmask[x / bx][{b.ijk[2] - lo[2], b.ijk[1] - lo[1]}] |= 1u << (x % bx);
     }
     for (const auto &b : tgt) {
         t_slot.push_back(slot_of(b));
         t_off.push_back(b.off);
-        tileset.insert({(b.ijk[2] - lo[2]) / TZ * TZ, (b.ijk[1] - lo[1]) / TY * TY});
+        const int y = b.ijk[1] - lo[1], z = b.ijk[2] - lo[2], x = b.ijk[0] - lo[0];
+        const int tzl = z % TZ, tyl = y % TY, seg = (x % bx) / A;
+        tileseg[x / bx][{z / TZ * TZ, y / TY * TY}].insert((tzl * TY + tyl) * NSEG + seg);
     }
-    // serpentine row order: z ascending, y alternating direction per z group
-    std::map<int, std::vector<int>> byz;
-    for (auto &r : rowmask) byz[r.first.first].push_back(r.first.second);
-    std::vector<SmacRow> rows;
-    int gi = 0;
-    for (auto &kv : byz) {
-        auto ys = kv.second;
-        std::sort(ys.begin(), ys.end());
-        if (gi & 1) std::reverse(ys.begin(), ys.end());
-        for (int y : ys) rows.push_back(SmacRow{y, kv.first, rowmask[{kv.first, y}], 0});
-        ++gi;
-    }
-    std::vector<int2> tiles;
-    for (auto &t : tileset) tiles.push_back(make_int2(t.second, t.first));
+    auto up = [&](DeviceBuffer &d, const void *h, size_t n) {
+        if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
+    };
+    std::vector<bool> stored(n_seg, false);
+    for (int ph = 0; ph < n_seg; ++ph)
+        for (int ts = 0; ts < n_seg; ++ts) {
+            const int ss = (ts + ph) % n_seg;
+            if (rowmask[ss].empty() || tileseg[ts].empty()) continue;
+            auto part = std::make_unique<SubConv>();
+            part->tx0 = ts * bx;
+            part->sx0 = ss * bx;
+            part->phase = ph;
+            part->accum = stored[ts];
+            stored[ts] = true;
+            // serpentine row order: z ascending, y alternating per z group
+            std::map<int, std::vector<int>> byz;
+            int64_t n_src_seg = 0;
+            for (auto &r : rowmask[ss]) {
+                byz[r.first.first].push_back(r.first.second);
+                n_src_seg += __builtin_popcount(r.second);
+            }
+            std::vector<SmacRow> rows;
+            int gi = 0;
+            for (auto &kv : byz) {
+                auto ys = kv.second;
+                std::sort(ys.begin(), ys.end());
+                if (gi & 1) std::reverse(ys.begin(), ys.end());
+                for (int y : ys) rows.push_back(SmacRow{y, kv.first, rowmask[ss][{kv.first, y}], 0});
+                ++gi;
+            }
+            // lanes in (tz, ty, seg) order: a full tile gets lane l = (tzl * TY
+            // + tyl) * NSEG + seg; tiles with more lanes than a workgroup split
+            std::vector<SmacTile> tiles;
+            std::vector<int> lanes;
+            for (auto &t : tileseg[ts]) {
+                std::vector<int> ls;
+                for (int key : t.second) {
+                    const int seg = key % NSEG, tyl = (key / NSEG) % TY, tzl = key / (NSEG * TY);
+                    ls.push_back(seg | (tyl << 8) | (tzl << 16));
+                }
+                for (size_t i = 0; i < ls.size(); i += NT) {
+                    const int n = (int)std::min<size_t>(NT, ls.size() - i);
+                    tiles.push_back(SmacTile{t.first.second, t.first.first, (int)lanes.size(), n});
+                    lanes.insert(lanes.end(), ls.begin() + i, ls.begin() + i + n);
+                }
+            }
+            part->n_rows = (int)rows.size();
+            part->n_tiles = (int)tiles.size();
+            // skipping empty source positions costs a branch per position:
+            // worth it once more than a few percent of them are empty
+            part->sparse = n_src_seg * 10 < (int64_t)rows.size() * bx * 9;
+            part->d_rows.alloc(ctx, sizeof(SmacRow) * std::max<size_t>(1, rows.size()), "rows");
+            part->d_tiles.alloc(ctx, sizeof(SmacTile) * std::max<size_t>(1, tiles.size()), "tiles");
+            part->d_lanes.alloc(ctx, sizeof(int) * std::max<size_t>(1, lanes.size()), "lanes");
+            up(part->d_rows, rows.data(), sizeof(SmacRow) * rows.size());
+            up(part->d_tiles, tiles.data(), sizeof(SmacTile) * tiles.size());
+            up(part->d_lanes, lanes.data(), sizeof(int) * lanes.size());
+            c.parts.push_back(std::move(part));
+        }
     c.n_src = (int)src.size();
     c.n_tgt = (int)tgt.size();
-    c.n_rows = (int)rows.size();
-    c.n_tiles = (int)tiles.size();
-    // skipping empty source positions costs a branch per position: worth it
-    // once more than a few percent of the rows' positions are empty
-    c.sparse = (int64_t)src.size() * 10 < (int64_t)rows.size() * bx * 9;
-    c.spec = get_spectra(ctx, nb, fp32, bx - 1, c.ey - 1, c.ez - 1);
+    c.spec = get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1);
     c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
     c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
     c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
     c.d_tgt_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, t_off.size()), "offsets");
-    c.d_rows.alloc(ctx, sizeof(SmacRow) * std::max<size_t>(1, rows.size()), "rows");
-    c.d_tiles.alloc(ctx, sizeof(int2) * std::max<size_t>(1, tiles.size()), "tiles");
-    auto up = [&](DeviceBuffer &d, const void *h, size_t n) {
-        if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
-    };
     up(c.d_src_slot, s_slot.data(), sizeof(int) * s_slot.size());
     up(c.d_tgt_slot, t_slot.data(), sizeof(int) * t_slot.size());
     up(c.d_src_off, s_off.data(), sizeof(int64_t) * s_off.size());
     up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
-    up(c.d_rows, rows.data(), sizeof(SmacRow) * rows.size());
-    up(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size());
 }
 
-SmacGeom conv_geom(const Conv &c) {
+SmacGeom conv_geom(const Conv &c, const SubConv &p) {
     SmacGeom g;
     g.bx = c.bx;
     g.ey = c.ey;
@@ -293,8 +335,13 @@ SmacGeom conv_geom(const Conv &c) {
     g.ZD = g.ZH + 1;
     g.N = 2 * c.spec->nb;
     g.perm = (const int *)c.spec->perm.ptr;
-    g.n_rows = c.n_rows;
-    g.n_tiles = c.n_tiles;
+    g.n_rows = p.n_rows;
+    g.n_tiles = p.n_tiles;
+    g.lanes = (const int *)p.d_lanes.ptr;
+    g.rs = c.rs;
+    g.tx0 = p.tx0;
+    g.sx0 = p.sx0;
+    g.accum = p.accum ? 1 : 0;
     return g;
 }
 
@@ -481,11 +528,13 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, dou
                                     (const int *)c.d_src_slot.ptr, c.n_src, plan->Fhat.ptr, c.n_slots, 1.0, s),
                   "forward block FFT");
     }
-    {
+    if (c.parts.empty())   // no source or no target: the convolution is zero
+        hip_check(hipMemsetAsync(plan->Uhat.ptr, 0, plan->Uhat.bytes, s), "clear Uhat");
+    for (const auto &p : c.parts) {
         StageTimer t(plan->ctx, 1, s);
-        const SmacGeom g = conv_geom(c);
-        hip_check(smac_launch(g, c.fp32, c.sparse, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
-                              (const SmacRow *)c.d_rows.ptr, (const int2 *)c.d_tiles.ptr, s),
+        const SmacGeom g = conv_geom(c, *p);
+        hip_check(smac_launch(g, c.fp32, p->sparse, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
+                              (const SmacRow *)p->d_rows.ptr, (const SmacTile *)p->d_tiles.ptr, s),
                   "spectral MAC");
     }
     {

@@ -90,16 +90,30 @@ struct Blk {
     int64_t off;
 };
 
+// One (target x-segment, source x-segment) part of a convolution, run by the
+// bx-wide MAC template: targets at x in [tx0, tx0 + bx), sources at x in
+// [sx0, sx0 + bx) of the padded box.
+struct SubConv {
+    int tx0 = 0, sx0 = 0;
+    int phase = 0;          // parts of one target segment run in different phases
+    bool accum = false;     // add into Uhat (an earlier phase stored the segment)
+    bool sparse = false;    // source rows have holes: the MAC skips empty positions
+    int n_rows = 0, n_tiles = 0;
+    DeviceBuffer d_rows, d_tiles, d_lanes;
+};
+
 // One blockwise LGF convolution on a level (sources -> targets).
 struct Conv {
-    int bx = 0, ey = 0, ez = 0;
+    int bx = 0;             // MAC row template (8 or 16)
+    int rs = 0;             // slots per row of the padded box: a multiple of bx
+    int ey = 0, ez = 0;
     int lo[3] = {0, 0, 0};
     int64_t n_slots = 0;
     bool fp32 = false;
-    bool sparse = false;    // source rows have holes: the MAC skips empty positions
-    int n_src = 0, n_tgt = 0, n_rows = 0, n_tiles = 0;
+    int n_src = 0, n_tgt = 0;
     SpecTable *spec = nullptr;
-    DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off, d_rows, d_tiles;
+    DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off;
+    std::vector<std::unique_ptr<SubConv>> parts;   // in phase order
 };
 
 // One L_dx^-1 application on a source and a target block set: a plain
@@ -133,7 +147,7 @@ struct LevelSched {
 };
 
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
-SmacGeom conv_geom(const Conv &c);
+SmacGeom conv_geom(const Conv &c, const SubConv &p);
 
 }  // namespace lgf
 

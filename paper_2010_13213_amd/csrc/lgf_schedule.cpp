@@ -383,33 +383,45 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
                   "batched forward FFT");
         ring_mark(ctx, slot, s);
     }
-    for (int fp = 0; fp < 2; ++fp)
-        for (int bx : {8, 16, 32})
-            for (int sp = 0; sp < 2; ++sp) {
-                std::vector<SmacJob> sj;
-                int64_t total = 0;
-                for (const ConvCall &k : calls) {
-                    if ((int)k.c->fp32 != fp || k.c->bx != bx || (int)k.c->sparse != sp || k.c->n_rows == 0 ||
-                        k.c->n_tiles == 0)
-                        continue;
-                    SmacJob j{};
-                    j.g = conv_geom(*k.c);
-                    j.F = k.p->Fhat.ptr;
-                    j.U = k.p->Uhat.ptr;
-                    j.K = k.c->spec->data.ptr;
-                    j.rows = (const SmacRow *)k.c->d_rows.ptr;
-                    j.tiles = (const int2 *)k.c->d_tiles.ptr;
-                    j.wg_begin = total;
-                    total += (int64_t)j.g.n_freq * j.g.n_tiles;
-                    sj.push_back(j);
+    for (const ConvCall &k : calls)
+        if (k.c->parts.empty())
+            hip_check(hipMemsetAsync(k.p->Uhat.ptr, 0, k.p->Uhat.bytes, s), "clear Uhat");
+    // parts of one target segment are in different phases: one launch per
+    // (phase, precision, template, sparse flag)
+    int n_phase = 0;
+    for (const ConvCall &k : calls)
+        for (const auto &pt : k.c->parts) n_phase = std::max(n_phase, pt->phase + 1);
+    for (int ph = 0; ph < n_phase; ++ph)
+        for (int fp = 0; fp < 2; ++fp)
+            for (int bx : {8, 16})
+                for (int sp = 0; sp < 2; ++sp) {
+                    std::vector<SmacJob> sj;
+                    int64_t total = 0;
+                    for (const ConvCall &k : calls) {
+                        if ((int)k.c->fp32 != fp || k.c->bx != bx) continue;
+                        for (const auto &pt : k.c->parts) {
+                            if (pt->phase != ph || (int)pt->sparse != sp || pt->n_rows == 0 || pt->n_tiles == 0)
+                                continue;
+                            SmacJob j{};
+                            j.g = conv_geom(*k.c, *pt);
+                            j.F = k.p->Fhat.ptr;
+                            j.U = k.p->Uhat.ptr;
+                            j.K = k.c->spec->data.ptr;
+                            j.rows = (const SmacRow *)pt->d_rows.ptr;
+                            j.tiles = (const SmacTile *)pt->d_tiles.ptr;
+                            j.wg_begin = total;
+                            total += (int64_t)j.g.n_freq * j.g.n_tiles;
+                            sj.push_back(j);
+                        }
+                    }
+                    if (sj.empty()) continue;
+                    StageTimer t(ctx, 1, s);
+                    int slot = 0;
+                    hip_check(smac_batch_launch(bx, fp == 1, sp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(),
+                                                total, s),
+                              "batched spectral MAC");
+                    ring_mark(ctx, slot, s);
                 }
-                if (sj.empty()) continue;
-                StageTimer t(ctx, 1, s);
-                int slot = 0;
-                hip_check(smac_batch_launch(bx, fp == 1, sp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(), total, s),
-                          "batched spectral MAC");
-                ring_mark(ctx, slot, s);
-            }
     for (int fp = 0; fp < 2; ++fp) {
         std::vector<FftJob> fj;
         int total = 0;

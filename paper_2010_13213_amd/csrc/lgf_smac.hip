@@ -15,7 +15,10 @@
 //
 // One workgroup owns one frequency and one tile of TY x TZ target rows (a
 // row is the bx blocks along x at fixed (y, z)).  Lane (seg, ty, tz) keeps A
-// consecutive targets of its row in registers.  The workgroup walks the
+// consecutive targets of its row in registers; a per-tile lane table gives
+// lanes only to the x-segments that hold targets, so thin supports do not
+// pay for the empty part of their rows (a crowded tile is split over
+// several workgroups).  The workgroup walks the
 // source rows (sy, sz) in serpentine order; for each row every lane needs
 // the kernel row K[., ty - sy, tz - sz] (2 bx - 1 values along x), which
 // lives in an LDS ring buffer of (TY+1) x (TZ+1) kernel rows indexed by
@@ -59,7 +62,7 @@ template <int BX, int A, int TY, int TZ> struct SmacCfg {
 template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__restrict__ Fhat,
                                           cplx<R> *__restrict__ Uhat, const cplx<R> *__restrict__ Ktab,
-                                          const SmacRow *__restrict__ rows, const int2 *__restrict__ tiles, int64_t wg) {
+                                          const SmacRow *__restrict__ rows, const SmacTile *__restrict__ tiles, int64_t wg) {
     using C = SmacCfg<BX, A, TY, TZ>;
     constexpr int KW = C::KW, SY = C::SY, SZ = C::SZ, NT = C::NT;
     __shared__ cplx<R> kbuf[SY * SZ * KW];
@@ -70,11 +73,13 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     // spectra-table rows: both then meet in the L2 of one XCD
     const int freq = g.perm[wg / g.n_tiles];
     const int tile = (int)(wg % g.n_tiles);
-    const int ty0 = tiles[tile].x, tz0 = tiles[tile].y;
+    const SmacTile tl = tiles[tile];
+    const int ty0 = tl.ty0, tz0 = tl.tz0;
     const int l = threadIdx.x;
-    const int seg = l % C::NSEG;
-    const int r = l / C::NSEG;
-    const int tyl = r % TY, tzl = r / TY;
+    // lanes past n_lanes only help with the cooperative loads
+    const bool active = l < tl.n_lanes;
+    const int code = active ? g.lanes[tl.lane_off + l] : 0;
+    const int seg = code & 255, tyl = (code >> 8) & 255, tzl = code >> 16;
     const int ty = ty0 + tyl, tz = tz0 + tzl;
     const int x0 = seg * A;
 
@@ -91,14 +96,15 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     };
     // raw table value for offset (dxi - (BX - 1), dy, dz), dxi in [0, KW);
     // a negative dx also needs the conjugate, applied by kfix
+    const int dox = g.tx0 - g.sx0;   // x offset between the target and source segments
     auto kraw = [&](int dy, int dz, int dxi) -> cplx<R> {
-        const int dx = dxi - (BX - 1);
+        const int dx = dxi - (BX - 1) + dox;
         const bool fx = dx < 0;
         const int fy = (dy < 0) != fx, fz = (dz < 0) != fx;
         return Ktab[frow_off(fy, fz) + ((size_t)abs(dy) * g.ZD + abs(dz)) * g.XD + abs(dx)];
     };
     auto kfix = [&](cplx<R> v, int dxi) -> cplx<R> {
-        if (dxi < BX - 1) v.y = -v.y;
+        if (dxi - (BX - 1) + dox < 0) v.y = -v.y;
         return v;
     };
     auto kload = [&](int dy, int dz, int dxi) -> cplx<R> { return kfix(kraw(dy, dz, dxi), dxi); };
@@ -118,7 +124,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
             const int dy = dy0 + q % TY, dz = dz0 + q / TY;
             kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
         }
-        for (int e = l; e < BX; e += NT) frow[0][e] = Ff[((size_t)sz * g.ey + sy) * BX + e];
+        for (int e = l; e < BX; e += NT) frow[0][e] = Ff[((size_t)sz * g.ey + sy) * g.rs + g.sx0 + e];
     }
     __syncthreads();
 
@@ -158,7 +164,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     pre[p] = kraw(dy, dz, dxi);
                 }
             }
-            if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * BX + l];
+            if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + l];
         }
 
         // compute: U[i] += K[x0 + i - j] * F[j], with a sliding register
@@ -227,7 +233,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                 const int dy = dy0 + q % TY, dz = dz0 + q / TY;
                 kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
             }
-            for (int e = l; e < BX; e += NT) frow[buf ^ 1][e] = Ff[((size_t)nsz * g.ey + nsy) * BX + e];
+            for (int e = l; e < BX; e += NT) frow[buf ^ 1][e] = Ff[((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + e];
             __syncthreads();
         }
         sy = nsy;
@@ -235,17 +241,22 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
         msk = nmsk;
     }
 
-    if (ty < g.ey && tz < g.ez) {
-        cplx<R> *Uf = Uhat + (size_t)freq * g.n_slots + ((size_t)tz * g.ey + ty) * BX + x0;
+    if (active) {
+        cplx<R> *Uf = Uhat + (size_t)freq * g.n_slots + ((size_t)tz * g.ey + ty) * g.rs + g.tx0 + x0;
+        if (g.accum) {
 #pragma unroll
-        for (int i = 0; i < A; ++i) Uf[i] = acc[i];
+            for (int i = 0; i < A; ++i) Uf[i] = cmake<R>(Uf[i].x + acc[i].x, Uf[i].y + acc[i].y);
+        } else {
+#pragma unroll
+            for (int i = 0; i < A; ++i) Uf[i] = acc[i];
+        }
     }
 }
 
 template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 __global__ void __launch_bounds__((BX / A) * TY * TZ)
     smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
-                const cplx<R> *__restrict__ Ktab, const SmacRow *__restrict__ rows, const int2 *__restrict__ tiles) {
+                const cplx<R> *__restrict__ Ktab, const SmacRow *__restrict__ rows, const SmacTile *__restrict__ tiles) {
     smac_body<BX, A, TY, TZ, R, SPARSE>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
 }
 
@@ -267,7 +278,7 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const Sm
 
 template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
 hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const SmacRow *rows,
-                      const int2 *tiles, hipStream_t s) {
+                      const SmacTile *tiles, hipStream_t s) {
     using C = SmacCfg<BX, A, TY, TZ>;
     if (g.n_rows <= 0 || g.n_tiles <= 0) return hipSuccess;
     const int64_t nwg = (int64_t)g.n_freq * g.n_tiles;
@@ -285,8 +296,8 @@ hipError_t launch_batch_cfg(const SmacJob *jobs, int n_jobs, int64_t total_wg, h
     return hipGetLastError();
 }
 
-// Template per row length: (A, TY, TZ) = (8, 8, 8) for bx = 8, (8, 16, 8) for
-// bx = 16 and (16, 16, 8) for bx = 32.
+// Template per row length: (A, TY, TZ) = (8, 8, 8) for bx = 8 and (8, 16, 8)
+// for bx = 16 (longer rows are cut into 16-wide segments by the runtime).
 template <typename F> hipError_t dispatch(int bx, bool fp32, bool sparse, const F &f) {
     auto pick = [&](auto bxc, auto ac, auto tyc, auto tzc) -> hipError_t {
         constexpr int BX = decltype(bxc)::value, A = decltype(ac)::value, TY = decltype(tyc)::value,
@@ -299,11 +310,9 @@ template <typename F> hipError_t dispatch(int bx, bool fp32, bool sparse, const 
     };
     using I8 = std::integral_constant<int, 8>;
     using I16 = std::integral_constant<int, 16>;
-    using I32 = std::integral_constant<int, 32>;
     switch (bx) {
     case 8: return pick(I8{}, I8{}, I8{}, I8{});
     case 16: return pick(I16{}, I8{}, I16{}, I8{});
-    case 32: return pick(I32{}, I16{}, I16{}, I8{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -324,7 +333,7 @@ struct SingleLaunch {
     void *U;
     const void *K;
     const SmacRow *rows;
-    const int2 *tiles;
+    const SmacTile *tiles;
     hipStream_t s;
     template <int BX, int A, int TY, int TZ, typename R, bool SP> hipError_t operator()() const {
         return launch_cfg<BX, A, TY, TZ, R, SP>(g, F, U, K, rows, tiles, s);
@@ -339,13 +348,17 @@ hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs
 }
 
 int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
+int smac_seg_len(int bx) {
+    (void)bx;
+    return 8;
+}
 int smac_tile_z(int bx) {
     (void)bx;
     return 8;
 }
 
 hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
-                       const SmacRow *rows, const int2 *tiles, hipStream_t s) {
+                       const SmacRow *rows, const SmacTile *tiles, hipStream_t s) {
     return dispatch(g.bx, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, s});
 }
 
