@@ -74,6 +74,7 @@ struct SmacGeom {
     int rs;                 // slots per row of the padded box (multiple of bx)
     int tx0, sx0;           // x offsets of this part's target / source segment
     int accum;              // add into Uhat instead of storing
+    int64_t fstride;        // elements between the components of Fhat / Uhat
 };
 // One convolution of a batched spectral-MAC launch (device-resident table).
 struct SmacJob {
@@ -90,11 +91,12 @@ hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs
 int smac_tile_y(int bx);
 int smac_tile_z(int bx);
 int smac_seg_len(int bx);   // A: targets per lane
-// Uhat[omega][t] = sum_s K[omega][t - s] * Fhat[omega][s] over every source row
+// Uhat[c][omega][t] = sum_s K[omega][t - s] * Fhat[c][omega][s] for the nc
+// (1..3) components c, over every source row
 // and every target slot of each tile; source positions outside a row's mask
 // are skipped when `sparse` (their Fhat must be zero either way).
-hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
-                       const SmacRow *rows, const SmacTile *tiles, hipStream_t s);
+hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const void *Fhat, void *Uhat,
+                       const void *Ktab, const SmacRow *rows, const SmacTile *tiles, hipStream_t s);
 
 // ---- composite-grid kernels (lgf_composite.hip) ----
 // dst block b = src block b with the octants flagged in cover[b] zeroed.

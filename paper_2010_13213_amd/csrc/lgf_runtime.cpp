@@ -342,6 +342,7 @@ SmacGeom conv_geom(const Conv &c, const SubConv &p) {
     g.tx0 = p.tx0;
     g.sx0 = p.sx0;
     g.accum = p.accum ? 1 : 0;
+    g.fstride = 0;
     return g;
 }
 
@@ -457,10 +458,9 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
     return op;
 }
 
-void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
-                   hipStream_t s) {
+void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, const double *ut, double *rin,
+                   double *cut, double dx, int accumulate, hipStream_t s) {
     const int nb = plan->nb;
-    double *ut = (double *)plan->ws_ut.ptr, *cut = (double *)plan->ws_ush.ptr, *rin = (double *)plan->ws_rho.ptr;
     RefGeom g = op.geom;
     g.dx = dx;
     StageTimer t(plan->ctx, 3, s);
@@ -474,16 +474,24 @@ void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *
                   "outside sources");
 }
 
-void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
-            hipStream_t s) {
-    if (!op.refined) {
-        run_conv(plan, *op.c64, src, dst, dx, accumulate, s);
-        return;
+void run_op(lgf_plan *plan, const ConvOp &op, const double *src, int64_t sstride, double *dst, int64_t dstride,
+            int nc, double dx, int accumulate, hipStream_t s) {
+    for (int c0 = 0; c0 < nc; c0 += kMacComponents) {
+        const int ng = std::min(kMacComponents, nc - c0);
+        const double *sg = src + (size_t)c0 * sstride;
+        double *dg = dst + (size_t)c0 * dstride;
+        if (!op.refined) {
+            run_conv(plan, *op.c64, sg, sstride, dg, dstride, ng, dx, accumulate, s);
+            continue;
+        }
+        double *ut = (double *)plan->ws_ut.ptr, *rin = (double *)plan->ws_rho.ptr, *cut = (double *)plan->ws_ush.ptr;
+        run_conv(plan, *op.c32, sg, sstride, ut, plan->ut_len, ng, dx, 0, s);
+        for (int c = 0; c < ng; ++c)
+            refine_middle(plan, op, sg + (size_t)c * sstride, dg + (size_t)c * dstride, ut + (size_t)c * plan->ut_len,
+                          rin + (size_t)c * plan->ut_len, cut + (size_t)c * plan->cut_len, dx, accumulate, s);
+        run_conv(plan, *op.c64, cut, plan->cut_len, dg, dstride, ng, dx, 1, s);
+        run_conv(plan, *op.ccorr, rin, plan->ut_len, dg, dstride, ng, dx, 1, s);
     }
-    run_conv(plan, *op.c32, src, (double *)plan->ws_ut.ptr, dx, 0, s);
-    refine_middle(plan, op, src, dst, dx, accumulate, s);
-    run_conv(plan, *op.c64, (const double *)plan->ws_ush.ptr, dst, dx, 1, s);
-    run_conv(plan, *op.ccorr, (const double *)plan->ws_rho.ptr, dst, dx, 1, s);
 }
 
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {
@@ -495,52 +503,65 @@ void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {
         }
     if (nt == 0) return;
     const int64_t nb3 = (int64_t)plan->nb * plan->nb * plan->nb;
-    plan->ws_ut.alloc(plan->ctx, sizeof(double) * nt * nb3, "u float32 pass");
-    plan->ws_rho.alloc(plan->ctx, sizeof(double) * nt * nb3, "refinement residual");
-    plan->ws_ush.alloc(plan->ctx, sizeof(double) * std::max<int64_t>(1, ncut) * nb3, "cut residual");
+    plan->ut_len = nt * nb3;
+    plan->cut_len = std::max<int64_t>(1, ncut) * nb3;
+    plan->ws_ut.alloc(plan->ctx, sizeof(double) * plan->ut_len * plan->mac_nc, "u float32 pass");
+    plan->ws_rho.alloc(plan->ctx, sizeof(double) * plan->ut_len * plan->mac_nc, "refinement residual");
+    plan->ws_ush.alloc(plan->ctx, sizeof(double) * plan->cut_len * plan->mac_nc, "cut residual");
 }
 
-// Spectral workspace large enough for every convolution of the plan.
+// Spectral workspace large enough for every convolution of the plan, for
+// mac_nc components.
 void plan_alloc_spectral(lgf_plan *plan) {
     size_t need = 0;
     for (const Conv *c : plan->convs_view) {
         const size_t elem = c->fp32 ? 8 : 16;
         need = std::max(need, elem * (size_t)c->spec->n_freq * (size_t)c->n_slots);
     }
+    need *= (size_t)plan->mac_nc;
     plan->Fhat.alloc(plan->ctx, need, "Fhat workspace");
     plan->Uhat.alloc(plan->ctx, need, "Uhat workspace");
 }
 
-// Run one convolution: dst (+)= dx^2 * G * src on the conv's blocks.
-void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,
-              hipStream_t s) {
+// Run one convolution for nc <= kMacComponents components:
+// dst_c (+)= dx^2 * G * src_c on the conv's blocks, component c at
+// src + c*sstride / dst + c*dstride, spectra at Fhat / Uhat + c*fs.
+void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride, double *dst, int64_t dstride,
+              int nc, double dx, int accumulate, hipStream_t s) {
     const int nb = plan->nb;
     const double N3 = 8.0 * nb * nb * nb;
+    const size_t elem = c.fp32 ? 8 : 16;
+    const int64_t fs = (int64_t)c.spec->n_freq * c.n_slots;   // elements per component region
+    if (nc < 1 || nc > kMacComponents || (size_t)nc * fs * elem > plan->Fhat.bytes)
+        throw Failure(LGF_E_INVALID, "internal: component count outside the spectral workspace");
     // empty slots of Fhat must read as zero; the forward FFT writes only
     // occupied slots, so clear when another slot map used the buffer last
     if (plan->fhat_conv != &c) {
         hip_check(hipMemsetAsync(plan->Fhat.ptr, 0, plan->Fhat.bytes, s), "clear Fhat");
         plan->fhat_conv = &c;
     }
-    {
+    for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 0, s);
-        hip_check(block_fft_forward(nb, c.fp32, src, (const int64_t *)c.d_src_off.ptr,
-                                    (const int *)c.d_src_slot.ptr, c.n_src, plan->Fhat.ptr, c.n_slots, 1.0, s),
+        hip_check(block_fft_forward(nb, c.fp32, src + (size_t)k * sstride, (const int64_t *)c.d_src_off.ptr,
+                                    (const int *)c.d_src_slot.ptr, c.n_src, (char *)plan->Fhat.ptr + k * fs * elem,
+                                    c.n_slots, 1.0, s),
                   "forward block FFT");
     }
     if (c.parts.empty())   // no source or no target: the convolution is zero
         hip_check(hipMemsetAsync(plan->Uhat.ptr, 0, plan->Uhat.bytes, s), "clear Uhat");
     for (const auto &p : c.parts) {
         StageTimer t(plan->ctx, 1, s);
-        const SmacGeom g = conv_geom(c, *p);
-        hip_check(smac_launch(g, c.fp32, p->sparse, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
+        SmacGeom g = conv_geom(c, *p);
+        g.fstride = fs;
+        hip_check(smac_launch(g, c.fp32, p->sparse, nc, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
                               (const SmacRow *)p->d_rows.ptr, (const SmacTile *)p->d_tiles.ptr, s),
                   "spectral MAC");
     }
-    {
+    for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 2, s);
-        hip_check(block_fft_inverse(nb, c.fp32, plan->Uhat.ptr, c.n_slots, (const int *)c.d_tgt_slot.ptr,
-                                    (const int64_t *)c.d_tgt_off.ptr, c.n_tgt, dst, dx * dx / N3, accumulate, s),
+        hip_check(block_fft_inverse(nb, c.fp32, (char *)plan->Uhat.ptr + k * fs * elem, c.n_slots,
+                                    (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
+                                    dst + (size_t)k * dstride, dx * dx / N3, accumulate, s),
                   "inverse block FFT");
     }
 }

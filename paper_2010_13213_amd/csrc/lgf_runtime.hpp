@@ -23,6 +23,9 @@ struct Failure : std::runtime_error {
 
 void hip_check(hipError_t e, const char *what);
 
+// components that share one spectral-MAC launch (the MAC's right-hand sides)
+constexpr int kMacComponents = 3;
+
 struct lgf_context_impl;
 }  // namespace lgf
 
@@ -167,7 +170,10 @@ struct lgf_plan {
     std::vector<const lgf::Conv *> convs_view;              // every convolution of the plan
     lgf::DeviceBuffer ws_fhat, ws_F, ws_psi[2], ws_ppsi, ws_srcF, ws_srcf;
     lgf::DeviceBuffer ws_ut, ws_ush, ws_rho;               // refinement workspaces
-    lgf::DeviceBuffer Fhat, Uhat;
+    int mac_nc = 1;                                // components per MAC launch: min(nc, 3)
+    int64_t ut_len = 0, cut_len = 0;               // elements per component in ws_ut / ws_rho and ws_ush
+    int64_t dom_len = 0, ext_len = 0;              // elements per component in ws_psi and ws_ppsi / ws_src*
+    lgf::DeviceBuffer Fhat, Uhat;                  // mac_nc component regions each
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     size_t workspace_bytes() const;
 };
@@ -193,11 +199,16 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32);
 void plan_alloc_spectral(lgf_plan *plan);
 std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool refine);
+// Refinement workspaces (per component region) for the plan's refined ops.
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops);
-void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
-                   hipStream_t s);
-void run_op(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, double dx, int accumulate,
-            hipStream_t s);
-void run_conv(lgf_plan *plan, const Conv &c, const double *src, double *dst, double dx, int accumulate,
-              hipStream_t s);
+// One component's residual step of a refined op: w into dst, rin / cut from
+// ut (see lgf_refine.hip); ut, rin, cut are that component's regions.
+void refine_middle(lgf_plan *plan, const ConvOp &op, const double *src, double *dst, const double *ut, double *rin,
+                   double *cut, double dx, int accumulate, hipStream_t s);
+// dst (+)= dx^2 G * src for nc components (component c at src + c*sstride,
+// dst + c*dstride); groups of up to kMacComponents share one MAC launch.
+void run_op(lgf_plan *plan, const ConvOp &op, const double *src, int64_t sstride, double *dst, int64_t dstride,
+            int nc, double dx, int accumulate, hipStream_t s);
+void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride, double *dst, int64_t dstride,
+              int nc, double dx, int accumulate, hipStream_t s);
 }  // namespace lgf

@@ -60,6 +60,7 @@ void build_schedule(lgf_plan *p) {
     const bool refine = p->prec == LGF_FP32_REFINE;
     const int nb = p->nb, K = p->K;
     const int64_t nb3 = (int64_t)nb * nb * nb;
+    p->mac_nc = std::min(p->nc, kMacComponents);
     if (K == 1) {
         p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
         plan_alloc_refine(p, {p->op0.get()});
@@ -206,14 +207,17 @@ void build_schedule(lgf_plan *p) {
             upload(ctx, L.d_cp_dst, cp_d, "copy offsets");
         }
     }
-    // workspaces (one component at a time)
-    p->ws_fhat.alloc(ctx, sizeof(double) * p->comp_len, "masked sources");
-    p->ws_F.alloc(ctx, sizeof(double) * p->comp_len, "cumulative sources");
-    p->ws_psi[0].alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_dom) * nb3, "psi");
-    p->ws_psi[1].alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_dom) * nb3, "psi");
-    p->ws_ppsi.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "P psi");
-    p->ws_srcF.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
-    p->ws_srcf.alloc(ctx, sizeof(double) * std::max<int64_t>(1, max_ext) * nb3, "sources");
+    // workspaces: mac_nc component regions each (the components of one MAC group)
+    const int64_t m = p->mac_nc;
+    p->dom_len = std::max<int64_t>(1, max_dom) * nb3;
+    p->ext_len = std::max<int64_t>(1, max_ext) * nb3;
+    p->ws_fhat.alloc(ctx, sizeof(double) * p->comp_len * m, "masked sources");
+    p->ws_F.alloc(ctx, sizeof(double) * p->comp_len * m, "cumulative sources");
+    p->ws_psi[0].alloc(ctx, sizeof(double) * p->dom_len * m, "psi");
+    p->ws_psi[1].alloc(ctx, sizeof(double) * p->dom_len * m, "psi");
+    p->ws_ppsi.alloc(ctx, sizeof(double) * p->ext_len * m, "P psi");
+    p->ws_srcF.alloc(ctx, sizeof(double) * p->ext_len * m, "sources");
+    p->ws_srcf.alloc(ctx, sizeof(double) * p->ext_len * m, "sources");
     std::vector<const ConvOp *> ops;
     for (int k = 0; k < K; ++k) {
         ops.push_back(p->lv[k]->convF.get());
@@ -223,29 +227,39 @@ void build_schedule(lgf_plan *p) {
     plan_alloc_spectral(p);
 }
 
+// The components run in groups of up to kMacComponents: every step of the
+// recursion is applied to each component of the group, and each
+// convolution takes the whole group in one MAC launch.
 static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream_t s) {
     const int K = p->K, nb = p->nb;
+    const int64_t CL = p->comp_len, DL = p->dom_len, EL = p->ext_len;
     double *FH = (double *)p->ws_fhat.ptr, *FC = (double *)p->ws_F.ptr;
-    for (int comp = 0; comp < p->nc; ++comp) {
-        const double *fc = f + (size_t)comp * p->comp_len;
-        double *uc = u + (size_t)comp * p->comp_len;
+    double *PP = (double *)p->ws_ppsi.ptr, *SF = (double *)p->ws_srcF.ptr, *Sf = (double *)p->ws_srcf.ptr;
+    for (int c0 = 0; c0 < p->nc; c0 += kMacComponents) {
+        const int ng = std::min(kMacComponents, p->nc - c0);
+        const double *fg = f + (size_t)c0 * CL;
+        double *ug = u + (size_t)c0 * CL;
         StageTimer tm(p->ctx, 3, s);
         // f^_k and F_k
-        for (int k = 0; k < K; ++k) {
-            const LevelSched &L = *p->lv[k];
-            hip_check(mask_blocks(nb, fc, FH, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
-                                  (const unsigned char *)L.d_cover.ptr, L.n_own, s),
-                      "mask sources");
-            hip_check(copy_blocks(nb, FH, FC, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
-                                  L.n_own, s),
-                      "copy sources");
-        }
-        for (int k = K - 2; k >= 0; --k) {
-            const LevelSched &L = *p->lv[k];
-            hip_check(coarsen_mean8(nb, FC, FC, (const int64_t *)L.d_cf_fine.ptr, (const int64_t *)L.d_cf_coarse.ptr,
-                                    (const unsigned char *)L.d_cf_oct.ptr, L.n_cf, s),
-                      "coarsen");
-        }
+        for (int c = 0; c < ng; ++c)
+            for (int k = 0; k < K; ++k) {
+                const LevelSched &L = *p->lv[k];
+                hip_check(mask_blocks(nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                      (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr, L.n_own,
+                                      s),
+                          "mask sources");
+                hip_check(copy_blocks(nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                      (const int64_t *)L.d_own_off.ptr, L.n_own, s),
+                          "copy sources");
+            }
+        for (int c = 0; c < ng; ++c)
+            for (int k = K - 2; k >= 0; --k) {
+                const LevelSched &L = *p->lv[k];
+                hip_check(coarsen_mean8(nb, FC + c * CL, FC + c * CL, (const int64_t *)L.d_cf_fine.ptr,
+                                        (const int64_t *)L.d_cf_coarse.ptr, (const unsigned char *)L.d_cf_oct.ptr,
+                                        L.n_cf, s),
+                          "coarsen");
+            }
         int cur = 0;   // psi ping-pong
         for (int k = 0; k < K; ++k) {
             const LevelSched &L = *p->lv[k];
@@ -253,29 +267,34 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
             double *psi_prev = (double *)p->ws_psi[cur].ptr;
             double *psi_next = (double *)p->ws_psi[cur ^ 1].ptr;
             if (k == 0) {
-                run_op(p, *L.convF, FC, uc, dxk, 0, s);
-                if (L.convPsi) run_op(p, *L.convPsi, FH, psi_next, dxk, 0, s);
+                run_op(p, *L.convF, FC, CL, ug, CL, ng, dxk, 0, s);
+                if (L.convPsi) run_op(p, *L.convPsi, FH, CL, psi_next, DL, ng, dxk, 0, s);
             } else {
-                hip_check(correction_source(nb, L.corr, psi_prev, (const int *)L.d_cmap.ptr, (const int *)L.d_fblk.ptr,
-                                            (const int64_t *)L.d_ext_own.ptr, FC, FH, (double *)p->ws_ppsi.ptr,
-                                            (double *)p->ws_srcF.ptr, (double *)p->ws_srcf.ptr, L.n_ext, s),
-                          "correction source");
-                hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, uc, (const int64_t *)L.d_cu_src.ptr,
-                                      (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
-                          "P psi -> phi");
-                run_op(p, *L.convF, (const double *)p->ws_srcF.ptr, uc, dxk, 1, s);
+                for (int c = 0; c < ng; ++c) {
+                    hip_check(correction_source(nb, L.corr, psi_prev + c * DL, (const int *)L.d_cmap.ptr,
+                                                (const int *)L.d_fblk.ptr, (const int64_t *)L.d_ext_own.ptr,
+                                                FC + c * CL, FH + c * CL, PP + c * EL, SF + c * EL, Sf + c * EL,
+                                                L.n_ext, s),
+                              "correction source");
+                    hip_check(copy_blocks(nb, PP + c * EL, ug + c * CL, (const int64_t *)L.d_cu_src.ptr,
+                                          (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
+                              "P psi -> phi");
+                }
+                run_op(p, *L.convF, SF, EL, ug, CL, ng, dxk, 1, s);
                 if (L.convPsi) {
-                    hip_check(copy_blocks(nb, (const double *)p->ws_ppsi.ptr, psi_next,
-                                          (const int64_t *)L.d_cp_src.ptr, (const int64_t *)L.d_cp_dst.ptr, L.n_dom,
-                                          s),
-                              "P psi -> psi");
-                    run_op(p, *L.convPsi, (const double *)p->ws_srcf.ptr, psi_next, dxk, 1, s);
+                    for (int c = 0; c < ng; ++c)
+                        hip_check(copy_blocks(nb, PP + c * EL, psi_next + c * DL, (const int64_t *)L.d_cp_src.ptr,
+                                              (const int64_t *)L.d_cp_dst.ptr, L.n_dom, s),
+                                  "P psi -> psi");
+                    run_op(p, *L.convPsi, Sf, EL, psi_next, DL, ng, dxk, 1, s);
                 }
             }
             if (L.any_cover)
-                hip_check(mask_blocks(nb, uc, uc, (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
-                                      (const unsigned char *)L.d_cover.ptr, L.n_own, s),
-                          "restrict phi");
+                for (int c = 0; c < ng; ++c)
+                    hip_check(mask_blocks(nb, ug + c * CL, ug + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                          (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
+                                          L.n_own, s),
+                              "restrict phi");
             cur ^= 1;
         }
     }
@@ -286,8 +305,7 @@ static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
         enqueue_composite(p, f, u, s);
         return;
     }
-    for (int comp = 0; comp < p->nc; ++comp)
-        run_op(p, *p->op0, f + (size_t)comp * p->comp_len, u + (size_t)comp * p->comp_len, p->dx0, 0, s);
+    run_op(p, *p->op0, f, p->comp_len, u, p->comp_len, p->nc, p->dx0, 0, s);
 }
 
 void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report *rep) {
@@ -494,7 +512,8 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
                 lgf_plan *p = plans[i];
                 if (comp >= p->nc || !p->op0->refined) continue;
                 refine_middle(p, *p->op0, f[i] + (size_t)comp * p->comp_len, u[i] + (size_t)comp * p->comp_len,
-                              p->dx0, 0, s);
+                              (const double *)p->ws_ut.ptr, (double *)p->ws_rho.ptr, (double *)p->ws_ush.ptr, p->dx0,
+                              0, s);
             }
             run_conv_batch(ctx, b1, s);
             run_conv_batch(ctx, b2, s);

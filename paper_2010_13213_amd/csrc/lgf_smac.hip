@@ -30,6 +30,11 @@
 // loaded kernel value across the lane's A targets, and the source row F is
 // read by all lanes from one LDS address (broadcast).
 //
+// Right-hand sides: up to three components with the same sources and
+// targets (a vector Poisson solve) go through one launch; every kernel row
+// staged in LDS then serves all of them, dividing the per-row cost of the
+// ring, the barrier and the window reads by the component count.
+//
 // Occupancy: the ring is (TY+1)(TZ+1)(2 bx - 1) complex values.  For bx = 16
 // in float64 a 16 x 8 tile needs 76 KB, so two workgroups share a CU's
 // 160 KB and one's barrier is covered by the other's arithmetic.  The LDS
@@ -59,14 +64,14 @@ template <int BX, int A, int TY, int TZ> struct SmacCfg {
     static constexpr int PER = (PLANE + NT - 1) / NT;          // per-lane prefetch slots
 };
 
-template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE, int NC>
 __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__restrict__ Fhat,
                                           cplx<R> *__restrict__ Uhat, const cplx<R> *__restrict__ Ktab,
                                           const SmacRow *__restrict__ rows, const SmacTile *__restrict__ tiles, int64_t wg) {
     using C = SmacCfg<BX, A, TY, TZ>;
     constexpr int KW = C::KW, SY = C::SY, SZ = C::SZ, NT = C::NT;
     __shared__ cplx<R> kbuf[SY * SZ * KW];
-    __shared__ cplx<R> frow[2][BX];
+    __shared__ cplx<R> frow[2][NC][BX];
 
     // the tiles of one frequency are consecutive work items, and consecutive
     // frequencies form groups of four whose reflected offsets read the same
@@ -110,9 +115,12 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     auto kload = [&](int dy, int dz, int dxi) -> cplx<R> { return kfix(kraw(dy, dz, dxi), dxi); };
     auto lds = [&](int dy, int dz, int dxi) -> int { return (pmod(dy, SY) * SZ + pmod(dz, SZ)) * KW + dxi; };
 
-    cplx<R> acc[A];
+    // NC right-hand sides (components) share every kernel row
+    cplx<R> acc[NC][A];
 #pragma unroll
-    for (int i = 0; i < A; ++i) acc[i] = cmake<R>((R)0, (R)0);
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < A; ++i) acc[c][i] = cmake<R>((R)0, (R)0);
 
     // full window load for row 0
     int sy = rows[0].y, sz = rows[0].z;
@@ -124,7 +132,8 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
             const int dy = dy0 + q % TY, dz = dz0 + q / TY;
             kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
         }
-        for (int e = l; e < BX; e += NT) frow[0][e] = Ff[((size_t)sz * g.ey + sy) * g.rs + g.sx0 + e];
+        for (int e = l; e < NC * BX; e += NT)
+            frow[0][e / BX][e % BX] = Ff[(size_t)(e / BX) * g.fstride + ((size_t)sz * g.ey + sy) * g.rs + g.sx0 + e % BX];
     }
     __syncthreads();
 
@@ -164,7 +173,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     pre[p] = kraw(dy, dz, dxi);
                 }
             }
-            if (l < BX) fpre = Ff[((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + l];
+            if (l < NC * BX) fpre = Ff[(size_t)(l / BX) * g.fstride + ((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + l % BX];
         }
 
         // compute: U[i] += K[x0 + i - j] * F[j], with a sliding register
@@ -177,37 +186,51 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
             // sixteen reads use immediate offsets from one address
             int vzero;
             asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
-            const cplx<R> *fr = frow[buf] + vzero;
+            const cplx<R> *fr = &frow[buf][0][0] + vzero;
             cplx<R> kw[A];
 #pragma unroll
             for (int i = 0; i < A; ++i) kw[i] = krow[i];
-            cplx<R> fj = fr[0];
-            cplx<R> kn1 = krow[-1], fn1 = fr[1];
-            cplx<R> kn2 = kn1, fn2 = fn1;
+            cplx<R> fj[NC], fn1[NC], fn2[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                fj[c] = fr[c * BX];
+                fn1[c] = fr[c * BX + 1];
+                fn2[c] = fn1[c];
+            }
+            cplx<R> kn1 = krow[-1];
+            cplx<R> kn2 = kn1;
 #pragma unroll
             for (int j = 0; j < BX; ++j) {
                 if (j + 2 < BX) {
                     kn2 = krow[-(j + 2)];
-                    fn2 = fr[j + 2];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) fn2[c] = fr[c * BX + j + 2];
                 }
                 // on sparse rows a source position without a block is
                 // skipped (uniform branch; dense rows take no branch)
                 if (!SPARSE || ((msk >> j) & 1u)) {
 #pragma unroll
-                    for (int i = 0; i < A; ++i) acc[i] = cmac(acc[i], kw[i], fj);
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int i = 0; i < A; ++i) acc[c][i] = cmac(acc[c][i], kw[i], fj[c]);
                 }
                 if (j + 1 < BX) {
 #pragma unroll
                     for (int i = A - 1; i >= 1; --i) kw[i] = kw[i - 1];
                     kw[0] = kn1;
-                    fj = fn1;
                     kn1 = kn2;
-                    fn1 = fn2;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        fj[c] = fn1[c];
+                        fn1[c] = fn2[c];
+                    }
                 }
                 // keep each step's products here (IR passes would otherwise
                 // sink them below the prefetch stores)
 #pragma unroll
-                for (int i = 0; i < A; ++i) asm volatile("" : "+v"(acc[i].x), "+v"(acc[i].y)::"memory");
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int i = 0; i < A; ++i) asm volatile("" : "+v"(acc[c][i].x), "+v"(acc[c][i].y)::"memory");
             }
         }
 
@@ -223,7 +246,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     kbuf[lds(dy, dz, dxi)] = kfix(pre[p], dxi);
                 }
             }
-            if (l < BX) frow[buf ^ 1][l] = fpre;
+            if (l < NC * BX) frow[buf ^ 1][l / BX][l % BX] = fpre;
             __syncthreads();
         } else if (kind == 3) {
             __syncthreads();
@@ -233,7 +256,9 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                 const int dy = dy0 + q % TY, dz = dz0 + q / TY;
                 kbuf[lds(dy, dz, dxi)] = kload(dy, dz, dxi);
             }
-            for (int e = l; e < BX; e += NT) frow[buf ^ 1][e] = Ff[((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + e];
+            for (int e = l; e < NC * BX; e += NT)
+                frow[buf ^ 1][e / BX][e % BX] =
+                    Ff[(size_t)(e / BX) * g.fstride + ((size_t)nsz * g.ey + nsy) * g.rs + g.sx0 + e % BX];
             __syncthreads();
         }
         sy = nsy;
@@ -242,22 +267,26 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     }
 
     if (active) {
-        cplx<R> *Uf = Uhat + (size_t)freq * g.n_slots + ((size_t)tz * g.ey + ty) * g.rs + g.tx0 + x0;
-        if (g.accum) {
 #pragma unroll
-            for (int i = 0; i < A; ++i) Uf[i] = cmake<R>(Uf[i].x + acc[i].x, Uf[i].y + acc[i].y);
-        } else {
+        for (int c = 0; c < NC; ++c) {
+            cplx<R> *Uf = Uhat + (size_t)c * g.fstride + (size_t)freq * g.n_slots + ((size_t)tz * g.ey + ty) * g.rs +
+                          g.tx0 + x0;
+            if (g.accum) {
 #pragma unroll
-            for (int i = 0; i < A; ++i) Uf[i] = acc[i];
+                for (int i = 0; i < A; ++i) Uf[i] = cmake<R>(Uf[i].x + acc[c][i].x, Uf[i].y + acc[c][i].y);
+            } else {
+#pragma unroll
+                for (int i = 0; i < A; ++i) Uf[i] = acc[c][i];
+            }
         }
     }
 }
 
-template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE, int NC>
 __global__ void __launch_bounds__((BX / A) * TY * TZ)
     smac_kernel(SmacGeom g, const cplx<R> *__restrict__ Fhat, cplx<R> *__restrict__ Uhat,
                 const cplx<R> *__restrict__ Ktab, const SmacRow *__restrict__ rows, const SmacTile *__restrict__ tiles) {
-    smac_body<BX, A, TY, TZ, R, SPARSE>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
+    smac_body<BX, A, TY, TZ, R, SPARSE, NC>(g, Fhat, Uhat, Ktab, rows, tiles, xcd_order(blockIdx.x, gridDim.x));
 }
 
 // Several independent convolutions of one template in one grid: workgroup w
@@ -272,17 +301,17 @@ __global__ void __launch_bounds__((BX / A) * TY * TZ) smac_batch_kernel(const Sm
         else hi = mid - 1;
     }
     const SmacJob &j = jobs[lo];
-    smac_body<BX, A, TY, TZ, R, SPARSE>(j.g, (const cplx<R> *)j.F, (cplx<R> *)j.U, (const cplx<R> *)j.K, j.rows, j.tiles,
-                                w - j.wg_begin);
+    smac_body<BX, A, TY, TZ, R, SPARSE, 1>(j.g, (const cplx<R> *)j.F, (cplx<R> *)j.U, (const cplx<R> *)j.K, j.rows,
+                                           j.tiles, w - j.wg_begin);
 }
 
-template <int BX, int A, int TY, int TZ, typename R, bool SPARSE>
+template <int BX, int A, int TY, int TZ, typename R, bool SPARSE, int NC>
 hipError_t launch_cfg(const SmacGeom &g, const void *F, void *U, const void *K, const SmacRow *rows,
                       const SmacTile *tiles, hipStream_t s) {
     using C = SmacCfg<BX, A, TY, TZ>;
     if (g.n_rows <= 0 || g.n_tiles <= 0) return hipSuccess;
     const int64_t nwg = (int64_t)g.n_freq * g.n_tiles;
-    hipLaunchKernelGGL((smac_kernel<BX, A, TY, TZ, R, SPARSE>), dim3((unsigned)nwg), dim3(C::NT), 0, s, g,
+    hipLaunchKernelGGL((smac_kernel<BX, A, TY, TZ, R, SPARSE, NC>), dim3((unsigned)nwg), dim3(C::NT), 0, s, g,
                        (const cplx<R> *)F, (cplx<R> *)U, (const cplx<R> *)K, rows, tiles);
     return hipGetLastError();
 }
@@ -334,9 +363,15 @@ struct SingleLaunch {
     const void *K;
     const SmacRow *rows;
     const SmacTile *tiles;
+    int nc;
     hipStream_t s;
     template <int BX, int A, int TY, int TZ, typename R, bool SP> hipError_t operator()() const {
-        return launch_cfg<BX, A, TY, TZ, R, SP>(g, F, U, K, rows, tiles, s);
+        switch (nc) {
+        case 1: return launch_cfg<BX, A, TY, TZ, R, SP, 1>(g, F, U, K, rows, tiles, s);
+        case 2: return launch_cfg<BX, A, TY, TZ, R, SP, 2>(g, F, U, K, rows, tiles, s);
+        case 3: return launch_cfg<BX, A, TY, TZ, R, SP, 3>(g, F, U, K, rows, tiles, s);
+        default: return hipErrorInvalidValue;
+        }
     }
 };
 
@@ -357,9 +392,9 @@ int smac_tile_z(int bx) {
     return 8;
 }
 
-hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, const void *Fhat, void *Uhat, const void *Ktab,
-                       const SmacRow *rows, const SmacTile *tiles, hipStream_t s) {
-    return dispatch(g.bx, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, s});
+hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const void *Fhat, void *Uhat,
+                       const void *Ktab, const SmacRow *rows, const SmacTile *tiles, hipStream_t s) {
+    return dispatch(g.bx, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, nc, s});
 }
 
 }  // namespace lgf

@@ -123,6 +123,24 @@ def test_long_rows_use_the_wide_template(gpu_ctx):
     assert rel_l2(u, ref) < TOL64
 
 
+@pytest.mark.parametrize("ex,seed", [(46, 4), (60, 5)])
+def test_rows_longer_than_32_blocks_run_as_segment_pairs(gpu_ctx, ex, seed):
+    """x extents of 46 and 60 blocks: 3 and 4 sixteen-wide segments, every
+    (target, source) segment pair a separate phase-ordered part, with holes
+    in the rows (sparse parts) and one full row."""
+    rng = np.random.default_rng(seed)
+    nb = 8
+    full = [(x, 0, 0) for x in range(ex)]
+    holes = [(x, y, z) for z in range(2) for y in range(1, 3) for x in range(ex) if rng.uniform() < 0.3]
+    blocks = np.array(full + holes) + np.array([-7, 2, 1])
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    u = gpu_solve(gpu_ctx, _problem(blocks, nb, f, 0.5))[0]
+    tgt = rng.choice(len(c), 2500, replace=False)
+    ref = direct.direct_sum(c, f, c[tgt], 0.5)
+    assert rel_l2(u[tgt], ref) < TOL64
+
+
 def test_single_block_and_repeat_is_bitwise_stable(gpu_ctx):
     import torch
     from paper_2010_13213_amd import lgf
