@@ -83,6 +83,9 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     const int l = threadIdx.x;
     // lanes past n_lanes only help with the cooperative loads
     const bool active = l < tl.n_lanes;
+    // a wave without targets (lanes are packed from 0) only helps with the
+    // cooperative loads and skips the arithmetic (uniform per wave)
+    const bool wave_busy = (l & ~63) < tl.n_lanes;
     const int code = active ? g.lanes[tl.lane_off + l] : 0;
     const int seg = code & 255, tyl = (code >> 8) & 255, tzl = code >> 16;
     const int ty = ty0 + tyl, tz = tz0 + tzl;
@@ -180,7 +183,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
         // window kw[i] = K[x0 + i - j] that gains one LDS value per step j;
         // the LDS reads of step j + 2 are issued at step j, so the reads of
         // all waves spread over the row instead of bunching after the barrier
-        {
+        if (wave_busy) {
             const cplx<R> *krow = &kbuf[lds(ty - sy, tz - sz, 0)] + x0 + BX - 1;
             // a per-lane base register for the broadcast F row, so that its
             // sixteen reads use immediate offsets from one address
