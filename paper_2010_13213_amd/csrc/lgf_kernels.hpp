@@ -75,6 +75,7 @@ struct SmacGeom {
     int tx0, sx0;           // x offsets of this part's target / source segment
     int accum;              // add into Uhat instead of storing
     int64_t fstride;        // elements between the components of Fhat / Uhat
+    int axis;               // 0: rows along lattice x; 1: rows along lattice y (x and y swapped)
 };
 // One convolution of a batched spectral-MAC launch (device-resident table).
 struct SmacJob {

@@ -201,15 +201,20 @@ static int roundup(int a, int m) { return (a + m - 1) / m * m; }
 // (ss - ts) mod n_seg, so the parts of one target segment never run in the
 // same launch; the first of them stores into Uhat, later ones add.  Empty
 // source segments of a row and empty target segments of a tile cost nothing.
-void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32) {
+void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
+                int axis) {
     lgf_context *ctx = plan->ctx;
     const int nb = plan->nb;
+    // coordinates in the MAC's frame: rows along x (axis 0) or along the
+    // lattice y axis (axis 1: x and y swapped)
+    c.axis = axis;
+    auto P = [axis](const Blk &b, int a) -> int { return (axis == 1 && a < 2) ? b.ijk[1 - a] : b.ijk[a]; };
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     for (const auto *v : {&src, &tgt})
         for (const auto &b : *v)
             for (int a = 0; a < 3; ++a) {
-                lo[a] = std::min(lo[a], b.ijk[a]);
-                hi[a] = std::max(hi[a], b.ijk[a]);
+                lo[a] = std::min(lo[a], P(b, a));
+                hi[a] = std::max(hi[a], P(b, a));
             }
     const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
     if (ex > 64 || ey > 64 || ez > 64)
@@ -226,7 +231,7 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     c.n_slots = (int64_t)rs * c.ey * c.ez;
     c.fp32 = fp32;
     auto slot_of = [&](const Blk &b) -> int {
-        return ((b.ijk[2] - lo[2]) * c.ey + (b.ijk[1] - lo[1])) * rs + (b.ijk[0] - lo[0]);
+        return ((P(b, 2) - lo[2]) * c.ey + (P(b, 1) - lo[1])) * rs + (P(b, 0) - lo[0]);
     };
     std::vector<int> s_slot, t_slot;
     std::vector<int64_t> s_off, t_off;
@@ -238,13 +243,13 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     for (const auto &b : src) {
         s_slot.push_back(slot_of(b));
         s_off.push_back(b.off);
-        const int x = b.ijk[0] - lo[0];
-        rowmask[x / bx][{b.ijk[2] - lo[2], b.ijk[1] - lo[1]}] |= 1u << (x % bx);
+        const int x = P(b, 0) - lo[0];
+        rowmask[x / bx][{P(b, 2) - lo[2], P(b, 1) - lo[1]}] |= 1u << (x % bx);
     }
     for (const auto &b : tgt) {
         t_slot.push_back(slot_of(b));
         t_off.push_back(b.off);
-        const int y = b.ijk[1] - lo[1], z = b.ijk[2] - lo[2], x = b.ijk[0] - lo[0];
+        const int y = P(b, 1) - lo[1], z = P(b, 2) - lo[2], x = P(b, 0) - lo[0];
         const int tzl = z % TZ, tyl = y % TY, seg = (x % bx) / A;
         tileseg[x / bx][{z / TZ * TZ, y / TY * TY}].insert((tzl * TY + tyl) * NSEG + seg);
     }
@@ -262,22 +267,74 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
             part->phase = ph;
             part->accum = stored[ts];
             stored[ts] = true;
-            // serpentine row order: z ascending, y alternating per z group
-            std::map<int, std::vector<int>> byz;
+            // Source row order.  Consecutive rows one step apart in y or z
+            // cost the MAC one new ring plane; any other step reloads the
+            // whole ring.  Two orders are built and the one with fewer
+            // reloads kept: the serpentine (z ascending, y alternating per z
+            // group) and a greedy walk that keeps stepping to a neighbouring
+            // row (same direction first) and jumps to the nearest row only
+            // when it has none.
             int64_t n_src_seg = 0;
+            std::vector<std::pair<int, int>> rowset;   // (y, z)
             for (auto &r : rowmask[ss]) {
-                byz[r.first.first].push_back(r.first.second);
+                rowset.push_back({r.first.second, r.first.first});
                 n_src_seg += __builtin_popcount(r.second);
             }
-            std::vector<SmacRow> rows;
-            int gi = 0;
-            for (auto &kv : byz) {
-                auto ys = kv.second;
-                std::sort(ys.begin(), ys.end());
-                if (gi & 1) std::reverse(ys.begin(), ys.end());
-                for (int y : ys) rows.push_back(SmacRow{y, kv.first, rowmask[ss][{kv.first, y}], 0});
-                ++gi;
+            auto jumps = [](const std::vector<std::pair<int, int>> &o) {
+                int n = 0;
+                for (size_t i = 1; i < o.size(); ++i)
+                    n += std::abs(o[i].first - o[i - 1].first) + std::abs(o[i].second - o[i - 1].second) != 1;
+                return n;
+            };
+            std::vector<std::pair<int, int>> serp;
+            {
+                std::map<int, std::vector<int>> byz;
+                for (auto &r : rowset) byz[r.second].push_back(r.first);
+                int gi = 0;
+                for (auto &kv : byz) {
+                    auto ys = kv.second;
+                    std::sort(ys.begin(), ys.end());
+                    if (gi & 1) std::reverse(ys.begin(), ys.end());
+                    for (int y : ys) serp.push_back({y, kv.first});
+                    ++gi;
+                }
             }
+            std::vector<std::pair<int, int>> walk;
+            {
+                std::set<std::pair<int, int>> left(rowset.begin(), rowset.end());
+                std::pair<int, int> cur = serp.front(), dir = {1, 0};
+                walk.push_back(cur);
+                left.erase(cur);
+                const std::pair<int, int> steps[4] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+                while (!left.empty()) {
+                    std::pair<int, int> nxt{INT32_MIN, INT32_MIN};
+                    const std::pair<int, int> ahead{cur.first + dir.first, cur.second + dir.second};
+                    if (left.count(ahead)) nxt = ahead;
+                    for (int q = 0; q < 4 && nxt.first == INT32_MIN; ++q) {
+                        const std::pair<int, int> c2{cur.first + steps[q].first, cur.second + steps[q].second};
+                        if (left.count(c2)) nxt = c2;
+                    }
+                    if (nxt.first == INT32_MIN) {   // jump to the nearest row left
+                        int best = INT32_MAX;
+                        for (auto &r : left) {
+                            const int d = std::abs(r.first - cur.first) + std::abs(r.second - cur.second);
+                            if (d < best) {
+                                best = d;
+                                nxt = r;
+                            }
+                        }
+                        dir = {1, 0};
+                    } else {
+                        dir = {nxt.first - cur.first, nxt.second - cur.second};
+                    }
+                    walk.push_back(nxt);
+                    left.erase(nxt);
+                    cur = nxt;
+                }
+            }
+            const auto &order = jumps(walk) < jumps(serp) ? walk : serp;
+            std::vector<SmacRow> rows;
+            for (auto &r : order) rows.push_back(SmacRow{r.first, r.second, rowmask[ss][{r.second, r.first}], 0});
             // lanes in (tz, ty, seg) order: a full tile gets lane l = (tzl * TY
             // + tyl) * NSEG + seg; tiles with more lanes than a workgroup split
             std::vector<SmacTile> tiles;
@@ -309,7 +366,9 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
         }
     c.n_src = (int)src.size();
     c.n_tgt = (int)tgt.size();
-    c.spec = get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1);
+    // the spectra table is indexed by lattice offsets
+    c.spec = axis == 1 ? get_spectra(ctx, nb, fp32, c.ey - 1, rs - 1, c.ez - 1)
+                       : get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1);
     c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
     c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
     c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
@@ -343,6 +402,7 @@ SmacGeom conv_geom(const Conv &c, const SubConv &p) {
     g.sx0 = p.sx0;
     g.accum = p.accum ? 1 : 0;
     g.fstride = 0;
+    g.axis = c.axis;
     return g;
 }
 
@@ -400,13 +460,32 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
             cut.push_back(q);
         }
     op->n_out = (int)out_src.size();
+    // The cut is a thin shell: rows along x through the x-faces of T hold
+    // only a block or two of it.  Each cut block goes to the orientation
+    // (rows along x or along y) whose row through it holds more cut blocks,
+    // and each orientation is one float64 convolution.
+    std::map<std::pair<int, int>, int> xrow, yrow;
+    for (const auto &b : cut) {
+        ++xrow[{b.ijk[1], b.ijk[2]}];
+        ++yrow[{b.ijk[0], b.ijk[2]}];
+    }
+    std::vector<Blk> cutx, cuty;
+    for (const auto &b : cut)
+        (yrow[{b.ijk[0], b.ijk[2]}] > xrow[{b.ijk[1], b.ijk[2]}] ? cuty : cutx).push_back(b);
     op->c32 = std::make_unique<Conv>();
     build_conv(plan, *op->c32, src, tcomp, true);
-    op->c64 = std::make_unique<Conv>();
-    build_conv(plan, *op->c64, cut, tgt, false);
+    if (!cutx.empty()) {
+        op->c64 = std::make_unique<Conv>();
+        build_conv(plan, *op->c64, cutx, tgt, false, 0);
+    }
+    if (!cuty.empty()) {
+        op->c64y = std::make_unique<Conv>();
+        build_conv(plan, *op->c64y, cuty, tgt, false, 1);
+    }
     op->ccorr = std::make_unique<Conv>();
     build_conv(plan, *op->ccorr, tcomp, tgt, true);
-    for (const Conv *c : {op->c32.get(), op->c64.get(), op->ccorr.get()}) plan->convs_view.push_back(c);
+    for (const Conv *c : {op->c32.get(), op->c64.get(), op->c64y.get(), op->ccorr.get()})
+        if (c) plan->convs_view.push_back(c);
     // dense map of T over its bounding box
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     for (const auto &b : tgt)
@@ -489,7 +568,8 @@ void run_op(lgf_plan *plan, const ConvOp &op, const double *src, int64_t sstride
         for (int c = 0; c < ng; ++c)
             refine_middle(plan, op, sg + (size_t)c * sstride, dg + (size_t)c * dstride, ut + (size_t)c * plan->ut_len,
                           rin + (size_t)c * plan->ut_len, cut + (size_t)c * plan->cut_len, dx, accumulate, s);
-        run_conv(plan, *op.c64, cut, plan->cut_len, dg, dstride, ng, dx, 1, s);
+        if (op.c64) run_conv(plan, *op.c64, cut, plan->cut_len, dg, dstride, ng, dx, 1, s);
+        if (op.c64y) run_conv(plan, *op.c64y, cut, plan->cut_len, dg, dstride, ng, dx, 1, s);
         run_conv(plan, *op.ccorr, rin, plan->ut_len, dg, dstride, ng, dx, 1, s);
     }
 }

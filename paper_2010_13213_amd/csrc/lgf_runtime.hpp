@@ -108,6 +108,7 @@ struct SubConv {
 // One blockwise LGF convolution on a level (sources -> targets).
 struct Conv {
     int bx = 0;             // MAC row template (8 or 16)
+    int axis = 0;           // rows along lattice x (0) or y (1)
     int rs = 0;             // slots per row of the padded box: a multiple of bx
     int ey = 0, ez = 0;
     int lo[3] = {0, 0, 0};
@@ -124,8 +125,9 @@ struct Conv {
 struct ConvOp {
     bool refined = false;
     // plain: sources -> targets.  refined: the cut (depth <= 2 cells of the
-    // shell blocks) and the sources outside T -> targets, in float64
-    std::unique_ptr<Conv> c64;
+    // shell blocks) and the sources outside T -> targets, in float64, split
+    // into rows along x (c64) and rows along y (c64y); either may be null
+    std::unique_ptr<Conv> c64, c64y;
     // refined: u~ (sources -> T) and the float32 residual (T -> targets)
     std::unique_ptr<Conv> c32, ccorr;
     int n_t = 0, n_sh = 0, n_out = 0;
@@ -196,7 +198,8 @@ void build_schedule(lgf_plan *plan);
 void run_plan(lgf_plan *plan, const double *f, double *u, hipStream_t s, lgf_report *rep);
 void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
                hipStream_t s, lgf_report *reps);
-void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32);
+void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
+                int axis = 0);
 void plan_alloc_spectral(lgf_plan *plan);
 std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool refine);
 // Refinement workspaces (per component region) for the plan's refined ops.

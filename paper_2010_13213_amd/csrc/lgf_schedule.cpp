@@ -491,8 +491,9 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         for (int i : ids) max_nc = std::max(max_nc, plans[i]->nc);
         for (int comp = 0; comp < max_nc; ++comp) {
             // a: plain solves and the float32 pass of refined ones; then the
-            // refined ones' residual, cut (b1) and float32 residual (b2) passes
-            std::vector<ConvCall> a, b1, b2;
+            // refined ones' residual, cut (b1: rows along x, b1y: rows along
+            // y) and float32 residual (b2) passes
+            std::vector<ConvCall> a, b1, b1y, b2;
             for (int i : ids) {
                 lgf_plan *p = plans[i];
                 if (comp >= p->nc) continue;
@@ -503,7 +504,9 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
                     a.push_back(ConvCall{p, op.c64.get(), src, dst, p->dx0, 0});
                 } else {
                     a.push_back(ConvCall{p, op.c32.get(), src, (double *)p->ws_ut.ptr, p->dx0, 0});
-                    b1.push_back(ConvCall{p, op.c64.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
+                    if (op.c64) b1.push_back(ConvCall{p, op.c64.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
+                    if (op.c64y)
+                        b1y.push_back(ConvCall{p, op.c64y.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
                     b2.push_back(ConvCall{p, op.ccorr.get(), (const double *)p->ws_rho.ptr, dst, p->dx0, 1});
                 }
             }
@@ -516,6 +519,7 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
                               0, s);
             }
             run_conv_batch(ctx, b1, s);
+            run_conv_batch(ctx, b1y, s);
             run_conv_batch(ctx, b2, s);
         }
     }

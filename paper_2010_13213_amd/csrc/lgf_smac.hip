@@ -102,20 +102,24 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
     auto frow_off = [&](int fy, int fz) -> size_t {
         return ((size_t)((fz ? kzr : kz) * g.N + (fy ? kyr : ky)) * H + kx) * kper;
     };
-    // raw table value for offset (dxi - (BX - 1), dy, dz), dxi in [0, KW);
-    // a negative dx also needs the conjugate, applied by kfix
+    // raw table value for the offset (dx, dy, dz) = (dxi - (BX - 1) + dox,
+    // dy, dz) in the kernel's frame (x along the rows); g.axis = 1 runs the
+    // rows along the lattice y axis, i.e. the lattice offset is (dy, dx, dz).
+    // A negative lattice x offset also needs the conjugate, applied by kfix.
     const int dox = g.tx0 - g.sx0;   // x offset between the target and source segments
     auto kraw = [&](int dy, int dz, int dxi) -> cplx<R> {
         const int dx = dxi - (BX - 1) + dox;
-        const bool fx = dx < 0;
-        const int fy = (dy < 0) != fx, fz = (dz < 0) != fx;
-        return Ktab[frow_off(fy, fz) + ((size_t)abs(dy) * g.ZD + abs(dz)) * g.XD + abs(dx)];
+        const int px = g.axis ? dy : dx, py = g.axis ? dx : dy;
+        const bool fx = px < 0;
+        const int fy = (py < 0) != fx, fz = (dz < 0) != fx;
+        return Ktab[frow_off(fy, fz) + ((size_t)abs(py) * g.ZD + abs(dz)) * g.XD + abs(px)];
     };
-    auto kfix = [&](cplx<R> v, int dxi) -> cplx<R> {
-        if (dxi - (BX - 1) + dox < 0) v.y = -v.y;
+    auto kfix = [&](cplx<R> v, int dy, int dxi) -> cplx<R> {
+        const int dx = dxi - (BX - 1) + dox;
+        if ((g.axis ? dy : dx) < 0) v.y = -v.y;
         return v;
     };
-    auto kload = [&](int dy, int dz, int dxi) -> cplx<R> { return kfix(kraw(dy, dz, dxi), dxi); };
+    auto kload = [&](int dy, int dz, int dxi) -> cplx<R> { return kfix(kraw(dy, dz, dxi), dy, dxi); };
     auto lds = [&](int dy, int dz, int dxi) -> int { return (pmod(dy, SY) * SZ + pmod(dz, SZ)) * KW + dxi; };
 
     // NC right-hand sides (components) share every kernel row
@@ -246,7 +250,7 @@ __device__ __forceinline__ void smac_body(const SmacGeom &g, const cplx<R> *__re
                     const int dxi = e % KW, q = e / KW;
                     const int dy = (kind == 1) ? ndy : (ty0 - nsy + q);
                     const int dz = (kind == 1) ? (tz0 - nsz + q) : ndz;
-                    kbuf[lds(dy, dz, dxi)] = kfix(pre[p], dxi);
+                    kbuf[lds(dy, dz, dxi)] = kfix(pre[p], dy, dxi);
                 }
             }
             if (l < NC * BX) frow[buf ^ 1][l / BX][l % BX] = fpre;

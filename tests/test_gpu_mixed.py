@@ -1,8 +1,9 @@
 """GPU parity of the FP32 + FP64-refinement path (LGF_FP32_REFINE).
 
 Bar: relative L2 <= 1e-10 against the CPU FP64 oracle, for every result.
-Spectra, FFTs and products run in float32; the residual, the shell values
-and the final accumulation in float64 (see csrc/lgf_refine.hip).
+Spectra, FFTs and products run in float32; the residual, the convolution of
+the two-cell cut and the final accumulation in float64 (see
+csrc/lgf_refine.hip).
 """
 import numpy as np
 import pytest
@@ -23,7 +24,9 @@ def _cube(n, lo=(0, 0, 0)):
 def test_gaussian_box_32_mixed_full_parity(gpu_ctx):
     p = inputs.gaussian_box()
     (u, rep) = gpu_solve(gpu_ctx, p, "fp32_refine", report=True)
-    assert rep.passes == 3                       # float32, float64 shell, float32 correction
+    # float32 solve, float64 cut (rows along x for the y/z faces, rows along
+    # y for the x faces of the cube), float32 correction
+    assert rep.passes == 4
     c = level_cells(p)
     ref = direct.direct_sum(c, p.flat_source(), c, p.dx0)
     assert rel_l2(u[0], ref) < TOL_MIXED
