@@ -23,7 +23,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "target cells solved/s at 256^3, FP32+refine vs FP64; p50/p99 solve latency"
-MAC_KERNEL = "smac_kernel<16,8,16,8,double>"
+MAC_KERNEL = "smac_kernel<16,8,16,8,double,dense,1 component>"
 # HBM bytes of one launch of the MAC kernel, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE counters (scaled by a 1 GiB copy); valid only for the kernel
 # sources whose hash the summary records

@@ -472,6 +472,28 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
     std::vector<Blk> cutx, cuty;
     for (const auto &b : cut)
         (yrow[{b.ijk[0], b.ijk[2]}] > xrow[{b.ijk[1], b.ijk[2]}] ? cuty : cutx).push_back(b);
+    // Keep the split only when it saves MAC work.  Work ~ source rows x
+    // target tiles of each convolution; both have all of T as targets, so
+    // on thin supports (cut ~ all of T) one convolution is cheaper.
+    {
+        auto n_rows = [](const std::vector<Blk> &v, int a) {
+            std::set<std::pair<int, int>> r;
+            for (const auto &b : v) r.insert({b.ijk[a], b.ijk[2]});
+            return (int64_t)r.size();
+        };
+        auto n_tiles = [&](int a, int ty) {
+            std::set<std::pair<int, int>> t;
+            for (const auto &b : tgt) t.insert({(b.ijk[a] + 1024 * ty) / ty, (b.ijk[2] + 1024 * 8) / 8});
+            return (int64_t)t.size();
+        };
+        const int ty = smac_tile_y(16);
+        const int64_t single = n_rows(cut, 1) * n_tiles(1, ty);
+        const int64_t split = n_rows(cutx, 1) * n_tiles(1, ty) + (cuty.empty() ? 0 : n_rows(cuty, 0) * n_tiles(0, ty));
+        if (cuty.empty() || split * 5 >= single * 4) {
+            cutx = cut;
+            cuty.clear();
+        }
+    }
     op->c32 = std::make_unique<Conv>();
     build_conv(plan, *op->c32, src, tcomp, true);
     if (!cutx.empty()) {

@@ -24,9 +24,9 @@ def _cube(n, lo=(0, 0, 0)):
 def test_gaussian_box_32_mixed_full_parity(gpu_ctx):
     p = inputs.gaussian_box()
     (u, rep) = gpu_solve(gpu_ctx, p, "fp32_refine", report=True)
-    # float32 solve, float64 cut (rows along x for the y/z faces, rows along
-    # y for the x faces of the cube), float32 correction
-    assert rep.passes == 4
+    # float32 solve, float64 cut (one convolution, or two when rows along y
+    # for the x faces save work), float32 correction
+    assert rep.passes in (3, 4)
     c = level_cells(p)
     ref = direct.direct_sum(c, p.flat_source(), c, p.dx0)
     assert rel_l2(u[0], ref) < TOL_MIXED
