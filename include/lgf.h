@@ -155,8 +155,9 @@ lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans,
 /*
  * Evaluate the context's device LGF table at n lattice points (host arrays:
  * ijk [n][3] int32 in, out [n] float64): the exact near field for
- * max|n_i| <= lgf_table_radius(), the asymptotic series beyond (Sec. 5,
- * "exact values for near points, asymptotic expansions for far points").
+ * max|n_i| <= lgf_table_radius(), the asymptotic series beyond (Sec. 5:
+ * the paper tabulates G near the origin and expands it asymptotically far
+ * from it).
  */
 lgf_status lgf_table_values(lgf_context *ctx, int64_t n, const int32_t *ijk, double *out);
 int lgf_table_radius(void);

@@ -1,9 +1,9 @@
 """Symbolic derivation of the far-field expansion of the 7-point LGF.
 
-Oracle provenance script (test infrastructure).  The paper stores "exact
-values for near points" and "asymptotic expansions for far points" of the
-LGF (Sec. 5, Implementation) but does not print the expansion; this script
-derives it from the Fourier symbol of the 7-point operator.
+Oracle provenance script (test infrastructure).  The paper tabulates the
+LGF near the origin and uses an asymptotic expansion far from it (Sec. 5,
+Implementation) but does not print the expansion; this script derives it
+from the Fourier symbol of the 7-point operator.
 
 Derivation.  With (L g)(n) = sum_{+-e_i} g(n +- e_i) - 6 g(n) and L G = delta,
 

@@ -16,6 +16,9 @@
 //    eq. combine_S; F_k / f^_k are zero outside the level's own blocks).
 //  * copy_blocks: block-list copy (P psi into the targets before the
 //    convolution adds L_k^-1 of the sources).
+#include <algorithm>
+#include <cstdint>
+
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -75,6 +78,14 @@ __global__ void copy_kernel(const double *__restrict__ src, double *__restrict__
     const double *s = src + src_off[b];
     double *d = dst + dst_off[b];
     for (int i = threadIdx.x; i < nb3; i += blockDim.x) d[i] = s[i];
+}
+
+// Zero n 16-byte words (grid-stride, vector stores).  Used instead of a
+// memset node wherever a solve may be captured into a graph.
+__global__ void zero_kernel(int4 *__restrict__ p, int64_t n) {
+    const int4 z = make_int4(0, 0, 0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z;
 }
 
 // Trilinear value at fine cell (fx, fy, fz) from a coarse array staged in LDS
@@ -198,6 +209,15 @@ hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *sr
                        int n_blocks, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_kernel, dim3(n_blocks), dim3(256), 0, s, src, dst, src_off, dst_off, nb * nb * nb);
+    return hipGetLastError();
+}
+
+hipError_t zero_fill(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 16 != 0 || ((uintptr_t)p) % 16 != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 16);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (int4 *)p, n);
     return hipGetLastError();
 }
 

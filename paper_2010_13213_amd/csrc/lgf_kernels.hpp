@@ -109,6 +109,9 @@ hipError_t coarsen_mean8(int nb, const double *fine, double *coarse, const int64
                          const int64_t *coarse_off, const unsigned char *octant, int n_pairs, hipStream_t s);
 hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,
                        int n_blocks, hipStream_t s);
+// p[0, bytes) = 0 by a kernel (bytes and p 16-byte aligned); a memset node
+// is avoided in code that a caller may capture into a graph.
+hipError_t zero_fill(void *p, size_t bytes, hipStream_t s);
 struct CorrGeom {
     double dxc, dxf;        // cell widths of levels k-1 and k
     int mlo[3], mdim[3];    // dense map of psi_{k-1} blocks: index or -1

@@ -639,7 +639,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     // empty slots of Fhat must read as zero; the forward FFT writes only
     // occupied slots, so clear when another slot map used the buffer last
     if (plan->fhat_conv != &c) {
-        hip_check(hipMemsetAsync(plan->Fhat.ptr, 0, plan->Fhat.bytes, s), "clear Fhat");
+        hip_check(zero_fill(plan->Fhat.ptr, plan->Fhat.bytes, s), "clear Fhat");
         plan->fhat_conv = &c;
     }
     for (int k = 0; k < nc; ++k) {
@@ -650,7 +650,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
                   "forward block FFT");
     }
     if (c.parts.empty())   // no source or no target: the convolution is zero
-        hip_check(hipMemsetAsync(plan->Uhat.ptr, 0, plan->Uhat.bytes, s), "clear Uhat");
+        hip_check(zero_fill(plan->Uhat.ptr, plan->Uhat.bytes, s), "clear Uhat");
     for (const auto &p : c.parts) {
         StageTimer t(plan->ctx, 1, s);
         SmacGeom g = conv_geom(c, *p);

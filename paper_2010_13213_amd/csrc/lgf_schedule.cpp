@@ -371,7 +371,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     if (calls.empty()) return;
     for (const ConvCall &k : calls)
         if (k.p->fhat_conv != k.c) {
-            hip_check(hipMemsetAsync(k.p->Fhat.ptr, 0, k.p->Fhat.bytes, s), "clear Fhat");
+            hip_check(zero_fill(k.p->Fhat.ptr, k.p->Fhat.bytes, s), "clear Fhat");
             k.p->fhat_conv = k.c;
         }
     const int nb = calls[0].p->nb;
@@ -403,7 +403,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     }
     for (const ConvCall &k : calls)
         if (k.c->parts.empty())
-            hip_check(hipMemsetAsync(k.p->Uhat.ptr, 0, k.p->Uhat.bytes, s), "clear Uhat");
+            hip_check(zero_fill(k.p->Uhat.ptr, k.p->Uhat.bytes, s), "clear Uhat");
     // parts of one target segment are in different phases: one launch per
     // (phase, precision, template, sparse flag)
     int n_phase = 0;

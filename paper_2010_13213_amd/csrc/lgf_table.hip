@@ -1,7 +1,8 @@
 // LGF table generation and LGF block spectra (plan time, float64).
 //
-// Table (paper Sec. 5: the LGF is stored as exact values for near points and
-// an asymptotic expansion for far points; it is the same on every level).
+// Table (paper Sec. 5: G is tabulated exactly close to the origin and
+// replaced by its asymptotic series far from it; one table serves every
+// level).
 // The LGF of the unscaled 7-point Laplacian has the Bessel-integral form
 //
 //     G(n) = - \int_0^inf prod_i e^{-2t} I_{n_i}(2t) dt.
