@@ -153,6 +153,24 @@ lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans,
                            lgf_report *reps);
 
 /*
+ * Graph form of lgf_solve for fixed buffers: lgf_graph_create records every
+ * launch of one lgf_solve(plan, f, u) into a HIP graph (captured on a
+ * private stream; the device pointers f and u are bound into it) and
+ * instantiates it; lgf_graph_launch replays the whole solve on `stream` with
+ * one call, so repeated solves of one shape pay no per-kernel launch cost.
+ * The graph reads f and writes u at replay time, so the caller refreshes f in
+ * place between replays.  The plan must outlive the graph, and replays and
+ * solves of one plan must not overlap in time (one workspace).  Errors of
+ * create: LGF_E_INVALID (null/misaligned pointers), LGF_E_DEVICE (capture or
+ * instantiation failed).  Timing (lgf_context_set_timing) does not see
+ * graph replays.
+ */
+typedef struct lgf_graph lgf_graph;
+lgf_status lgf_graph_create(lgf_plan *plan, const double *f, double *u, lgf_graph **out);
+lgf_status lgf_graph_launch(lgf_graph *graph, void *stream);
+void lgf_graph_destroy(lgf_graph *graph);
+
+/*
  * Evaluate the context's device LGF table at n lattice points (host arrays:
  * ijk [n][3] int32 in, out [n] float64): the exact near field for
  * max|n_i| <= lgf_table_radius(), the asymptotic series beyond (Sec. 5:

@@ -221,6 +221,51 @@ lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream, l
     });
 }
 
+struct lgf_graph {
+    lgf_plan *plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+lgf_status lgf_graph_create(lgf_plan *plan, const double *f, double *u, lgf_graph **out) {
+    return guard([&] {
+        require(out != nullptr, "null output");
+        *out = nullptr;
+        require(plan != nullptr, "null plan");
+        require(f != nullptr && u != nullptr, "null field pointer");
+        require(((uintptr_t)f % 8) == 0 && ((uintptr_t)u % 8) == 0, "misaligned field pointer");
+        DeviceScope ds(plan->ctx->device);
+        auto g = std::make_unique<lgf_graph>();
+        g->plan = plan;
+        g->graph = capture_solve(plan, f, u);
+        const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g->graph);
+            hip_check(e, "graph instantiate");
+        }
+        *out = g.release();
+    });
+}
+
+lgf_status lgf_graph_launch(lgf_graph *g, void *stream) {
+    return guard([&] {
+        require(g != nullptr && g->exec != nullptr, "null graph");
+        DeviceScope ds(g->plan->ctx->device);
+        // the graph clears the spectral workspace itself; the next eager
+        // solve must not assume any slot map either
+        g->plan->fhat_conv = nullptr;
+        hip_check(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+    });
+}
+
+void lgf_graph_destroy(lgf_graph *g) {
+    if (!g) return;
+    DeviceScope ds(g->plan->ctx->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
 lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f,
                            double *const *u, void *stream, lgf_report *reps) {
     return guard([&] {

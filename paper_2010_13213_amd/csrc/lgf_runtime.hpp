@@ -196,6 +196,7 @@ void ring_free(lgf_context *ctx);
 void build_context_table(lgf_context *ctx);
 void build_schedule(lgf_plan *plan);
 void run_plan(lgf_plan *plan, const double *f, double *u, hipStream_t s, lgf_report *rep);
+hipGraph_t capture_solve(lgf_plan *plan, const double *f, double *u);
 void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
                hipStream_t s, lgf_report *reps);
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,

@@ -329,6 +329,36 @@ void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report
     }
 }
 
+// Record one solve of plan p on fixed f / u into a graph: the launches that
+// lgf_solve would enqueue, captured on a private stream.  Stage timing is
+// off while capturing (no event nodes), and the spectral workspace is
+// cleared at the start of the graph whatever the host believes it holds.
+hipGraph_t capture_solve(lgf_plan *p, const double *f, double *u) {
+    hipStream_t cs = nullptr;
+    hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+    const bool timing = p->ctx->timing;
+    p->ctx->timing = false;
+    p->fhat_conv = nullptr;
+    hipGraph_t g = nullptr;
+    try {
+        hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+        enqueue(p, f, u, cs);
+        hip_check(hipStreamEndCapture(cs, &g), "end capture");
+    } catch (...) {
+        hipGraph_t partial = nullptr;
+        (void)hipStreamEndCapture(cs, &partial);
+        if (partial) (void)hipGraphDestroy(partial);
+        p->ctx->timing = timing;
+        p->fhat_conv = nullptr;
+        (void)hipStreamDestroy(cs);
+        throw;
+    }
+    p->ctx->timing = timing;
+    p->fhat_conv = nullptr;
+    (void)hipStreamDestroy(cs);
+    return g;
+}
+
 namespace {
 
 // One convolution of a batch: plan workspace, sources -> destination.

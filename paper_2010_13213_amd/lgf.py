@@ -21,7 +21,7 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
             "lgf_solve", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
-            "lgf_last_error", "lgf_status_string"]
+            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy"]
 
 
 class LgfError(RuntimeError):
@@ -98,6 +98,12 @@ def lib():
     L.lgf_last_error.restype = ctypes.c_char_p
     L.lgf_status_string.argtypes = [ctypes.c_int]
     L.lgf_status_string.restype = ctypes.c_char_p
+    L.lgf_graph_create.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+    L.lgf_graph_create.restype = ctypes.c_int
+    L.lgf_graph_launch.argtypes = [vp, vp]
+    L.lgf_graph_launch.restype = ctypes.c_int
+    L.lgf_graph_destroy.argtypes = [vp]
+    L.lgf_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -257,6 +263,38 @@ class Plan:
         _check(lib().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                _stream_handle(stream), ctypes.byref(rep) if rep is not None else None))
         return (u, rep) if report else u
+
+
+class Graph:
+    """One solve of `plan` on the fixed tensors f, u, captured as a HIP graph
+    (lgf_graph_create); launch() replays it.  Keep f, u and the plan alive
+    while the graph exists."""
+
+    def __init__(self, plan, f, u):
+        import torch
+        n = plan.field_len()
+        for t in (f, u):
+            if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+                raise ValueError("f and u must be contiguous CUDA float64 tensors of %d elements" % n)
+        self.plan, self.f, self.u = plan, f, u
+        self._h = ctypes.c_void_p()
+        _check(lib().lgf_graph_create(plan.handle, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                      ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(lib().lgf_graph_launch(self._h, _stream_handle(stream)))
+        return self.u
+
+    def close(self):
+        if self._h:
+            lib().lgf_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_batch(ctx, plans, fs, us, stream=None, report=False):
