@@ -99,6 +99,7 @@ def config_table(ctx, reps=3):
             plan.close()
             res[prec] = u.cpu().numpy().reshape(prob.n_components, -1)
             ms = 1e3 * float(np.median(ts))
+            print("config %s %s: plan %.2f s, solve %.3f ms" % (name, prec, t_plan, ms), file=sys.stderr, flush=True)
             row[prec] = {"plan_s": round(t_plan, 3), "solve_ms": ms, "cells_per_s": cells / (ms * 1e-3)}
         if gpath is not None:
             g = np.load(gpath)
@@ -170,6 +171,10 @@ def main():
                     help="print the hash of the MAC kernel sources and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration reference)")
+    ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
+                    help="time every compiled MAC tile shape on each new convolution shape at plan "
+                         "creation (REPS launches each) and keep the fastest")
+    ap.add_argument("--save-tuning", default=None, help="write the context's tuning table here")
     args = ap.parse_args()
     if args.print_mac_hash:
         print(mac_source_hash())
@@ -185,6 +190,8 @@ def main():
 
     torch.cuda.init()
     ctx = lgf.Context(0)
+    if args.autotune:
+        ctx.set_autotune(args.autotune)
     prob = inputs.mstar()
     nb = prob.nb
     n_blocks = len(prob.levels[0].blocks)
@@ -306,6 +313,8 @@ def main():
         out["configs"] = config_table(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+    if args.save_tuning:
+        ctx.save_tuning(args.save_tuning)
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -200,6 +200,36 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
 lgf_status lgf_context_set_timing(lgf_context *ctx, int enable);
 lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
 
+/*
+ * MAC tile-shape tuning.  The spectral multiply-accumulate is compiled for a
+ * few tile shapes (rectangles of target rows per workgroup); which one is
+ * fastest depends on the shape of the block set.  A context keeps a table
+ * from convolution shape (block size, precision, components per MAC
+ * launch, extent of the padded box, source and target block counts) to
+ * tile shape.  Plans take the table's
+ * shape when it has one, else the default shape.
+ *
+ * lgf_context_set_autotune(ctx, reps): with reps > 0 (at most 1000), plan
+ * creation on this context times every compiled shape on each convolution
+ * shape the table lacks (one warm-up and up to reps launches, fewer where
+ * they would take more than about 200 ms, on the context's own stream, with scratch spectra the size of that convolution's, released
+ * after) and records the fastest, or the default shape unless another is
+ * faster by more than 3%; 0 turns this off (the default).  Results
+ * do not depend on the tile shape: each target sums its sources in the same
+ * order under every shape.
+ * lgf_context_save_tuning / lgf_context_load_tuning write / merge the table
+ * as JSON: {"version": 1, "entries": {key: {"ty": rows along y, "tz": rows
+ * along z, "candidates": [[ty, tz], ...], "ms": [ms per launch, ...]}}};
+ * candidates and ms may be empty or absent in a loaded file.  Loading
+ * rejects malformed text with LGF_E_INVALID (the message names the byte)
+ * and changes nothing then; an entry whose shape is not compiled for its
+ * convolution is ignored at plan creation.  lgf_context_tuning_size returns the number of entries.
+ */
+lgf_status lgf_context_set_autotune(lgf_context *ctx, int reps);
+lgf_status lgf_context_save_tuning(lgf_context *ctx, const char *path);
+lgf_status lgf_context_load_tuning(lgf_context *ctx, const char *path);
+lgf_status lgf_context_tuning_size(lgf_context *ctx, int64_t *n_entries);
+
 const char *lgf_last_error(void);
 const char *lgf_status_string(lgf_status s);
 

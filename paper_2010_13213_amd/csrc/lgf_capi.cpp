@@ -4,7 +4,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <set>
 #include <string>
 #include <tuple>
@@ -349,6 +354,51 @@ lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launch
         require(ctx && ms && launches, "null arguments");
         DeviceScope ds(ctx->device);
         resolve_stage_times(ctx, ms, launches);
+    });
+}
+
+lgf_status lgf_context_set_autotune(lgf_context *ctx, int reps) {
+    return guard([&] {
+        require(ctx != nullptr, "null context");
+        require(reps >= 0 && reps <= 1000, "autotune repetitions must be in [0, 1000]");
+        ctx->autotune_reps = reps;
+    });
+}
+
+lgf_status lgf_context_save_tuning(lgf_context *ctx, const char *path) {
+    return guard([&] {
+        require(ctx && path, "null arguments");
+        std::string text;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            text = tuning_to_json(ctx->tune);
+        }
+        FILE *fp = std::fopen(path, "w");
+        if (!fp) throw Failure(LGF_E_INVALID, std::string("cannot open ") + path + " for writing");
+        const size_t n = std::fwrite(text.data(), 1, text.size(), fp);
+        const int rc = std::fclose(fp);
+        if (n != text.size() || rc != 0) throw Failure(LGF_E_INVALID, std::string("write failed: ") + path);
+    });
+}
+
+lgf_status lgf_context_load_tuning(lgf_context *ctx, const char *path) {
+    return guard([&] {
+        require(ctx && path, "null arguments");
+        std::ifstream in(path, std::ios::binary);
+        if (!in) throw Failure(LGF_E_INVALID, std::string("cannot open ") + path);
+        std::ostringstream ss;
+        ss << in.rdbuf();
+        std::map<std::string, TuneEntry> got = tuning_from_json(ss.str());
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &kv : got) ctx->tune[kv.first] = kv.second;
+    });
+}
+
+lgf_status lgf_context_tuning_size(lgf_context *ctx, int64_t *n_entries) {
+    return guard([&] {
+        require(ctx && n_entries, "null arguments");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        *n_entries = (int64_t)ctx->tune.size();
     });
 }
 

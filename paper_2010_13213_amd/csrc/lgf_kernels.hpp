@@ -62,6 +62,7 @@ struct SmacTile {
 };
 struct SmacGeom {
     int bx;                 // row length template (8 or 16)
+    int ty, tz;             // tile shape in rows (one of smac_tiles(bx))
     int ey, ez;             // padded box extent in blocks along y, z (slots)
     int n_freq;
     int64_t n_slots;        // bx * ey * ez
@@ -87,11 +88,12 @@ struct SmacJob {
     const SmacTile *tiles;
     int64_t wg_begin;       // first workgroup of this job in the batched grid
 };
-hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs, int64_t total_wg,
-                             hipStream_t s);
-int smac_tile_y(int bx);
-int smac_tile_z(int bx);
+hipError_t smac_batch_launch(int bx, int ty, int tz, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs,
+                             int64_t total_wg, hipStream_t s);
 int smac_seg_len(int bx);   // A: targets per lane
+// Tile shapes (TY, TZ) compiled for row template bx, the default first;
+// writes up to max_tiles of them and returns how many exist.
+int smac_tiles(int bx, int (*tiles)[2], int max_tiles);
 // Uhat[c][omega][t] = sum_s K[omega][t - s] * Fhat[c][omega][s] for the nc
 // (1..3) components c, over every source row
 // and every target slot of each tile; source positions outside a row's mask

@@ -201,8 +201,8 @@ static int roundup(int a, int m) { return (a + m - 1) / m * m; }
 // (ss - ts) mod n_seg, so the parts of one target segment never run in the
 // same launch; the first of them stores into Uhat, later ones add.  Empty
 // source segments of a row and empty target segments of a tile cost nothing.
-void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
-                int axis) {
+static void build_conv_tile(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt,
+                            bool fp32, int axis, int TY, int TZ) {
     lgf_context *ctx = plan->ctx;
     const int nb = plan->nb;
     // coordinates in the MAC's frame: rows along x (axis 0) or along the
@@ -222,7 +222,8 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     const int bx = ex <= 8 ? 8 : 16;
     const int rs = roundup(ex, bx);
     const int n_seg = rs / bx;
-    const int TY = smac_tile_y(bx), TZ = smac_tile_z(bx);
+    c.ty = TY;
+    c.tz = TZ;
     c.bx = bx;
     c.rs = rs;
     c.ey = roundup(ey, TY);
@@ -379,9 +380,125 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
 }
 
+// Shape key of a convolution for the tuning table.
+static std::string tune_key(int nb, bool fp32, int nc, int axis, const std::vector<Blk> &src,
+                            const std::vector<Blk> &tgt) {
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (const auto *v : {&src, &tgt})
+        for (const auto &b : *v)
+            for (int a = 0; a < 3; ++a) {
+                const int c = (axis == 1 && a < 2) ? b.ijk[1 - a] : b.ijk[a];
+                lo[a] = std::min(lo[a], c);
+                hi[a] = std::max(hi[a], c);
+            }
+    char k[160];
+    std::snprintf(k, sizeof k, "nb%d_%s_nc%d_ext%dx%dx%d_src%zu_tgt%zu", nb, fp32 ? "f32" : "f64", nc,
+                  hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, src.size(), tgt.size());
+    return k;
+}
+
+// Milliseconds per launch of the MAC parts of c, for the plan's components
+// per launch, on the context stream, with throw-away spectral buffers.
+static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
+    lgf_context *ctx = plan->ctx;
+    const int nc = plan->mac_nc;
+    const int64_t fs = (int64_t)c.spec->n_freq * c.n_slots;
+    const size_t bytes = (c.fp32 ? 8 : 16) * (size_t)fs * nc;
+    DeviceBuffer F, U;
+    F.alloc(ctx, bytes, "tuning workspace");
+    U.alloc(ctx, bytes, "tuning workspace");
+    hip_check(zero_fill(F.ptr, bytes, ctx->stream), "tuning clear");
+    auto run = [&] {
+        for (const auto &p : c.parts) {
+            SmacGeom g = conv_geom(c, *p);
+            g.fstride = fs;
+            hip_check(smac_launch(g, c.fp32, p->sparse, nc, F.ptr, U.ptr, c.spec->data.ptr,
+                                  (const SmacRow *)p->d_rows.ptr, (const SmacTile *)p->d_tiles.ptr, ctx->stream),
+                      "tuning MAC");
+        }
+    };
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventCreate(&b), "event");
+    auto timed = [&](int n) {
+        hip_check(hipEventRecord(a, ctx->stream), "event record");
+        for (int r = 0; r < n; ++r) run();
+        hip_check(hipEventRecord(b, ctx->stream), "event record");
+        hip_check(hipEventSynchronize(b), "event sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, a, b), "elapsed");
+        return (double)ms;
+    };
+    // warm-up; long launches get fewer repetitions (about 200 ms per shape)
+    const double first = timed(1);
+    const int n = std::max(1, std::min(reps, (int)(200.0 / std::max(first, 1e-3))));
+    const double ms = timed(n) / n;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+// Build a convolution with the MAC tile shape of the context's tuning table
+// for its shape.  With autotuning on and no entry yet, every compiled tile
+// shape is built and timed on this convolution's own geometry; the fastest
+// is recorded if it beats the default shape by more than the 3% that
+// repeated timings of one shape differ by, else the default is.  Without an
+// entry the default tile shape is used.
+void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
+                int axis) {
+    lgf_context *ctx = plan->ctx;
+    int xmin = INT32_MAX, xmax = INT32_MIN;
+    for (const auto *v : {&src, &tgt})
+        for (const auto &b : *v) {
+            const int x = axis == 1 ? b.ijk[1] : b.ijk[0];
+            xmin = std::min(xmin, x);
+            xmax = std::max(xmax, x);
+        }
+    const int bx = (xmax - xmin + 1) <= 8 ? 8 : 16;
+    int cand[4][2];
+    const int n_cand = smac_tiles(bx, cand, 4);
+    int ty = cand[0][0], tz = cand[0][1];
+    const std::string key = tune_key(plan->nb, fp32, plan->mac_nc, axis, src, tgt);
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->tune.find(key);
+        if (it != ctx->tune.end())
+            for (int i = 0; i < n_cand; ++i)   // a loaded entry must name a compiled shape
+                if (cand[i][0] == it->second.ty && cand[i][1] == it->second.tz) {
+                    ty = cand[i][0];
+                    tz = cand[i][1];
+                    found = true;
+                }
+    }
+    if (!found && ctx->autotune_reps > 0 && n_cand > 1 && !src.empty() && !tgt.empty()) {
+        TuneEntry e;
+        double best = 1e300;
+        for (int i = 0; i < n_cand; ++i) {
+            Conv trial;
+            build_conv_tile(plan, trial, src, tgt, fp32, axis, cand[i][0], cand[i][1]);
+            const double ms = time_mac(plan, trial, ctx->autotune_reps);
+            e.cand.push_back({cand[i][0], cand[i][1]});
+            e.ms.push_back(ms);
+            if (i == 0 || (ms < 0.97 * e.ms[0] && ms < best)) {
+                best = ms;
+                ty = cand[i][0];
+                tz = cand[i][1];
+            }
+        }
+        e.ty = ty;
+        e.tz = tz;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tune[key] = e;
+    }
+    build_conv_tile(plan, c, src, tgt, fp32, axis, ty, tz);
+}
+
 SmacGeom conv_geom(const Conv &c, const SubConv &p) {
     SmacGeom g;
     g.bx = c.bx;
+    g.ty = c.ty;
+    g.tz = c.tz;
     g.ey = c.ey;
     g.ez = c.ez;
     g.n_freq = c.spec->n_freq;
@@ -486,7 +603,7 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
             for (const auto &b : tgt) t.insert({(b.ijk[a] + 1024 * ty) / ty, (b.ijk[2] + 1024 * 8) / 8});
             return (int64_t)t.size();
         };
-        const int ty = smac_tile_y(16);
+        const int ty = 16;   // rows per tile of the default 16-wide template
         const int64_t single = n_rows(cut, 1) * n_tiles(1, ty);
         const int64_t split = n_rows(cutx, 1) * n_tiles(1, ty) + (cuty.empty() ? 0 : n_rows(cuty, 0) * n_tiles(0, ty));
         if (cuty.empty() || split * 5 >= single * 4) {

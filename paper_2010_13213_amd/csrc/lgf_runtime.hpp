@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -72,9 +74,23 @@ struct JobRing {
     int next = 0;
 };
 
+// Tuning-table entry: the chosen MAC tile shape, and every candidate shape
+// timed with its milliseconds per launch.
+struct TuneEntry {
+    int ty = 0, tz = 0;
+    std::vector<std::array<int, 2>> cand;
+    std::vector<double> ms;
+};
+// The table as JSON and back (lgf_tuning.cpp); the reader throws Failure
+// (LGF_E_INVALID) on malformed text.
+std::string tuning_to_json(const std::map<std::string, TuneEntry> &table);
+std::map<std::string, TuneEntry> tuning_from_json(const std::string &text);
+
 struct lgf_context_impl {
     int device;
     bool timing = false;
+    int autotune_reps = 0;                       // > 0: time tile shapes for new shapes
+    std::map<std::string, TuneEntry> tune;       // shape key -> tile shape (guarded by mu)
     JobRing ring;
     std::vector<StageEvent> pending;
     size_t budget;
@@ -108,6 +124,7 @@ struct SubConv {
 // One blockwise LGF convolution on a level (sources -> targets).
 struct Conv {
     int bx = 0;             // MAC row template (8 or 16)
+    int ty = 0, tz = 0;     // MAC tile shape in rows
     int axis = 0;           // rows along lattice x (0) or y (1)
     int rs = 0;             // slots per row of the padded box: a multiple of bx
     int ey = 0, ez = 0;

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -439,14 +440,18 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     int n_phase = 0;
     for (const ConvCall &k : calls)
         for (const auto &pt : k.c->parts) n_phase = std::max(n_phase, pt->phase + 1);
+    // one launch per (phase, precision, template, tile shape, sparsity)
+    std::set<std::tuple<int, int, int>> shapes;   // (bx, ty, tz)
+    for (const ConvCall &k : calls) shapes.insert({k.c->bx, k.c->ty, k.c->tz});
     for (int ph = 0; ph < n_phase; ++ph)
         for (int fp = 0; fp < 2; ++fp)
-            for (int bx : {8, 16})
+            for (const auto &shape : shapes)
                 for (int sp = 0; sp < 2; ++sp) {
+                    const int bx = std::get<0>(shape), ty = std::get<1>(shape), tz = std::get<2>(shape);
                     std::vector<SmacJob> sj;
                     int64_t total = 0;
                     for (const ConvCall &k : calls) {
-                        if ((int)k.c->fp32 != fp || k.c->bx != bx) continue;
+                        if ((int)k.c->fp32 != fp || k.c->bx != bx || k.c->ty != ty || k.c->tz != tz) continue;
                         for (const auto &pt : k.c->parts) {
                             if (pt->phase != ph || (int)pt->sparse != sp || pt->n_rows == 0 || pt->n_tiles == 0)
                                 continue;
@@ -465,7 +470,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
                     if (sj.empty()) continue;
                     StageTimer t(ctx, 1, s);
                     int slot = 0;
-                    hip_check(smac_batch_launch(bx, fp == 1, sp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(),
+                    hip_check(smac_batch_launch(bx, ty, tz, fp == 1, sp == 1, stage_jobs(ctx, sj, s, slot), (int)sj.size(),
                                                 total, s),
                               "batched spectral MAC");
                     ring_mark(ctx, slot, s);

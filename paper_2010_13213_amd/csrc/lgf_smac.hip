@@ -332,12 +332,12 @@ hipError_t launch_batch_cfg(const SmacJob *jobs, int n_jobs, int64_t total_wg, h
     return hipGetLastError();
 }
 
-// Template per row length: (A, TY, TZ) = (8, 8, 8) for bx = 8 and (8, 16, 8)
-// for bx = 16 (longer rows are cut into 16-wide segments by the runtime).
-template <typename F> hipError_t dispatch(int bx, bool fp32, bool sparse, const F &f) {
-    auto pick = [&](auto bxc, auto ac, auto tyc, auto tzc) -> hipError_t {
-        constexpr int BX = decltype(bxc)::value, A = decltype(ac)::value, TY = decltype(tyc)::value,
-                      TZ = decltype(tzc)::value;
+// Templates (bx, A, TY, TZ): bx = 8 with 8 x 8 tiles; bx = 16 with 16 x 8
+// (the default), 8 x 8 or 16 x 16 tiles (longer rows are cut into 16-wide
+// segments by the runtime).  A = 8 targets per lane throughout.
+template <typename F> hipError_t dispatch(int bx, int ty, int tz, bool fp32, bool sparse, const F &f) {
+    auto pick = [&](auto bxc, auto tyc, auto tzc) -> hipError_t {
+        constexpr int BX = decltype(bxc)::value, A = 8, TY = decltype(tyc)::value, TZ = decltype(tzc)::value;
         if (fp32)
             return sparse ? f.template operator()<BX, A, TY, TZ, float, true>()
                           : f.template operator()<BX, A, TY, TZ, float, false>();
@@ -346,11 +346,11 @@ template <typename F> hipError_t dispatch(int bx, bool fp32, bool sparse, const 
     };
     using I8 = std::integral_constant<int, 8>;
     using I16 = std::integral_constant<int, 16>;
-    switch (bx) {
-    case 8: return pick(I8{}, I8{}, I8{}, I8{});
-    case 16: return pick(I16{}, I8{}, I16{}, I8{});
-    default: return hipErrorInvalidValue;
-    }
+    if (bx == 8 && ty == 8 && tz == 8) return pick(I8{}, I8{}, I8{});
+    if (bx == 16 && ty == 16 && tz == 8) return pick(I16{}, I16{}, I8{});
+    if (bx == 16 && ty == 8 && tz == 8) return pick(I16{}, I8{}, I8{});
+    if (bx == 16 && ty == 16 && tz == 16) return pick(I16{}, I16{}, I16{});
+    return hipErrorInvalidValue;
 }
 
 struct BatchLaunch {
@@ -384,24 +384,31 @@ struct SingleLaunch {
 
 }  // namespace
 
-hipError_t smac_batch_launch(int bx, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs, int64_t total_wg,
-                             hipStream_t s) {
-    return dispatch(bx, fp32, sparse, BatchLaunch{jobs, n_jobs, total_wg, s});
+hipError_t smac_batch_launch(int bx, int ty, int tz, bool fp32, bool sparse, const SmacJob *jobs, int n_jobs,
+                             int64_t total_wg, hipStream_t s) {
+    return dispatch(bx, ty, tz, fp32, sparse, BatchLaunch{jobs, n_jobs, total_wg, s});
 }
 
-int smac_tile_y(int bx) { return bx == 8 ? 8 : 16; }
 int smac_seg_len(int bx) {
     (void)bx;
     return 8;
 }
-int smac_tile_z(int bx) {
-    (void)bx;
-    return 8;
+
+int smac_tiles(int bx, int (*tiles)[2], int max_tiles) {
+    static const int t8[][2] = {{8, 8}};
+    static const int t16[][2] = {{16, 8}, {8, 8}, {16, 16}};
+    const int(*t)[2] = bx == 8 ? t8 : t16;
+    const int n = bx == 8 ? 1 : 3;
+    for (int i = 0; i < n && i < max_tiles; ++i) {
+        tiles[i][0] = t[i][0];
+        tiles[i][1] = t[i][1];
+    }
+    return n;
 }
 
 hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const void *Fhat, void *Uhat,
                        const void *Ktab, const SmacRow *rows, const SmacTile *tiles, hipStream_t s) {
-    return dispatch(g.bx, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, nc, s});
+    return dispatch(g.bx, g.ty, g.tz, fp32, sparse, SingleLaunch{g, Fhat, Uhat, Ktab, rows, tiles, nc, s});
 }
 
 }  // namespace lgf

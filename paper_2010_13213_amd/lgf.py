@@ -21,7 +21,9 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
             "lgf_solve", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
-            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy"]
+            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
+            "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
+            "lgf_context_tuning_size"]
 
 
 class LgfError(RuntimeError):
@@ -89,6 +91,14 @@ def lib():
     L.lgf_block_spectrum.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_double)]
     L.lgf_block_spectrum.restype = ctypes.c_int
+    L.lgf_context_set_autotune.argtypes = [vp, ctypes.c_int]
+    L.lgf_context_set_autotune.restype = ctypes.c_int
+    L.lgf_context_save_tuning.argtypes = [vp, ctypes.c_char_p]
+    L.lgf_context_save_tuning.restype = ctypes.c_int
+    L.lgf_context_load_tuning.argtypes = [vp, ctypes.c_char_p]
+    L.lgf_context_load_tuning.restype = ctypes.c_int
+    L.lgf_context_tuning_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lgf_context_tuning_size.restype = ctypes.c_int
     L.lgf_context_set_timing.argtypes = [vp, ctypes.c_int]
     L.lgf_context_set_timing.restype = ctypes.c_int
     L.lgf_context_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -157,6 +167,21 @@ class Context:
             pass
 
     STAGES = ("fwd_fft", "smac", "inv_fft", "other")
+
+    def set_autotune(self, reps):
+        """Time every compiled MAC tile shape on new convolution shapes (reps > 0) or not (0)."""
+        _check(lib().lgf_context_set_autotune(self._h, int(reps)))
+
+    def save_tuning(self, path):
+        _check(lib().lgf_context_save_tuning(self._h, str(path).encode()))
+
+    def load_tuning(self, path):
+        _check(lib().lgf_context_load_tuning(self._h, str(path).encode()))
+
+    def tuning_size(self):
+        n = ctypes.c_int64()
+        _check(lib().lgf_context_tuning_size(self._h, ctypes.byref(n)))
+        return n.value
 
     def set_timing(self, enable=True):
         _check(lib().lgf_context_set_timing(self._h, 1 if enable else 0))
