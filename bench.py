@@ -5,12 +5,15 @@ Workload: a dense 256^3-cell single-level scalar solve (dx = R/64 over
 [-2R, 2R]^3, 4096 blocks of 16^3 cells, source = x-vorticity of a thin
 Gaussian-core vortex ring, R = 1, sigma = 0.1 R), the 256^3 configuration
 of the headline metric.  A step is one full solve through the C ABI
-(forward block FFTs, spectral multiply-accumulate over all 16.8M block
-pairs, inverse block FFTs), with the source already resident in HBM.
+(forward block FFTs, spectral multiply-accumulate over the 16.8M block
+pairs -- by an FFT over the block lattice or pair by pair -- inverse block
+FFTs), with the source already resident in HBM.
 
 Prints one JSON line (rank 0, N = 1).  The roofline entry is for the
-dominant kernel, the spectral multiply-accumulate, timed with HIP events
-recorded by the library around each of its launches on the solve stream.
+dominant kernel of the solve, timed with HIP events recorded by the library
+around each of its launches on the solve stream: the lattice z-line kernel
+(HBM-bound) when the spectral product runs as an FFT over the block lattice,
+the block-pair kernel (FP64 ALU-bound) when it runs as block pairs.
 """
 import argparse
 import json
@@ -23,37 +26,47 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "target cells solved/s at 256^3, FP32+refine vs FP64; p50/p99 solve latency"
-MAC_KERNEL = "smac_kernel<16,8,16,8,double,dense,1 component>"
-# HBM bytes of one launch of the MAC kernel, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE counters (scaled by a 1 GiB copy); valid only for the kernel
-# sources whose hash the summary records
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "smac_fp64_dense256_traffic.txt")
-MAC_SOURCES = ["lgf_smac.hip", "lgf_device.hpp", "lgf_kernels.hpp"]
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X FP64 vector FMA: 256 CU * 4 SIMD * 16 lanes * 2 * 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# Per dominant kernel: its name in profiles, the counter summary holding its
+# HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB
+# copy) and the sources whose hash that summary must record to be used.
+KERNELS = {
+    "lat_z": ("lat_z<double,32>", "lat_z_fp64_dense256_traffic.txt",
+              ["lgf_lattice.hip", "lgf_device.hpp", "lgf_kernels.hpp"]),
+    "smac": ("smac_kernel<16,8,16,8,double,dense,1 component>", "smac_fp64_dense256_traffic.txt",
+             ["lgf_smac.hip", "lgf_device.hpp", "lgf_kernels.hpp"]),
+}
 
 
-def mac_source_hash():
+def source_hash(kind):
     import hashlib
     h = hashlib.sha256()
-    for name in MAC_SOURCES:
+    for name in KERNELS[kind][2]:
         with open(os.path.join(ROOT, "paper_2010_13213_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Counter-measured bytes per MAC launch, or None when the summary is
-    missing or was taken for other kernel sources."""
+def measured_traffic(kind):
+    """Counter-measured bytes per launch of the kernel, or None when the
+    summary is missing or was taken for other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", KERNELS[kind][1])) as fh:
             kv = dict(l[1:].split(":", 1) for l in fh if l.startswith("@") and ":" in l)
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("mac_source_sha256") != mac_source_hash():
+    if kv.get("source_sha256") != source_hash(kind):
         return None
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+
+
+def lattice_len(extent):
+    L = 4
+    while L < 2 * extent - 1:
+        L *= 2
+    return L
 
 
 def config_table(ctx, reps=3):
@@ -212,17 +225,19 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--configs", action="store_true",
                     help="also time every workload (FP64 and FP32+refine) into a 'configs' entry")
-    ap.add_argument("--print-mac-hash", action="store_true",
-                    help="print the hash of the MAC kernel sources and exit")
+    ap.add_argument("--print-hash", choices=sorted(KERNELS),
+                    help="print the hash of that kernel's sources (as counter summaries record it) and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration reference)")
+    ap.add_argument("--mac", choices=["auto", "pairs", "lattice"], default="auto",
+                    help="spectral MAC method of the solves (auto: tuning table, else the cost model)")
     ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
                     help="time every compiled MAC tile shape on each new convolution shape at plan "
                          "creation (REPS launches each) and keep the fastest")
     ap.add_argument("--save-tuning", default=None, help="write the context's tuning table here")
     args = ap.parse_args()
-    if args.print_mac_hash:
-        print(mac_source_hash())
+    if args.print_hash:
+        print(source_hash(args.print_hash))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the LGF path here runs on a single MI355X and has no "
@@ -235,6 +250,7 @@ def main():
 
     torch.cuda.init()
     ctx = lgf.Context(0)
+    ctx.set_mac_method(args.mac)
     if args.autotune:
         ctx.set_autotune(args.autotune)
     prob = inputs.mstar()
@@ -297,12 +313,31 @@ def main():
     ms_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall
 
+    # roofline of the dominant kernel (per launch, HIP events on the solve stream)
     n_freq = (2 * nb) ** 2 * (nb + 1)
-    pairs = n_blocks * n_blocks
-    flops_mac = 8.0 * pairs * n_freq                       # one complex MAC = 8 flops
-    smac_ms, smac_n = r64["stages"]["smac"]
-    smac_avg = smac_ms / max(1, smac_n)
-    achieved = flops_mac / (smac_avg * 1e-3) / 1e12
+    st = r64["stages"]
+    if st["lat_z"][1] > 0:
+        ext = [int(v) for v in (prob.levels[0].blocks.max(0) - prob.levels[0].blocks.min(0) + 1)]
+        L = [lattice_len(e) for e in ext]
+        hcol = L[0] * L[1] * ext[2]
+        # z lines: H read and written once (complex float64), Khat read once (real float64)
+        bytes_z = n_freq * (2 * 16 * hcol + 8 * L[0] * L[1] * L[2])
+        z_ms = st["lat_z"][0] / st["lat_z"][1]
+        achieved = bytes_z / (z_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": KERNELS["lat_z"][0], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("lat_z"),
+                "traffic_unit": "bytes per launch (HBM, counters)", "algorithmic_bytes_per_launch": bytes_z,
+                "avg_launch_ms": z_ms, "lattice_lengths": L,
+                "mac_stage_ms_per_step": sum(st[k][0] for k in ("lat_xy", "lat_z", "lat_inv")) / args.steps}
+    else:
+        pairs = n_blocks * n_blocks
+        flops_mac = 8.0 * pairs * n_freq                       # one complex MAC = 8 flops
+        smac_avg = st["smac"][0] / max(1, st["smac"][1])
+        achieved = flops_mac / (smac_avg * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": KERNELS["smac"][0], "achieved": achieved,
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic("smac"), "traffic_unit": "bytes per launch (HBM, counters)",
+                "algorithmic_flops_per_launch": flops_mac, "avg_launch_ms": smac_avg}
 
     out = {
         "metric": METRIC,
@@ -319,7 +354,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dense 256^3 box, 4096 blocks of 16^3, dx=R/64, ring x-vorticity, "
                                "single level, scalar; value = FP64 path",
-                   "cells": cells, "block_pairs": pairs, "plan_s": round(r64["plan_s"], 3)},
+                   "cells": cells, "block_pairs": n_blocks * n_blocks, "plan_s": round(r64["plan_s"], 3),
+                   "mac_method": "lattice" if st["lat_z"][1] > 0 else "pairs"},
         "latency_ms": {"p50": _pct(r64["lat"], 50), "p99": _pct(r64["lat"], 99)},
         "err_vs_oracle": {"fp64": err(r64["u"]),
                           "fp32_refine": err(r32["u"]) if r32 else None,
@@ -331,11 +367,7 @@ def main():
             "stages_ms_per_step": {k: v[0] / args.steps for k, v in r32["stages"].items()},
             "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in r64["stages"].items()},
-        "roofline": {"bound": "alu", "kernel": MAC_KERNEL,
-                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "traffic_unit": "bytes per launch (HBM, counters)",
-                     "algorithmic_flops_per_launch": flops_mac, "avg_launch_ms": smac_avg},
+        "roofline": roof,
     }
     if not args.no_serving:
         from paper_2010_13213_amd import serve

@@ -194,37 +194,56 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
  * spectral multiply-accumulate and the inverse block FFT, on the stream the
  * launch uses (no synchronisation is added).  lgf_context_stage_times waits
  * for the recorded events, returns the summed milliseconds and launch
- * counts per stage (index 0 forward FFT, 1 spectral MAC, 2 inverse FFT,
- * 3 everything else), and clears them.  ms and launches have 4 entries.
+ * counts per stage, and clears them.  ms and launches have LGF_N_STAGES
+ * entries: 0 forward block FFT, 1 spectral MAC by block pairs, 2 inverse
+ * block FFT, 3 everything else, 4 lattice x/y DFTs, 5 lattice z lines (DFT,
+ * product with the lattice spectra, inverse DFT), 6 lattice inverse x/y
+ * DFTs (stages 4-6 form the spectral MAC of lattice convolutions).
  */
+#define LGF_N_STAGES 7
 lgf_status lgf_context_set_timing(lgf_context *ctx, int enable);
 lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
 
 /*
- * MAC tile-shape tuning.  The spectral multiply-accumulate is compiled for a
- * few tile shapes (rectangles of target rows per workgroup); which one is
- * fastest depends on the shape of the block set.  A context keeps a table
- * from convolution shape (block size, precision, components per MAC
- * launch, extent of the padded box, source and target block counts) to
- * tile shape.  Plans take the table's
- * shape when it has one, else the default shape.
+ * MAC method and tuning.  The spectral multiply-accumulate of a level
+ * convolution (at each block frequency, a convolution over the block
+ * lattice) runs either as block pairs, compiled for a few tile shapes
+ * (rectangles of target rows per workgroup), or, for boxes of at most 16
+ * blocks along each axis, as a zero-padded FFT over the block lattice with
+ * real lattice spectra (exact up to rounding, O(L^3 log L) per frequency
+ * instead of the O(E^6) pairs).  Which is fastest depends on the shape of
+ * the block set.  A context keeps a table from convolution shape (block
+ * size, precision, components per MAC launch, extent of the box, source and
+ * target block counts) to method.  Plans take the table's method when it
+ * has one, else a model (pairs at the pair kernel's arithmetic rate, the
+ * lattice FFT at half the HBM bandwidth over its bytes) picks between the
+ * default tile shape and the lattice FFT.
+ *
+ * lgf_context_set_mac_method(ctx, m): LGF_MAC_AUTO (the default) as above;
+ * LGF_MAC_PAIRS uses block pairs only; LGF_MAC_LATTICE uses the lattice FFT
+ * wherever the box allows it.  Plans made before the call keep their method.
  *
  * lgf_context_set_autotune(ctx, reps): with reps > 0 (at most 1000), plan
- * creation on this context times every compiled shape on each convolution
- * shape the table lacks (one warm-up and up to reps launches, fewer where
- * they would take more than about 200 ms, on the context's own stream, with scratch spectra the size of that convolution's, released
- * after) and records the fastest, or the default shape unless another is
- * faster by more than 3%; 0 turns this off (the default).  Results
- * do not depend on the tile shape: each target sums its sources in the same
- * order under every shape.
+ * creation on this context times every candidate (each compiled tile shape,
+ * and the lattice FFT where allowed) on each convolution shape the table
+ * lacks (one warm-up and up to reps launches, fewer where they would take
+ * more than about 200 ms, on the context's own stream, with scratch spectra
+ * the size of that convolution's, released after) and records the fastest,
+ * or the default shape unless another candidate is faster by more than 3%;
+ * 0 turns this off (the default).  Block-pair results do not depend on the
+ * tile shape (each target sums its sources in the same order under every
+ * shape); the lattice FFT differs from them by rounding only.
  * lgf_context_save_tuning / lgf_context_load_tuning write / merge the table
- * as JSON: {"version": 1, "entries": {key: {"ty": rows along y, "tz": rows
- * along z, "candidates": [[ty, tz], ...], "ms": [ms per launch, ...]}}};
+ * as JSON: {"version": 2, "entries": {key: {"choice": "pairs TYxTZ" or
+ * "lattice", "candidates": [...], "ms": [ms per launch, ...]}}};
  * candidates and ms may be empty or absent in a loaded file.  Loading
  * rejects malformed text with LGF_E_INVALID (the message names the byte)
- * and changes nothing then; an entry whose shape is not compiled for its
- * convolution is ignored at plan creation.  lgf_context_tuning_size returns the number of entries.
+ * and changes nothing then; an entry whose choice is not a candidate of its
+ * convolution is ignored at plan creation.  lgf_context_tuning_size returns
+ * the number of entries.
  */
+typedef enum { LGF_MAC_AUTO = 0, LGF_MAC_PAIRS = 1, LGF_MAC_LATTICE = 2 } lgf_mac_method;
+lgf_status lgf_context_set_mac_method(lgf_context *ctx, int method);
 lgf_status lgf_context_set_autotune(lgf_context *ctx, int reps);
 lgf_status lgf_context_save_tuning(lgf_context *ctx, const char *path);
 lgf_status lgf_context_load_tuning(lgf_context *ctx, const char *path);

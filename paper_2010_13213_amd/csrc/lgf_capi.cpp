@@ -108,7 +108,8 @@ void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
 
 size_t lgf_plan::workspace_bytes() const {
     size_t b = Fhat.bytes + Uhat.bytes + ws_fhat.bytes + ws_F.bytes + ws_psi[0].bytes + ws_psi[1].bytes +
-               ws_ppsi.bytes + ws_srcF.bytes + ws_srcf.bytes + ws_ut.bytes + ws_ush.bytes + ws_rho.bytes;
+               ws_ppsi.bytes + ws_srcF.bytes + ws_srcf.bytes + ws_ut.bytes + ws_ush.bytes + ws_rho.bytes +
+               ws_lat.bytes;
     for (const Conv *c : convs_view) {
         b += c->d_src_slot.bytes + c->d_tgt_slot.bytes + c->d_src_off.bytes + c->d_tgt_off.bytes;
         for (const auto &p : c->parts) b += p->d_rows.bytes + p->d_tiles.bytes + p->d_lanes.bytes;
@@ -354,6 +355,15 @@ lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launch
         require(ctx && ms && launches, "null arguments");
         DeviceScope ds(ctx->device);
         resolve_stage_times(ctx, ms, launches);
+    });
+}
+
+lgf_status lgf_context_set_mac_method(lgf_context *ctx, int method) {
+    return guard([&] {
+        require(ctx != nullptr, "null context");
+        require(method == LGF_MAC_AUTO || method == LGF_MAC_PAIRS || method == LGF_MAC_LATTICE,
+                "unknown MAC method");
+        ctx->mac_method = method;
     });
 }
 

@@ -1,7 +1,7 @@
 // Device-side building blocks shared by the LGF kernels (gfx950).
 //
 // * cplx<R>: a 2-vector complex number in float or double.
-// * fft_reg<N, INV>: an in-register radix-2 FFT of length N (16 or 32) on a
+// * fft_reg<N, INV>: an in-register radix-2 FFT of length N (2 to 32) on a
 //   per-thread array; all indices are compile-time so the array lives in
 //   VGPRs.  Forward uses exp(-2 pi i k / N), inverse exp(+2 pi i k / N), no
 //   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 32),
@@ -69,7 +69,7 @@ template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddl
 }
 
 template <int N> struct bitrev {
-    static constexpr int L = (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : 2;
+    static constexpr int L = (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : (N == 4) ? 2 : 1;
     static __host__ __device__ constexpr int of(int i) {
         int r = 0;
         for (int b = 0; b < L; ++b)

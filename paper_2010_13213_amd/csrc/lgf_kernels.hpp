@@ -101,6 +101,44 @@ int smac_tiles(int bx, int (*tiles)[2], int max_tiles);
 hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const void *Fhat, void *Uhat,
                        const void *Ktab, const SmacRow *rows, const SmacTile *tiles, hipStream_t s);
 
+// ---- spectral MAC by an FFT over the block lattice (lgf_lattice.hip) ----
+// Box E = (ex, ey, ez) blocks, lattice DFT lengths (lx, ly, lz), each a
+// compiled length (4, 8, 16, 32) with 2 e <= l.  Fhat / Uhat: [c][omega][slot]
+// (slot = (z ey + y) ex + x), components fstride elements apart; H:
+// [c][omega][z][ky][kx] workspace, hstride elements apart (>= n_freq ez ly lx);
+// Khat: real [omega][kz][ky][kx].
+struct LatGeom {
+    int ex, ey, ez;
+    int lx, ly, lz;
+    int nc;
+    int n_freq;
+    int64_t n_slots;        // ex * ey * ez
+    int64_t fstride, hstride;
+};
+// Octant block-spectra table (offsets 0..XD-1 etc.) of FFT edge N = 2 nb.
+struct LatSpecGeom {
+    int N;
+    int lx, ly, lz;
+    int XD, YD, ZD;
+    int n_freq;
+};
+bool lattice_len_ok(int L);
+int lattice_len(int extent);   // smallest compiled length L >= 2 extent - 1 (may not be compiled)
+// Uhat[c] = the lattice convolution of Fhat[c] with the kernel whose
+// spectrum is Khat, for the nc components: lattice_fwd (x and y DFTs into
+// H), lattice_z (z DFT, product, inverse z DFT in H), lattice_inv (inverse
+// y and x DFTs into Uhat), or all three by lattice_conv.
+hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s);
+hipError_t lattice_z(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s);
+hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s);
+hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, void *Uhat,
+                        hipStream_t s);
+// Khat for lattice lengths (lx, ly, lz) from the octant table (same
+// precision), scaled by 1 / (lx ly lz); scratch holds the complex
+// intermediate of a chunk of frequencies.
+hipError_t lattice_spectra(const LatSpecGeom &sg, bool fp32, const void *octant, void *Khat, void *scratch,
+                           size_t scratch_bytes, hipStream_t s);
+
 // ---- composite-grid kernels (lgf_composite.hip) ----
 // dst block b = src block b with the octants flagged in cover[b] zeroed.
 hipError_t mask_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,

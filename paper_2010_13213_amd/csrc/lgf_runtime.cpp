@@ -82,7 +82,7 @@ StageTimer::~StageTimer() {
 }
 
 void resolve_stage_times(lgf_context *ctx, double *ms, int64_t *launches) {
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kStages; ++i) {
         ms[i] = 0.0;
         launches[i] = 0;
     }
@@ -188,9 +188,137 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     return ctx->tables.back().get();
 }
 
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz) {
+    auto find = [&]() -> LatSpec * {
+        for (auto &t : ctx->lat_tables)
+            if (t->nb == nb && t->fp32 == fp32 && t->lx == lx && t->ly == ly && t->lz == lz) return t.get();
+        return nullptr;
+    };
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (LatSpec *t = find()) return t;
+    }
+    // offsets up to L/2 - 1 per axis
+    SpecTable *oct = get_spectra(ctx, nb, fp32, lx / 2 - 1, ly / 2 - 1, lz / 2 - 1);
+    auto t = std::make_unique<LatSpec>();
+    t->nb = nb;
+    t->fp32 = fp32;
+    t->lx = lx;
+    t->ly = ly;
+    t->lz = lz;
+    t->n_freq = oct->n_freq;
+    const size_t per_w = (size_t)lx * ly * lz;
+    t->data.alloc(ctx, (fp32 ? 4 : 8) * per_w * t->n_freq, "lattice spectra");
+    const size_t ec = fp32 ? 8 : 16;
+    const size_t chunk = std::max<size_t>(1, std::min<size_t>(t->n_freq, (size_t(256) << 20) / (ec * per_w)));
+    DeviceBuffer scratch;
+    scratch.alloc(ctx, chunk * per_w * ec, "lattice spectra scratch");
+    LatSpecGeom sg{2 * nb, lx, ly, lz, oct->XH + 1, oct->YH + 1, oct->ZH + 1, t->n_freq};
+    hip_check(lattice_spectra(sg, fp32, oct->data.ptr, t->data.ptr, scratch.ptr, scratch.bytes, ctx->stream),
+              "lattice spectra");
+    hip_check(hipStreamSynchronize(ctx->stream), "lattice spectra sync");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (LatSpec *other = find()) return other;   // built meanwhile by another thread
+    ctx->lat_tables.push_back(std::move(t));
+    return ctx->lat_tables.back().get();
+}
+
 // ------------------------------------------------------------------ plan
 
 static int roundup(int a, int m) { return (a + m - 1) / m * m; }
+
+static void upload_slots(lgf_context *ctx, Conv &c, const std::vector<int> &s_slot, const std::vector<int> &t_slot,
+                         const std::vector<int64_t> &s_off, const std::vector<int64_t> &t_off) {
+    auto up = [&](DeviceBuffer &d, const void *h, size_t n) {
+        if (n) hip_check(hipMemcpy(d.ptr, h, n, hipMemcpyHostToDevice), "upload");
+    };
+    c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
+    c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
+    c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
+    c.d_tgt_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, t_off.size()), "offsets");
+    up(c.d_src_slot, s_slot.data(), sizeof(int) * s_slot.size());
+    up(c.d_tgt_slot, t_slot.data(), sizeof(int) * t_slot.size());
+    up(c.d_src_off, s_off.data(), sizeof(int64_t) * s_off.size());
+    up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
+}
+
+// Extents in blocks of the bounding box of src and tgt.
+static void box_extent(const std::vector<Blk> &src, const std::vector<Blk> &tgt, int lo[3], int ext[3]) {
+    int hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int a = 0; a < 3; ++a) lo[a] = INT32_MAX;
+    for (const auto *v : {&src, &tgt})
+        for (const auto &b : *v)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], b.ijk[a]);
+                hi[a] = std::max(hi[a], b.ijk[a]);
+            }
+    for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a] + 1;
+}
+
+// The lattice method needs a compiled DFT length of at least 2E - 1 per axis.
+static bool lattice_feasible(const std::vector<Blk> &src, const std::vector<Blk> &tgt) {
+    if (src.empty() || tgt.empty()) return false;
+    int lo[3], ext[3];
+    box_extent(src, tgt, lo, ext);
+    for (int a = 0; a < 3; ++a)
+        if (!lattice_len_ok(lattice_len(ext[a]))) return false;
+    return true;
+}
+
+// A convolution whose MAC is the lattice FFT: slots over the tight bounding
+// box, spectra for its DFT lengths.
+static void build_conv_lattice(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt,
+                               bool fp32) {
+    lgf_context *ctx = plan->ctx;
+    int lo[3], ext[3];
+    box_extent(src, tgt, lo, ext);
+    c.method = kMethodLattice;
+    c.axis = 0;
+    c.bx = c.ty = c.tz = 0;
+    c.rs = ext[0];
+    c.ey = ext[1];
+    c.ez = ext[2];
+    for (int a = 0; a < 3; ++a) c.lo[a] = lo[a];
+    c.lx = lattice_len(ext[0]);
+    c.ly = lattice_len(ext[1]);
+    c.lz = lattice_len(ext[2]);
+    c.n_slots = (int64_t)ext[0] * ext[1] * ext[2];
+    c.fp32 = fp32;
+    c.n_src = (int)src.size();
+    c.n_tgt = (int)tgt.size();
+    c.lspec = get_lat_spectra(ctx, plan->nb, fp32, c.lx, c.ly, c.lz);
+    c.spec = get_spectra(ctx, plan->nb, fp32, c.lx / 2 - 1, c.ly / 2 - 1, c.lz / 2 - 1);
+    std::vector<int> s_slot, t_slot;
+    std::vector<int64_t> s_off, t_off;
+    auto slot_of = [&](const Blk &b) {
+        return ((b.ijk[2] - lo[2]) * ext[1] + (b.ijk[1] - lo[1])) * ext[0] + (b.ijk[0] - lo[0]);
+    };
+    for (const auto &b : src) {
+        s_slot.push_back(slot_of(b));
+        s_off.push_back(b.off);
+    }
+    for (const auto &b : tgt) {
+        t_slot.push_back(slot_of(b));
+        t_off.push_back(b.off);
+    }
+    upload_slots(ctx, c, s_slot, t_slot, s_off, t_off);
+}
+
+LatGeom lat_geom(const Conv &c, int nc) {
+    LatGeom g;
+    g.ex = c.rs;
+    g.ey = c.ey;
+    g.ez = c.ez;
+    g.lx = c.lx;
+    g.ly = c.ly;
+    g.lz = c.lz;
+    g.nc = nc;
+    g.n_freq = c.spec->n_freq;
+    g.n_slots = c.n_slots;
+    g.fstride = (int64_t)c.spec->n_freq * c.n_slots;
+    g.hstride = (int64_t)c.spec->n_freq * c.lx * c.ly * c.ez;
+    return g;
+}
 
 // Build a convolution: sources `src` and targets `tgt` (block coords of one
 // level), field offsets (in elements, per component) of each block.
@@ -370,14 +498,7 @@ static void build_conv_tile(lgf_plan *plan, Conv &c, const std::vector<Blk> &src
     // the spectra table is indexed by lattice offsets
     c.spec = axis == 1 ? get_spectra(ctx, nb, fp32, c.ey - 1, rs - 1, c.ez - 1)
                        : get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1);
-    c.d_src_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, s_slot.size()), "slots");
-    c.d_tgt_slot.alloc(ctx, sizeof(int) * std::max<size_t>(1, t_slot.size()), "slots");
-    c.d_src_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, s_off.size()), "offsets");
-    c.d_tgt_off.alloc(ctx, sizeof(int64_t) * std::max<size_t>(1, t_off.size()), "offsets");
-    up(c.d_src_slot, s_slot.data(), sizeof(int) * s_slot.size());
-    up(c.d_tgt_slot, t_slot.data(), sizeof(int) * t_slot.size());
-    up(c.d_src_off, s_off.data(), sizeof(int64_t) * s_off.size());
-    up(c.d_tgt_off, t_off.data(), sizeof(int64_t) * t_off.size());
+    upload_slots(ctx, c, s_slot, t_slot, s_off, t_off);
 }
 
 // Shape key of a convolution for the tuning table.
@@ -397,18 +518,27 @@ static std::string tune_key(int nb, bool fp32, int nc, int axis, const std::vect
     return k;
 }
 
-// Milliseconds per launch of the MAC parts of c, for the plan's components
-// per launch, on the context stream, with throw-away spectral buffers.
+// Milliseconds per launch of the spectral MAC of c (its pair parts, or the
+// lattice FFT), for the plan's components per launch, on the context
+// stream, with throw-away spectral buffers.
 static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
     lgf_context *ctx = plan->ctx;
     const int nc = plan->mac_nc;
     const int64_t fs = (int64_t)c.spec->n_freq * c.n_slots;
-    const size_t bytes = (c.fp32 ? 8 : 16) * (size_t)fs * nc;
-    DeviceBuffer F, U;
+    const size_t ec = c.fp32 ? 8 : 16;
+    const size_t bytes = ec * (size_t)fs * nc;
+    DeviceBuffer F, U, Hb;
     F.alloc(ctx, bytes, "tuning workspace");
     U.alloc(ctx, bytes, "tuning workspace");
+    if (c.method == kMethodLattice)
+        Hb.alloc(ctx, ec * (size_t)lat_geom(c, nc).hstride * nc, "tuning workspace");
     hip_check(zero_fill(F.ptr, bytes, ctx->stream), "tuning clear");
     auto run = [&] {
+        if (c.method == kMethodLattice) {
+            hip_check(lattice_conv(lat_geom(c, nc), c.fp32, F.ptr, Hb.ptr, c.lspec->data.ptr, U.ptr, ctx->stream),
+                      "tuning lattice MAC");
+            return;
+        }
         for (const auto &p : c.parts) {
             SmacGeom g = conv_geom(c, *p);
             g.fstride = fs;
@@ -438,12 +568,35 @@ static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
     return ms;
 }
 
-// Build a convolution with the MAC tile shape of the context's tuning table
-// for its shape.  With autotuning on and no entry yet, every compiled tile
-// shape is built and timed on this convolution's own geometry; the fastest
-// is recorded if it beats the default shape by more than the 3% that
-// repeated timings of one shape differ by, else the default is.  Without an
-// entry the default tile shape is used.
+// Models of a MAC launch in milliseconds, used when the tuning table has no
+// entry: block pairs at the measured arithmetic rate of the pair kernel,
+// the lattice FFT at half the HBM bandwidth over its streamed bytes (Fhat
+// read, H written, read and written, read, Uhat written, Khat read).
+static double model_pairs_ms(const Conv &c, int nc) {
+    double cmacs = 0;   // complex multiply-adds per frequency
+    for (const auto &p : c.parts) cmacs += (double)p->n_rows * p->n_tiles * c.ty * c.tz * c.bx * c.bx;
+    return 0.01 + 8.0 * cmacs * c.spec->n_freq * nc / (c.fp32 ? 80e9 : 45e9);
+}
+static double model_lattice_ms(int nb, bool fp32, int nc, const std::vector<Blk> &src, const std::vector<Blk> &tgt) {
+    int lo[3], ext[3];
+    box_extent(src, tgt, lo, ext);
+    const double nf = 4.0 * nb * nb * (nb + 1);
+    const double ec = fp32 ? 8 : 16, er = fp32 ? 4 : 8;
+    const double lx = lattice_len(ext[0]), ly = lattice_len(ext[1]), lz = lattice_len(ext[2]);
+    const double box = (double)ext[0] * ext[1] * ext[2], hcol = lx * ly * ext[2];
+    return 0.02 + nf * (ec * nc * (2 * box + 4 * hcol) + er * lx * ly * lz) / 4e9;
+}
+
+// Build a convolution with the MAC method of the context's tuning table for
+// its shape: block pairs with one of the compiled tile shapes, or (boxes up
+// to 16 blocks per axis) the lattice FFT.  With autotuning on and no entry
+// yet, every candidate is built and timed on this convolution's own
+// geometry; the fastest is recorded if it beats the default (pairs with the
+// first tile shape) by more than the 3% that repeated timings of one
+// candidate differ by, else the default is.  Without an entry the model
+// above picks between the default pairs shape and the lattice FFT.  The
+// context's method setting can restrict the candidates to block pairs or
+// (where feasible) to the lattice FFT.
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
                 int axis) {
     lgf_context *ctx = plan->ctx;
@@ -455,43 +608,56 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
             xmax = std::max(xmax, x);
         }
     const int bx = (xmax - xmin + 1) <= 8 ? 8 : 16;
-    int cand[4][2];
-    const int n_cand = smac_tiles(bx, cand, 4);
-    int ty = cand[0][0], tz = cand[0][1];
-    const std::string key = tune_key(plan->nb, fp32, plan->mac_nc, axis, src, tgt);
-    bool found = false;
+    int tiles[4][2];
+    const int n_tiles = smac_tiles(bx, tiles, 4);
+    std::vector<std::string> cand;
+    for (int i = 0; i < n_tiles; ++i) cand.push_back("pairs " + std::to_string(tiles[i][0]) + "x" + std::to_string(tiles[i][1]));
+    const bool lattice_ok = lattice_feasible(src, tgt);
+    if (lattice_ok && ctx->mac_method != LGF_MAC_PAIRS) cand.push_back("lattice");
+    if (lattice_ok && ctx->mac_method == LGF_MAC_LATTICE) cand.assign(1, "lattice");
+    auto build = [&](Conv &into, const std::string &choice) {
+        int ty = 0, tz = 0;
+        if (parse_choice(choice, ty, tz)) build_conv_lattice(plan, into, src, tgt, fp32);
+        else build_conv_tile(plan, into, src, tgt, fp32, axis, ty, tz);
+    };
+    std::string choice;
+    // a table entry timed among block-pair shapes only is kept apart
+    const std::string key = tune_key(plan->nb, fp32, plan->mac_nc, axis, src, tgt) +
+                            (lattice_ok && ctx->mac_method == LGF_MAC_PAIRS ? "_pairs" : "");
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         auto it = ctx->tune.find(key);
-        if (it != ctx->tune.end())
-            for (int i = 0; i < n_cand; ++i)   // a loaded entry must name a compiled shape
-                if (cand[i][0] == it->second.ty && cand[i][1] == it->second.tz) {
-                    ty = cand[i][0];
-                    tz = cand[i][1];
-                    found = true;
-                }
+        // a loaded entry must name a candidate of this convolution
+        if (it != ctx->tune.end() && std::find(cand.begin(), cand.end(), it->second.choice) != cand.end())
+            choice = it->second.choice;
     }
-    if (!found && ctx->autotune_reps > 0 && n_cand > 1 && !src.empty() && !tgt.empty()) {
+    if (choice.empty() && ctx->autotune_reps > 0 && cand.size() > 1 && !src.empty() && !tgt.empty()) {
         TuneEntry e;
+        e.cand = cand;
         double best = 1e300;
-        for (int i = 0; i < n_cand; ++i) {
+        for (size_t i = 0; i < cand.size(); ++i) {
             Conv trial;
-            build_conv_tile(plan, trial, src, tgt, fp32, axis, cand[i][0], cand[i][1]);
+            build(trial, cand[i]);
             const double ms = time_mac(plan, trial, ctx->autotune_reps);
-            e.cand.push_back({cand[i][0], cand[i][1]});
             e.ms.push_back(ms);
             if (i == 0 || (ms < 0.97 * e.ms[0] && ms < best)) {
                 best = ms;
-                ty = cand[i][0];
-                tz = cand[i][1];
+                choice = cand[i];
             }
         }
-        e.ty = ty;
-        e.tz = tz;
+        e.choice = choice;
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->tune[key] = e;
     }
-    build_conv_tile(plan, c, src, tgt, fp32, axis, ty, tz);
+    if (choice.empty() && cand.size() > 1 && cand.back() == "lattice") {
+        Conv trial;
+        build(trial, cand[0]);
+        choice = model_lattice_ms(plan->nb, fp32, plan->mac_nc, src, tgt) < model_pairs_ms(trial, plan->mac_nc)
+                     ? "lattice"
+                     : cand[0];
+    }
+    if (choice.empty()) choice = cand[0];
+    build(c, choice);
 }
 
 SmacGeom conv_geom(const Conv &c, const SubConv &p) {
@@ -606,7 +772,8 @@ std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, co
         const int ty = 16;   // rows per tile of the default 16-wide template
         const int64_t single = n_rows(cut, 1) * n_tiles(1, ty);
         const int64_t split = n_rows(cutx, 1) * n_tiles(1, ty) + (cuty.empty() ? 0 : n_rows(cuty, 0) * n_tiles(0, ty));
-        if (cuty.empty() || split * 5 >= single * 4) {
+        // the lattice FFT costs the same for any sources in the box
+        if (cuty.empty() || split * 5 >= single * 4 || lattice_feasible(cut, tgt)) {
             cutx = cut;
             cuty.clear();
         }
@@ -740,6 +907,10 @@ void plan_alloc_spectral(lgf_plan *plan) {
     need *= (size_t)plan->mac_nc;
     plan->Fhat.alloc(plan->ctx, need, "Fhat workspace");
     plan->Uhat.alloc(plan->ctx, need, "Uhat workspace");
+    size_t hneed = 0;
+    for (const Conv *c : plan->convs_view)
+        if (c->method == kMethodLattice) hneed = std::max(hneed, (c->fp32 ? 8 : 16) * (size_t)lat_geom(*c, 1).hstride);
+    if (hneed) plan->ws_lat.alloc(plan->ctx, hneed * (size_t)plan->mac_nc, "lattice workspace");
 }
 
 // Run one convolution for nc <= kMacComponents components:
@@ -766,8 +937,21 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
                                     c.n_slots, 1.0, s),
                   "forward block FFT");
     }
-    if (c.parts.empty())   // no source or no target: the convolution is zero
+    if (c.method == kMethodLattice) {
+        const LatGeom g = lat_geom(c, nc);
+        {
+            StageTimer t(plan->ctx, kStageLatXY, s);
+            hip_check(lattice_fwd(g, c.fp32, plan->Fhat.ptr, plan->ws_lat.ptr, s), "lattice x/y DFT");
+        }
+        {
+            StageTimer t(plan->ctx, kStageLatZ, s);
+            hip_check(lattice_z(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, s), "lattice z line");
+        }
+        StageTimer t(plan->ctx, kStageLatInv, s);
+        hip_check(lattice_inv(g, c.fp32, plan->ws_lat.ptr, plan->Uhat.ptr, s), "lattice inverse x/y DFT");
+    } else if (c.parts.empty()) {   // no source or no target: the convolution is zero
         hip_check(zero_fill(plan->Uhat.ptr, plan->Uhat.bytes, s), "clear Uhat");
+    }
     for (const auto &p : c.parts) {
         StageTimer t(plan->ctx, 1, s);
         SmacGeom g = conv_geom(c, *p);

@@ -74,13 +74,26 @@ struct JobRing {
     int next = 0;
 };
 
-// Tuning-table entry: the chosen MAC tile shape, and every candidate shape
-// timed with its milliseconds per launch.
+// Real lattice spectra Khat[omega][kz][ky][kx] for lattice DFT lengths
+// (lx, ly, lz) (lgf_lattice.hip), shared by every plan of the context.
+struct LatSpec {
+    int nb = 0;
+    bool fp32 = false;
+    int lx = 0, ly = 0, lz = 0;
+    int n_freq = 0;
+    DeviceBuffer data;
+};
+
+// Tuning-table entry: the chosen MAC method ("pairs TYxTZ": the block-pair
+// kernel with that tile shape, or "lattice"), and every candidate timed
+// with its milliseconds per launch.
 struct TuneEntry {
-    int ty = 0, tz = 0;
-    std::vector<std::array<int, 2>> cand;
+    std::string choice;
+    std::vector<std::string> cand;
     std::vector<double> ms;
 };
+// "pairs TYxTZ" -> (ty, tz) and false; "lattice" -> true; anything else throws
+bool parse_choice(const std::string &s, int &ty, int &tz);
 // The table as JSON and back (lgf_tuning.cpp); the reader throws Failure
 // (LGF_E_INVALID) on malformed text.
 std::string tuning_to_json(const std::map<std::string, TuneEntry> &table);
@@ -89,7 +102,8 @@ std::map<std::string, TuneEntry> tuning_from_json(const std::string &text);
 struct lgf_context_impl {
     int device;
     bool timing = false;
-    int autotune_reps = 0;                       // > 0: time tile shapes for new shapes
+    int autotune_reps = 0;                       // > 0: time MAC candidates for new shapes
+    int mac_method = LGF_MAC_AUTO;               // lgf_mac_method
     std::map<std::string, TuneEntry> tune;       // shape key -> tile shape (guarded by mu)
     JobRing ring;
     std::vector<StageEvent> pending;
@@ -98,6 +112,7 @@ struct lgf_context_impl {
     hipStream_t stream = nullptr;
     DeviceBuffer gcube;
     std::vector<std::unique_ptr<SpecTable>> tables;
+    std::vector<std::unique_ptr<LatSpec>> lat_tables;
     std::mutex mu;
     lgf_context_impl(int dev, size_t budget_);
 };
@@ -121,12 +136,18 @@ struct SubConv {
     DeviceBuffer d_rows, d_tiles, d_lanes;
 };
 
-// One blockwise LGF convolution on a level (sources -> targets).
+// One blockwise LGF convolution on a level (sources -> targets).  The
+// spectral MAC runs either as block pairs (parts, below) or, for boxes of at
+// most 16 blocks per axis, as an FFT over the block lattice (method 1).
+constexpr int kMethodPairs = 0, kMethodLattice = 1;
 struct Conv {
+    int method = kMethodPairs;
+    int lx = 0, ly = 0, lz = 0;     // lattice DFT lengths (method 1)
+    LatSpec *lspec = nullptr;       // lattice spectra (method 1)
     int bx = 0;             // MAC row template (8 or 16)
     int ty = 0, tz = 0;     // MAC tile shape in rows
     int axis = 0;           // rows along lattice x (0) or y (1)
-    int rs = 0;             // slots per row of the padded box: a multiple of bx
+    int rs = 0;             // slots per row of the padded box: a multiple of bx (method 1: the box extent)
     int ey = 0, ez = 0;
     int lo[3] = {0, 0, 0};
     int64_t n_slots = 0;
@@ -169,6 +190,8 @@ struct LevelSched {
 };
 
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz);
+LatGeom lat_geom(const Conv &c, int nc);
 SmacGeom conv_geom(const Conv &c, const SubConv &p);
 
 }  // namespace lgf
@@ -193,11 +216,18 @@ struct lgf_plan {
     int64_t ut_len = 0, cut_len = 0;               // elements per component in ws_ut / ws_rho and ws_ush
     int64_t dom_len = 0, ext_len = 0;              // elements per component in ws_psi and ws_ppsi / ws_src*
     lgf::DeviceBuffer Fhat, Uhat;                  // mac_nc component regions each
+    lgf::DeviceBuffer ws_lat;                      // lattice-DFT workspace H, mac_nc regions
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     size_t workspace_bytes() const;
 };
 
 namespace lgf {
+// Timed stages: block FFT forward, block-pair MAC, block FFT inverse, other,
+// lattice x/y DFTs, lattice z line (DFT, product, inverse), lattice inverse
+// x/y DFTs.
+constexpr int kStages = 7;
+enum { kStageFwd = 0, kStagePairs = 1, kStageInv = 2, kStageOther = 3, kStageLatXY = 4, kStageLatZ = 5,
+       kStageLatInv = 6 };
 // Records an event before/after a stage launch when timing is on.
 struct StageTimer {
     lgf_context *ctx;

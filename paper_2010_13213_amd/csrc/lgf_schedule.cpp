@@ -433,8 +433,21 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
         ring_mark(ctx, slot, s);
     }
     for (const ConvCall &k : calls)
-        if (k.c->parts.empty())
+        if (k.c->method == kMethodLattice) {
+            const LatGeom g = lat_geom(*k.c, 1);
+            {
+                StageTimer t(ctx, kStageLatXY, s);
+                hip_check(lattice_fwd(g, k.c->fp32, k.p->Fhat.ptr, k.p->ws_lat.ptr, s), "lattice x/y DFT");
+            }
+            {
+                StageTimer t(ctx, kStageLatZ, s);
+                hip_check(lattice_z(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, s), "lattice z line");
+            }
+            StageTimer t(ctx, kStageLatInv, s);
+            hip_check(lattice_inv(g, k.c->fp32, k.p->ws_lat.ptr, k.p->Uhat.ptr, s), "lattice inverse x/y DFT");
+        } else if (k.c->parts.empty()) {
             hip_check(zero_fill(k.p->Uhat.ptr, k.p->Uhat.bytes, s), "clear Uhat");
+        }
     // parts of one target segment are in different phases: one launch per
     // (phase, precision, template, sparse flag)
     int n_phase = 0;

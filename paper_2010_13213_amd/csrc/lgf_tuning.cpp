@@ -1,13 +1,16 @@
-// The MAC tile-shape tuning table as JSON:
+// The MAC tuning table as JSON:
 //
-//   {"version": 1, "entries": {"<shape key>": {"ty": 16, "tz": 8,
-//     "candidates": [[16, 8], [8, 8], [16, 16]], "ms": [42.7, 48.1, 45.6]}, ...}}
+//   {"version": 2, "entries": {"<shape key>": {"choice": "pairs 16x8",
+//     "candidates": ["pairs 16x8", "pairs 8x8", "pairs 16x16", "lattice"],
+//     "ms": [42.7, 48.1, 45.6, 4.1]}, ...}}
 //
-// ty / tz: the chosen tile shape (target rows along y and z per workgroup);
-// candidates / ms: every compiled shape timed and its milliseconds per MAC
-// launch (both empty for an entry written by hand).  The reader accepts any
-// JSON of this form (whitespace, key order, extra keys in an entry) and
-// rejects everything else with the byte offset of the problem.
+// choice: the MAC method of convolutions of that shape, "pairs TYxTZ" (the
+// block-pair kernel with TY x TZ target rows per workgroup) or "lattice"
+// (the FFT over the block lattice); candidates / ms: every method timed and
+// its milliseconds per MAC launch (both empty or absent for an entry written
+// by hand).  The reader accepts any JSON of this form (whitespace, key
+// order, extra keys in an entry) and rejects everything else with the byte
+// offset of the problem.
 #include <array>
 #include <cctype>
 #include <cmath>
@@ -154,19 +157,32 @@ void put_string(std::string &o, const std::string &k) {
 
 }  // namespace
 
+bool parse_choice(const std::string &c, int &ty, int &tz) {
+    if (c == "lattice") return true;
+    int a = 0, b = 0, n = 0;
+    if (std::sscanf(c.c_str(), "pairs %dx%d%n", &a, &b, &n) == 2 && n == (int)c.size() && a >= 1 && a <= 64 &&
+        b >= 1 && b <= 64) {
+        ty = a;
+        tz = b;
+        return false;
+    }
+    throw Failure(LGF_E_INVALID, "tuning choice '" + c + "' is neither 'lattice' nor 'pairs TYxTZ'");
+}
+
 std::string tuning_to_json(const std::map<std::string, TuneEntry> &table) {
-    std::string o = "{\"version\": 1, \"entries\": {";
+    std::string o = "{\"version\": 2, \"entries\": {";
     bool first = true;
     char buf[64];
     for (const auto &kv : table) {
         o += first ? "\n  " : ",\n  ";
         first = false;
         put_string(o, kv.first);
-        std::snprintf(buf, sizeof buf, ": {\"ty\": %d, \"tz\": %d, \"candidates\": [", kv.second.ty, kv.second.tz);
-        o += buf;
+        o += ": {\"choice\": ";
+        put_string(o, kv.second.choice);
+        o += ", \"candidates\": [";
         for (size_t c = 0; c < kv.second.cand.size(); ++c) {
-            std::snprintf(buf, sizeof buf, "%s[%d, %d]", c ? ", " : "", kv.second.cand[c][0], kv.second.cand[c][1]);
-            o += buf;
+            if (c) o += ", ";
+            put_string(o, kv.second.cand[c]);
         }
         o += "], \"ms\": [";
         for (size_t c = 0; c < kv.second.ms.size(); ++c) {
@@ -185,37 +201,31 @@ std::map<std::string, TuneEntry> tuning_from_json(const std::string &text) {
     bool have_entries = false;
     r.object([&](const std::string &k) {
         if (k == "version") {
-            if (r.whole(1, 1) != 1) r.fail("unknown version");
+            if (r.whole(2, 2) != 2) r.fail("unknown version");
         } else if (k == "entries") {
             have_entries = true;
             r.object([&](const std::string &key) {
                 TuneEntry e;
-                bool ty = false, tz = false;
+                bool have_choice = false;
                 r.object([&](const std::string &f) {
-                    if (f == "ty") {
-                        e.ty = r.whole(1, 64);
-                        ty = true;
-                    } else if (f == "tz") {
-                        e.tz = r.whole(1, 64);
-                        tz = true;
+                    if (f == "choice") {
+                        e.choice = r.str();
+                        int ty, tz;
+                        try {
+                            parse_choice(e.choice, ty, tz);
+                        } catch (const Failure &) {
+                            r.fail("choice is neither \"lattice\" nor \"pairs TYxTZ\"");
+                        }
+                        have_choice = true;
                     } else if (f == "candidates") {
-                        r.array([&] {
-                            std::array<int, 2> c{};
-                            int n = 0;
-                            r.array([&] {
-                                if (n >= 2) r.fail("a candidate is [ty, tz]");
-                                c[n++] = r.whole(1, 64);
-                            });
-                            if (n != 2) r.fail("a candidate is [ty, tz]");
-                            e.cand.push_back(c);
-                        });
+                        r.array([&] { e.cand.push_back(r.str()); });
                     } else if (f == "ms") {
                         r.array([&] { e.ms.push_back(r.num()); });
                     } else {
                         r.skip();
                     }
                 });
-                if (!ty || !tz) r.fail("an entry needs ty and tz");
+                if (!have_choice) r.fail("an entry needs a choice");
                 if (!e.ms.empty() && e.ms.size() != e.cand.size()) r.fail("ms and candidates differ in length");
                 out[key] = e;
             });

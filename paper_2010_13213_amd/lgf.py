@@ -23,6 +23,7 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
             "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
+            "lgf_context_set_mac_method",
             "lgf_context_tuning_size"]
 
 
@@ -58,6 +59,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblgf.so is not built (python -m paper_2010_13213_amd.build); "
                            "the LGF path has no fallback")
+    # torch first: its HIP runtime is then the one the process has loaded when
+    # the library's own dependency on the runtime is resolved, so both use a
+    # single runtime (loading the library first leaves torch without devices)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     L.lgf_context_create.argtypes = [ctypes.c_int, sz, ctypes.POINTER(vp)]
@@ -91,6 +96,8 @@ def lib():
     L.lgf_block_spectrum.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_double)]
     L.lgf_block_spectrum.restype = ctypes.c_int
+    L.lgf_context_set_mac_method.argtypes = [vp, ctypes.c_int]
+    L.lgf_context_set_mac_method.restype = ctypes.c_int
     L.lgf_context_set_autotune.argtypes = [vp, ctypes.c_int]
     L.lgf_context_set_autotune.restype = ctypes.c_int
     L.lgf_context_save_tuning.argtypes = [vp, ctypes.c_char_p]
@@ -166,7 +173,13 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("fwd_fft", "smac", "inv_fft", "other")
+    STAGES = ("fwd_fft", "smac", "inv_fft", "other", "lat_xy", "lat_z", "lat_inv")
+
+    MAC_METHODS = {"auto": 0, "pairs": 1, "lattice": 2}
+
+    def set_mac_method(self, method):
+        """'auto' (tuning table, else model), 'pairs' or 'lattice' (where the box allows it)."""
+        _check(lib().lgf_context_set_mac_method(self._h, self.MAC_METHODS[method]))
 
     def set_autotune(self, reps):
         """Time every compiled MAC tile shape on new convolution shapes (reps > 0) or not (0)."""
@@ -188,8 +201,8 @@ class Context:
 
     def stage_times(self):
         """{stage: (total_ms, launches)} since the last call; waits for the events."""
-        ms = (ctypes.c_double * 4)()
-        n = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * len(self.STAGES))()
+        n = (ctypes.c_int64 * len(self.STAGES))()
         _check(lib().lgf_context_stage_times(self._h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(self.STAGES)}
 

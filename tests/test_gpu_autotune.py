@@ -1,11 +1,13 @@
-"""MAC tile-shape tuning (lgf_context_set_autotune / save / load).
+"""MAC method tuning (lgf_context_set_autotune / save / load).
 
-Each target sums its sources in the same order under every compiled tile
-shape, so a solve must give the same bits whichever shape its convolutions
-use.  The tests force every shape through a loaded tuning table and compare
-with a context that uses the default shape, for plain and refined solves,
-a composite solve and a batched solve; autotuning itself must record one
-entry per convolution shape with a time for every candidate; a malformed
+Under the block-pair method each target sums its sources in the same order
+under every compiled tile shape, so a solve must give the same bits
+whichever shape its convolutions use.  The tests force every shape through
+a loaded tuning table on a pairs-only context and compare with the default
+shape, for plain and refined solves, a composite solve and a batched solve.
+Autotuning (every tile shape and the lattice FFT) must record one entry per
+convolution shape with a time for every candidate, pick the fastest or the
+default, and give the same bits again from the saved table; a malformed
 table is refused and leaves the context's table as it was.
 """
 import json
@@ -14,6 +16,7 @@ import numpy as np
 import pytest
 
 from paper_2010_13213_amd import inputs
+from helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -52,19 +55,25 @@ def _solve(ctx, p, precision):
 def _read(path):
     with open(path) as fh:
         doc = json.load(fh)
-    assert doc["version"] == 1
-    return [(k, e["ty"], e["tz"], [tuple(c) for c in e["candidates"]], e["ms"])
-            for k, e in doc["entries"].items()]
+    assert doc["version"] == 2
+    return [(k, e["choice"], e["candidates"], e["ms"]) for k, e in doc["entries"].items()]
 
 
 def _ext_x(key):
     return int(key.split("_ext")[1].split("x")[0])
 
 
-def _tuned_ctx(tmp_path, p, precision, shape):
-    """A context whose table sends every 16-wide convolution of p to `shape`."""
+def _ctx(method="auto"):
     from paper_2010_13213_amd import lgf
-    probe = lgf.Context(0)
+    ctx = lgf.Context(0)
+    ctx.set_mac_method(method)
+    return ctx
+
+
+def _tuned_ctx(tmp_path, p, precision, shape):
+    """A pairs-only context whose table sends every 16-wide convolution of p
+    to `shape`."""
+    probe = _ctx("pairs")
     probe.set_autotune(1)
     _solve(probe, p, precision)
     src = tmp_path / "probe.json"
@@ -72,13 +81,13 @@ def _tuned_ctx(tmp_path, p, precision, shape):
     probe.close()
     forced = tmp_path / "forced.json"
     entries = {}
-    for key, ty, tz, cand, ms in _read(src):
+    for key, choice, cand, ms in _read(src):
         if _ext_x(key) > 8:
-            ty, tz = shape
-        entries[key] = {"tz": tz, "ty": ty}          # hand-written: no timings
+            choice = "pairs %dx%d" % shape
+        entries[key] = {"choice": choice}          # hand-written: no timings
     with open(forced, "w") as fh:
-        json.dump({"entries": entries, "version": 1}, fh, indent=1)
-    ctx = lgf.Context(0)
+        json.dump({"entries": entries, "version": 2}, fh, indent=1)
+    ctx = _ctx("pairs")
     ctx.load_tuning(forced)
     return ctx
 
@@ -86,9 +95,11 @@ def _tuned_ctx(tmp_path, p, precision, shape):
 @pytest.mark.parametrize("shape", SHAPES16)
 @pytest.mark.parametrize("case,precision", [("ring", "fp64"), ("box", "fp64"), ("box", "fp32_refine"),
                                             ("composite", "fp64")])
-def test_every_tile_shape_gives_the_same_bits(gpu_ctx, tmp_path, case, precision, shape):
+def test_every_tile_shape_gives_the_same_bits(tmp_path, case, precision, shape):
     p = CASES[case]()
-    ref = _solve(gpu_ctx, p, precision)
+    ref_ctx = _ctx("pairs")
+    ref = _solve(ref_ctx, p, precision)
+    ref_ctx.close()
     ctx = _tuned_ctx(tmp_path, p, precision, shape)
     assert ctx.tuning_size() > 0
     u = _solve(ctx, p, precision)
@@ -97,11 +108,13 @@ def test_every_tile_shape_gives_the_same_bits(gpu_ctx, tmp_path, case, precision
 
 
 @pytest.mark.parametrize("shape", SHAPES16[1:])
-def test_batched_solves_with_tuned_shapes(gpu_ctx, tmp_path, shape):
+def test_batched_solves_with_tuned_shapes(tmp_path, shape):
     import torch
     from paper_2010_13213_amd import lgf
     probs = [CASES["box"](), CASES["ring"](), inputs.gaussian_box(n_blk=4, nb=8)]
-    refs = [_solve(gpu_ctx, p, "fp64") for p in probs]
+    ref_ctx = _ctx("pairs")
+    refs = [_solve(ref_ctx, p, "fp64") for p in probs]
+    ref_ctx.close()
     ctx = _tuned_ctx(tmp_path, probs[0], "fp64", shape)
     plans = [lgf.Plan.for_problem(ctx, p, "fp64") for p in probs]
     fs = [torch.from_numpy(p.flat_source()).cuda() for p in probs]
@@ -115,39 +128,38 @@ def test_batched_solves_with_tuned_shapes(gpu_ctx, tmp_path, shape):
     ctx.close()
 
 
-def test_autotune_records_every_convolution_shape(gpu_ctx, tmp_path):
-    from paper_2010_13213_amd import lgf
+def test_autotune_records_every_convolution_shape(tmp_path):
     p = CASES["composite"]()
-    ref = _solve(gpu_ctx, p, "fp64")
-    ctx = lgf.Context(0)
+    pairs = _ctx("pairs")
+    ref = _solve(pairs, p, "fp64")
+    pairs.close()
+    ctx = _ctx("auto")
     ctx.set_autotune(3)
     u = _solve(ctx, p, "fp64")
-    assert np.array_equal(u, ref)
+    assert rel_l2(u, ref) < 1e-13          # lattice choices differ by rounding only
     n = ctx.tuning_size()
     assert n > 0
     path = tmp_path / "table.json"
     ctx.save_tuning(path)
     rows = _read(path)
     assert len(rows) == n
-    for key, ty, tz, cand, ms in rows:
-        if _ext_x(key) > 8:
-            assert cand == SHAPES16 and (ty, tz) in SHAPES16 and len(ms) == len(SHAPES16)
-            assert all(m > 0 for m in ms)
-            # the fastest shape, or the default unless another beats it by 3%
-            if (ty, tz) == SHAPES16[0]:
-                assert min(ms) >= 0.97 * ms[0] * (1 - 1e-5)
-            else:
-                assert ms[SHAPES16.index((ty, tz))] == min(ms)
+    for key, choice, cand, ms in rows:
+        assert choice in cand and len(ms) == len(cand) and all(m > 0 for m in ms)
+        shapes = ["pairs %dx%d" % s for s in (SHAPES16 if _ext_x(key) > 8 else [(8, 8)])]
+        assert cand[:len(shapes)] == shapes and cand[len(shapes):] in ([], ["lattice"])
+        # the fastest, or the default unless another beats it by 3%
+        if choice == cand[0]:
+            assert min(ms) >= 0.97 * ms[0] * (1 - 1e-5)
         else:
-            assert (ty, tz) == (8, 8)
+            assert ms[cand.index(choice)] == min(ms)
     # a second plan of the same shapes times nothing new
-    _solve(ctx, p, "fp64")
+    assert np.array_equal(_solve(ctx, p, "fp64"), u)
     assert ctx.tuning_size() == n
     # the saved table loads into a fresh context and gives the same bits
-    ctx2 = lgf.Context(0)
+    ctx2 = _ctx("auto")
     ctx2.load_tuning(path)
     assert ctx2.tuning_size() == n
-    assert np.array_equal(_solve(ctx2, p, "fp64"), ref)
+    assert np.array_equal(_solve(ctx2, p, "fp64"), u)
     ctx2.close()
     ctx.close()
 
@@ -156,24 +168,25 @@ def test_malformed_table_is_refused(tmp_path):
     from paper_2010_13213_amd import lgf
     ctx = lgf.Context(0)
     good = tmp_path / "good.json"
-    good.write_text('{"version": 1, "note": ["any", {"extra": null}], "entries": {'
-                    '"nb8_f64_nc1_ext12x12x12_src1728_tgt1728": {"ty": 8, "tz": 8, "by": "hand"}}}')
+    good.write_text('{"version": 2, "note": ["any", {"extra": null}], "entries": {'
+                    '"nb8_f64_nc1_ext12x12x12_src1728_tgt1728": {"choice": "lattice", "by": "hand"}}}')
     ctx.load_tuning(good)
     assert ctx.tuning_size() == 1
-    entry = '"nb8_f64_nc1_ext9x9x9_src1_tgt1": {"ty": 16, "tz": 8}'
+    entry = '"nb8_f64_nc1_ext9x9x9_src1_tgt1": {"choice": "pairs 16x8"}'
     bad_texts = [
-        "",                                                     # empty
-        '{"version": 1}',                                       # no entries
-        '{"version": 2, "entries": {}}',                        # unknown version
-        '{"entries": {%s, "k": {"ty": 8}}}' % entry,            # tz missing
-        '{"entries": {%s, "k": {"ty": 0, "tz": 8}}}' % entry,   # out of range
-        '{"entries": {%s, "k": {"ty": 8.5, "tz": 8}}}' % entry,  # not whole
-        '{"entries": {%s, "k": {"ty": 8, "tz": 65}}}' % entry,
-        '{"entries": {%s, "k": {"ty": 8, "tz": 8, "candidates": [[8, 8]], "ms": [1, 2]}}}' % entry,
-        '{"entries": {%s, "k": {"ty": 8, "tz": 8, "candidates": [[8]]}}}' % entry,
+        "",                                                          # empty
+        '{"version": 2}',                                            # no entries
+        '{"version": 1, "entries": {}}',                             # old version
+        '{"entries": {%s, "k": {"ms": []}}}' % entry,                # choice missing
+        '{"entries": {%s, "k": {"choice": "pairs 0x8"}}}' % entry,   # out of range
+        '{"entries": {%s, "k": {"choice": "pairs 8x65"}}}' % entry,
+        '{"entries": {%s, "k": {"choice": "pairs 8x8 "}}}' % entry,  # trailing text
+        '{"entries": {%s, "k": {"choice": "fft"}}}' % entry,         # unknown method
+        '{"entries": {%s, "k": {"choice": 8}}}' % entry,             # not a string
+        '{"entries": {%s, "k": {"choice": "lattice", "candidates": ["lattice"], "ms": [1, 2]}}}' % entry,
         '{"entries": {%s}} trailing' % entry,
-        '{"entries": {%s,}}' % entry,                           # trailing comma
-        '{"entries": {%s}' % entry,                             # unclosed
+        '{"entries": {%s,}}' % entry,                                # trailing comma
+        '{"entries": {%s}' % entry,                                  # unclosed
     ]
     for text in bad_texts:
         bad = tmp_path / "bad.json"
@@ -186,4 +199,6 @@ def test_malformed_table_is_refused(tmp_path):
         ctx.load_tuning(tmp_path / "missing.json")
     with pytest.raises(lgf.LgfError):
         ctx.set_autotune(-1)
+    with pytest.raises(KeyError):
+        ctx.set_mac_method("fft")
     ctx.close()
