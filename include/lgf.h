@@ -196,9 +196,10 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
  * for the recorded events, returns the summed milliseconds and launch
  * counts per stage, and clears them.  ms and launches have LGF_N_STAGES
  * entries: 0 forward block FFT, 1 spectral MAC by block pairs, 2 inverse
- * block FFT, 3 everything else, 4 lattice x/y DFTs, 5 lattice z lines (DFT,
- * product with the lattice spectra, inverse DFT), 6 lattice inverse x/y
- * DFTs (stages 4-6 form the spectral MAC of lattice convolutions).
+ * block FFT, 3 everything else, 4 lattice x DFTs, 5 lattice y/z slabs (y
+ * and z DFTs, product with the lattice spectra, inverse z and y DFTs), 6
+ * lattice inverse x DFTs (stages 4-6 form the spectral MAC of lattice
+ * convolutions).
  */
 #define LGF_N_STAGES 7
 lgf_status lgf_context_set_timing(lgf_context *ctx, int enable);

@@ -103,14 +103,17 @@ hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const 
 
 // ---- spectral MAC by an FFT over the block lattice (lgf_lattice.hip) ----
 // Box E = (ex, ey, ez) blocks, lattice DFT lengths (lx, ly, lz), each a
-// compiled length (4, 8, 16, 32) with 2 e <= l.  Fhat / Uhat: [c][omega][slot]
-// (slot = (z ey + y) ex + x), components fstride elements apart; H:
-// [c][omega][z][ky][kx] workspace, hstride elements apart (>= n_freq ez ly lx);
-// Khat: real [omega][kz][ky][kx].
+// compiled length (4, 8, 16, 32) with 2 e <= l; N = 2 nb is the block FFT
+// edge (n_freq = N^2 (N/2 + 1)).  Fhat / Uhat: [c][omega][slot] (slot =
+// (z ey + y) ex + x), components fstride elements apart; H:
+// [c][omega][kx][z][y] workspace, components hstride (>= n_freq lx ey ez)
+// elements apart; Khat: real [omega_r][kx][kz][ky] over the stored
+// frequencies (ky, kz in [0, N/2]).
 struct LatGeom {
     int ex, ey, ez;
     int lx, ly, lz;
     int nc;
+    int N;
     int n_freq;
     int64_t n_slots;        // ex * ey * ez
     int64_t fstride, hstride;
@@ -120,16 +123,16 @@ struct LatSpecGeom {
     int N;
     int lx, ly, lz;
     int XD, YD, ZD;
-    int n_freq;
 };
 bool lattice_len_ok(int L);
-int lattice_len(int extent);   // smallest compiled length L >= 2 extent - 1 (may not be compiled)
+int lattice_len(int extent);   // smallest length L >= max(4, 2 extent - 1) (compiled up to 32)
+int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (N/2 + 1)^3
 // Uhat[c] = the lattice convolution of Fhat[c] with the kernel whose
-// spectrum is Khat, for the nc components: lattice_fwd (x and y DFTs into
-// H), lattice_z (z DFT, product, inverse z DFT in H), lattice_inv (inverse
-// y and x DFTs into Uhat), or all three by lattice_conv.
+// spectrum is Khat, for the nc components: lattice_fwd (x DFTs into H),
+// lattice_yz (y and z DFTs, product, inverse z and y DFTs in H),
+// lattice_inv (inverse x DFTs into Uhat), or all three by lattice_conv.
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s);
-hipError_t lattice_z(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s);
+hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s);
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s);
 hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, void *Uhat,
                         hipStream_t s);

@@ -13,21 +13,32 @@
 //     Khat(omega, k) = sum_d K_d(omega) exp(-2 pi i k.d / L),
 //
 // with d in (-L/2, L/2) per axis (d = L/2 is never reached and is set to
-// zero).  K_{-d}(omega) is the complex conjugate of K_d(omega) (the window
-// of a real, even kernel mirrored), so Khat is real: it is stored as real
-// numbers with the 1 / (Lx Ly Lz) of the inverse folded in.  The cost per
-// frequency is O(L^3 log L) instead of the O(E^6) block pairs.
+// zero).  Two symmetries of the block windows of the real kernel, which is
+// even along each axis, shape the spectra:
+//   * K_{-d}(omega) = conj(K_d(omega)), so Khat is real;
+//   * mirroring d along y (z) mirrors omega along y (z), so
+//     Khat(omega, k) = Khat(R omega, R k) for R a y and/or z reflection:
+//     only frequencies with ky, kz in [0, N/2] are stored (28% at N = 32).
+// Khat is stored as real numbers with the 1 / (Lx Ly Lz) of the inverse
+// folded in.  The cost per frequency is O(L^3 log L) instead of the O(E^6)
+// block pairs.
 //
 // Layouts (complex R, per component region):
 //   Fhat, Uhat [omega][slot], slot = (z Ey + y) Ex + x over the box E;
-//   H          [omega][z][ky][kx], z < Ez: the box after the x and y DFTs;
-//   Khat       [omega][kz][ky][kx] (real R).
-// Three kernels: xy forward (one workgroup per PL planes (component, omega,
-// z), LDS-staged, register FFTs per line), z (a lane pair per column
-// (omega, ky, kx): DFT, product with Khat, inverse DFT, in place), xy
-// inverse.  Each streams its data once from HBM.  The spectra Khat are
-// built once per (nb, precision, Lx, Ly, Lz) from the octant table of
-// block spectra with the same line FFTs.
+//   H          [omega][kx][z][y]: the box after the x DFT (kx < Lx);
+//   Khat       [omega_r][kx][kz][ky] (real R), omega_r over the stored
+//              frequencies.
+// Three kernels, each streaming its data once from HBM:
+//   lat_x_fwd  x lines of Fhat -> H (a lane pair per line);
+//   lat_yz     one (omega, kx) slab per 2 Ly lanes, in LDS: y DFT, z DFT,
+//              product with Khat, inverse z and y DFTs, in place in H;
+//   lat_x_inv  inverse x lines of H, cropped, -> Uhat.
+// Inputs beyond E are zero (E <= L/2) and outputs beyond E are dropped, so
+// every line is split over a lane pair by the radix-2 identities
+// (M = L/2, w = exp(-2 pi i / L)):
+//   X[2m] = DFT_M(x)[m],  X[2m+1] = DFT_M(w^n x)[m]                (forward)
+//   y[n]  = IDFT_M(X[2m])[n] + w^-n IDFT_M(X[2m+1])[n],  n < M      (inverse)
+// the inverse with one exchange of half a line between the two lanes.
 #include <algorithm>
 #include <type_traits>
 
@@ -42,171 +53,207 @@ constexpr int kLatThreads = 256;
 
 template <typename R> __device__ __forceinline__ cplx<R> czero() { return cmake<R>((R)0, (R)0); }
 
-// Forward DFT of the x and y axes of PL planes (component, omega, z).
-template <typename R, int LX, int LY>
-__global__ void __launch_bounds__(kLatThreads) lat_fwd_xy(LatGeom g, const cplx<R> *__restrict__ F,
-                                                          cplx<R> *__restrict__ H) {
-    constexpr int PL = kLatThreads / LX;      // planes per workgroup
-    constexpr int YR = LY / 2;                // rows of a plane that can hold data (Ey <= LY/2)
-    __shared__ cplx<R> X[PL * YR * LX];
-    const int t = threadIdx.x;
-    const int ex = g.ex, ey = g.ey, ez = g.ez;
-    const int64_t n_items = (int64_t)g.nc * g.n_freq * ez;
-    const int64_t item0 = (int64_t)blockIdx.x * PL;
-    const int plane = ey * ex;
-    // 1. coalesced load of the planes into rows of X (row stride LX)
-    for (int e = t; e < PL * plane; e += kLatThreads) {
-        const int p = e / plane, r = e % plane;
-        const int64_t item = item0 + p;
-        if (item >= n_items) break;
-        const int64_t cw = item / ez;                  // c * n_freq + omega
-        const int z = (int)(item % ez);
-        const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-        const cplx<R> v = F[c * g.fstride + w * g.n_slots + (int64_t)z * plane + r];
-        X[(p * YR + r / ex) * LX + r % ex] = v;
+// c ? a : b per component (a select of whole structs is lowered through
+// private memory)
+template <typename R> __device__ __forceinline__ cplx<R> csel(bool c, cplx<R> a, cplx<R> b) {
+    return cmake<R>(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// Forward half-line DFT of a lane pair: a holds x[n] (n < L/2, zero beyond
+// the data); on return a[m] = X[2m + odd].
+template <typename R, int L> __device__ __forceinline__ void pair_fwd(cplx<R> (&a)[L / 2], int odd) {
+#pragma unroll
+    for (int n = 1; n < L / 2; ++n) {
+        // select on data, not on the twiddle: the constants stay literal
+        const cplx<R> t = cmul(a[n], twiddle<R, L, false>(n));
+        a[n] = csel(odd, t, a[n]);
     }
-    __syncthreads();
-    // 2. x lines (p, y), y < ey
-    for (int e = t; e < PL * ey; e += kLatThreads) {
-        const int p = e / ey, y = e % ey;
-        cplx<R> a[LX];
-        cplx<R> *row = X + (p * YR + y) * LX;
+    fft_reg<R, L / 2, false>(a);
+}
+
+// Inverse half-line DFT of a lane pair: a holds X[2m + odd] (m < L/2); on
+// return out[j] = y[n] with n = j (even lane) or L/4 + j (odd lane),
+// j < L/4.  Both lanes of every pair must call it (one exchange).
+template <typename R, int L>
+__device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (&out)[L / 4]) {
+    constexpr int M = L / 2;
+    fft_reg<R, M, true>(a);
 #pragma unroll
-        for (int x = 0; x < LX; ++x) a[x] = x < ex ? row[x] : czero<R>();
-        fft_reg<R, LX, false>(a);
-#pragma unroll
-        for (int x = 0; x < LX; ++x) row[x] = a[x];
-    }
-    __syncthreads();
-    // 3. y lines (p, kx) -> H
-    {
-        const int p = t / LX, kx = t % LX;
-        const int64_t item = item0 + p;
-        if (item < n_items) {
-            cplx<R> a[LY];
-#pragma unroll
-            for (int y = 0; y < LY; ++y) a[y] = y < ey ? X[(p * YR + y) * LX + kx] : czero<R>();
-            fft_reg<R, LY, false>(a);
-            const int64_t cw = item / ez;
-            const int z = (int)(item % ez);
-            const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-            cplx<R> *out = H + c * g.hstride + (w * ez + z) * (int64_t)(LY * LX) + kx;
-#pragma unroll
-            for (int ky = 0; ky < LY; ++ky) out[ky * LX] = a[ky];
-        }
+    for (int j = 0; j < M / 2; ++j) {
+        const int jo = M / 2 + j;   // the odd lane's output index
+        const cplx<R> send = csel(odd, a[j], a[jo]);
+        cplx<R> recv;
+        recv.x = __shfl_xor(send.x, 1);
+        recv.y = __shfl_xor(send.y, 1);
+        const cplx<R> ye = cadd(a[j], cmul(recv, twiddle<R, L, true>(j)));     // even lane: n = j
+        const cplx<R> yo = cadd(recv, cmul(a[jo], twiddle<R, L, true>(jo)));   // odd lane: n = jo
+        out[j] = csel(odd, yo, ye);
     }
 }
 
-// z lines: DFT, product with the real spectrum, inverse DFT, in place.
-// The input of a line is zero beyond ez <= LZ/2 and only its first LZ/2
-// outputs are kept, so each line is split over a pair of lanes by the
-// radix-2 identities (M = LZ/2, w = exp(-2 pi i / LZ)):
-//   X[2m]   = DFT_M(x)[m],            X[2m+1] = DFT_M(w^n x)[m],
-//   y[n]    = IDFT_M(X[2m] K[2m])[n] + w^-n IDFT_M(X[2m+1] K[2m+1])[n], n < M.
-// The even lane does the first half, the odd lane the second; one exchange
-// of half a line each way forms y.  Half-length lines halve the registers
-// a lane holds.
-template <typename R, int LZ>
-__global__ void __launch_bounds__(kLatThreads) lat_z(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat) {
-    constexpr int M = LZ / 2;
-    const int64_t plane = (int64_t)g.lx * g.ly;
-    const int64_t gid = (int64_t)blockIdx.x * kLatThreads + threadIdx.x;
-    const int64_t col = gid >> 1;                          // omega * plane + (ky, kx)
-    const int odd = (int)(gid & 1);
-    // both lanes of a pair stay to the exchange; a dead pair only skips memory
-    const bool live = col < (int64_t)g.n_freq * plane;
-    const int64_t w = live ? col / plane : 0, q = live ? col % plane : 0;
-    const int ez = g.ez;
-    // the spectrum column is read once per component; later components find
-    // it in L2
-    const R *kc = Khat + (w * LZ + odd) * plane + q;       // kz = 2m + odd
-    for (int c = 0; c < g.nc; ++c) {
-        cplx<R> *hc = H + c * g.hstride + w * ez * plane + q;
-        cplx<R> a[M];
+// x lines of Fhat -> H.  128 lines per workgroup, a lane pair each; the
+// lines are staged through LDS so that the loads are coalesced.
+template <typename R, int LX>
+__global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
+                                                         cplx<R> *__restrict__ H) {
+    constexpr int M = LX / 2, RW = kLatThreads / 2, SP = M + 1;   // rows padded against bank conflicts
+    __shared__ cplx<R> S[RW * SP];
+    const int t = threadIdx.x;
+    const int ex = g.ex;
+    const int64_t per_w = (int64_t)g.ey * g.ez, n_rows = (int64_t)g.nc * g.n_freq * per_w;
+    const int64_t row0 = (int64_t)blockIdx.x * RW;
+    for (int e = t; e < RW * ex; e += kLatThreads) {
+        const int rl = e / ex, x = e % ex;
+        const int64_t r = row0 + rl;
+        if (r >= n_rows) break;
+        const int64_t cw = r / per_w, q = r % per_w;
+        const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
+        S[rl * SP + x] = F[c * g.fstride + w * g.n_slots + q * ex + x];
+    }
+    __syncthreads();
+    const int rl = t >> 1, odd = t & 1;
+    const int64_t r = row0 + rl;
+    if (r >= n_rows) return;
+    cplx<R> a[M];
 #pragma unroll
-        for (int n = 0; n < M; ++n) {
-            const cplx<R> x = (live && n < ez) ? hc[n * plane] : czero<R>();
-            // select on data, not on the twiddle: constants stay literal
-            a[n] = (n > 0 && odd) ? cmul(x, twiddle<R, LZ, false>(n)) : x;
-        }
-        fft_reg<R, M, false>(a);
+    for (int n = 0; n < M; ++n) a[n] = n < ex ? S[rl * SP + n] : czero<R>();
+    pair_fwd<R, LX>(a, odd);
+    const int64_t cw = r / per_w, q = r % per_w;
+    const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
+    cplx<R> *out = H + c * g.hstride + w * LX * per_w + q;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const R k = live ? kc[2 * m * plane] : (R)0;
+    for (int m = 0; m < M; ++m) out[(2 * m + odd) * per_w] = a[m];
+}
+
+// One (c, omega, kx) slab of H per 2 Ly lanes: y DFT, z DFT, product with
+// the spectra, inverse z and y DFTs, in place.
+template <typename R, int LY, int LZ>
+__global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat) {
+    constexpr int SL = kLatThreads / (2 * LY);          // slabs per workgroup
+    constexpr int MY = LY / 2, MZ = LZ / 2;
+    // lines padded by one element: unpadded, the lines a wave reads at once
+    // start 256 B apart and fall into one LDS bank
+    constexpr int PY = MY + 1, QZ = MZ + 1;
+    __shared__ cplx<R> P[SL * MZ * PY];   // slab [s][z][y]
+    __shared__ cplx<R> Q[SL * LY * QZ];   // after the y DFT [s][ky][z]
+    const int t = threadIdx.x;
+    const int ey = g.ey, ez = g.ez, slab = ey * ez;
+    const int64_t per_c = (int64_t)g.n_freq * g.lx;     // slabs per component
+    const int64_t n_slabs = (int64_t)g.nc * per_c;
+    const int64_t s0 = (int64_t)blockIdx.x * SL;
+    // 1. load the slabs ([c][omega][kx] slabs are consecutive within a component)
+    for (int e = t; e < SL * slab; e += kLatThreads) {
+        const int sl = e / slab, q = e % slab;
+        const int64_t si = s0 + sl;
+        if (si >= n_slabs) break;
+        P[(sl * MZ + q / ey) * PY + q % ey] = H[(si / per_c) * g.hstride + (si % per_c) * slab + q];
+    }
+    __syncthreads();
+    // 2. y lines (s, z), z < ez: Ey inputs -> Ly outputs
+    for (int e = t; e < SL * MZ * 2; e += kLatThreads) {
+        const int odd = e & 1, line = e >> 1, sl = line / MZ, z = line % MZ;
+        if (z >= ez || s0 + sl >= n_slabs) continue;
+        cplx<R> a[MY];
+#pragma unroll
+        for (int n = 0; n < MY; ++n) a[n] = n < ey ? P[(sl * MZ + z) * PY + n] : czero<R>();
+        pair_fwd<R, LY>(a, odd);
+#pragma unroll
+        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + odd) * QZ + z] = a[m];
+    }
+    __syncthreads();
+    // 3. z lines (s, ky): exactly one lane pair per line (SL * LY * 2 lanes)
+    {
+        const int odd = t & 1, line = t >> 1, sl = line / LY, ky = line % LY;
+        const int64_t si = s0 + sl;
+        const bool live = si < n_slabs;
+        const int64_t wk = live ? si % per_c : 0;
+        const int w = (int)(wk / g.lx), kx = (int)(wk % g.lx);
+        // stored frequency and reflections of omega = (kz N + ky) Hh + kx
+        const int N = g.N, Hh = N / 2 + 1;
+        const int fx = w % Hh, fyv = (w / Hh) % N, fzv = w / (Hh * N);
+        const bool ry = fyv > N / 2, rz = fzv > N / 2;
+        const int wr = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
+        const int kyk = ry ? (LY - ky) % LY : ky;
+        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;   // [kz][ky] plane of the slab
+        cplx<R> *qline = Q + (sl * LY + ky) * QZ;
+        cplx<R> a[MZ];
+#pragma unroll
+        for (int n = 0; n < MZ; ++n) a[n] = n < ez ? qline[n] : czero<R>();
+        pair_fwd<R, LZ>(a, odd);
+#pragma unroll
+        for (int m = 0; m < MZ; ++m) {
+            const int kz = 2 * m + odd;
+            const R k = live ? kc[(rz ? (LZ - kz) % LZ : kz) * LY] : (R)0;
             a[m] = cmake<R>(a[m].x * k, a[m].y * k);
         }
-        fft_reg<R, M, true>(a);
-        // even lane: y[j] = E[j] + w^-j O[j]; odd lane: y[M/2+j] likewise
+        cplx<R> out[LZ / 4];
+        pair_inv<R, LZ>(a, odd, out);
 #pragma unroll
-        for (int j = 0; j < (M + 1) / 2; ++j) {
-            const int jo = M / 2 + j;           // the odd lane's output index
-            if (jo >= M) break;
-            const cplx<R> send = odd ? a[j] : a[jo];
-            cplx<R> recv;
-            recv.x = __shfl_xor(send.x, 1);
-            recv.y = __shfl_xor(send.y, 1);
-            const int n = odd ? jo : j;
-            const cplx<R> ye = cadd(a[j], cmul(recv, twiddle<R, LZ, true>(j)));    // even lane: n = j
-            const cplx<R> yo = cadd(recv, cmul(a[jo], twiddle<R, LZ, true>(jo)));  // odd lane: n = jo
-            const cplx<R> y = odd ? yo : ye;
-            if (live && n < ez) hc[n * plane] = y;
+        for (int j = 0; j < LZ / 4; ++j) {
+            const int n = odd ? MZ / 2 + j : j;
+            if (n < ez) qline[n] = out[j];
         }
+    }
+    __syncthreads();
+    // 4. inverse y lines (s, z): Ly inputs -> Ey outputs; every lane takes
+    // part in each round (the exchange), idle ones with zeros
+    for (int base = 0; base < SL * MZ * 2; base += kLatThreads) {
+        const int e = base + t;
+        const int odd = e & 1, line = e >> 1, sl = line / MZ, z = line % MZ;
+        const bool on = e < SL * MZ * 2 && z < ez && s0 + sl < n_slabs;
+        cplx<R> a[MY];
+#pragma unroll
+        for (int m = 0; m < MY; ++m) a[m] = on ? Q[(sl * LY + 2 * m + odd) * QZ + z] : czero<R>();
+        cplx<R> out[LY / 4];
+        pair_inv<R, LY>(a, odd, out);
+#pragma unroll
+        for (int j = 0; j < LY / 4; ++j) {
+            const int n = odd ? MY / 2 + j : j;
+            if (on && n < ey) P[(sl * MZ + z) * PY + n] = out[j];
+        }
+    }
+    __syncthreads();
+    // 5. store the slabs back
+    for (int e = t; e < SL * slab; e += kLatThreads) {
+        const int sl = e / slab, q = e % slab;
+        const int64_t si = s0 + sl;
+        if (si >= n_slabs) break;
+        H[(si / per_c) * g.hstride + (si % per_c) * slab + q] = P[(sl * MZ + q / ey) * PY + q % ey];
     }
 }
 
-// Inverse DFT of the y and x axes, cropped to the box, into Uhat.
-template <typename R, int LX, int LY>
-__global__ void __launch_bounds__(kLatThreads) lat_inv_xy(LatGeom g, const cplx<R> *__restrict__ H,
-                                                          cplx<R> *__restrict__ U) {
-    constexpr int PL = kLatThreads / LX;
-    constexpr int YR = LY / 2;
-    __shared__ cplx<R> X[PL * YR * LX];
+// Inverse x lines of H, cropped to the box, -> Uhat (staged through LDS for
+// coalesced stores).  Every lane reaches the exchange.
+template <typename R, int LX>
+__global__ void __launch_bounds__(kLatThreads) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
+                                                         cplx<R> *__restrict__ U) {
+    constexpr int M = LX / 2, RW = kLatThreads / 2, SP = M + 1;   // rows padded against bank conflicts
+    __shared__ cplx<R> S[RW * SP];
     const int t = threadIdx.x;
-    const int ex = g.ex, ey = g.ey, ez = g.ez;
-    const int64_t n_items = (int64_t)g.nc * g.n_freq * ez;
-    const int64_t item0 = (int64_t)blockIdx.x * PL;
-    const int plane = ey * ex;
-    // 1. y lines (p, kx) from H, keep y < ey
-    {
-        const int p = t / LX, kx = t % LX;
-        const int64_t item = item0 + p;
-        if (item < n_items) {
-            const int64_t cw = item / ez;
-            const int z = (int)(item % ez);
-            const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-            const cplx<R> *in = H + c * g.hstride + (w * ez + z) * (int64_t)(LY * LX) + kx;
-            cplx<R> a[LY];
+    const int ex = g.ex;
+    const int64_t per_w = (int64_t)g.ey * g.ez, n_rows = (int64_t)g.nc * g.n_freq * per_w;
+    const int64_t row0 = (int64_t)blockIdx.x * RW;
+    const int rl = t >> 1, odd = t & 1;
+    const int64_t r = row0 + rl;
+    const bool on = r < n_rows;
+    const int64_t cw = on ? r / per_w : 0, q = on ? r % per_w : 0;
+    const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
+    const cplx<R> *in = H + c * g.hstride + w * LX * per_w + q;
+    cplx<R> a[M];
 #pragma unroll
-            for (int ky = 0; ky < LY; ++ky) a[ky] = in[ky * LX];
-            fft_reg<R, LY, true>(a);
+    for (int m = 0; m < M; ++m) a[m] = on ? in[(2 * m + odd) * per_w] : czero<R>();
+    cplx<R> out[LX / 4];
+    pair_inv<R, LX>(a, odd, out);
 #pragma unroll
-            for (int y = 0; y < LY; ++y)
-                if (y < ey) X[(p * YR + y) * LX + kx] = a[y];
-        }
-    }
+    for (int j = 0; j < LX / 4; ++j) S[rl * SP + (odd ? M / 2 + j : j)] = out[j];
     __syncthreads();
-    // 2. x lines (p, y), keep x < ex (in place, row start)
-    for (int e = t; e < PL * ey; e += kLatThreads) {
-        const int p = e / ey, y = e % ey;
-        cplx<R> *row = X + (p * YR + y) * LX;
-        cplx<R> a[LX];
-#pragma unroll
-        for (int x = 0; x < LX; ++x) a[x] = row[x];
-        fft_reg<R, LX, true>(a);
-#pragma unroll
-        for (int x = 0; x < LX; ++x)
-            if (x < ex) row[x] = a[x];
-    }
-    __syncthreads();
-    // 3. coalesced store of the cropped planes
-    for (int e = t; e < PL * plane; e += kLatThreads) {
-        const int p = e / plane, r = e % plane;
-        const int64_t item = item0 + p;
-        if (item >= n_items) break;
-        const int64_t cw = item / ez;
-        const int z = (int)(item % ez);
-        const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-        U[c * g.fstride + w * g.n_slots + (int64_t)z * plane + r] = X[(p * YR + r / ex) * LX + r % ex];
+    for (int e = t; e < RW * ex; e += kLatThreads) {
+        const int rr = e / ex, x = e % ex;
+        const int64_t r2 = row0 + rr;
+        if (r2 >= n_rows) break;
+        const int64_t cw2 = r2 / per_w, q2 = r2 % per_w;
+        const int64_t c2 = cw2 / g.n_freq, w2 = cw2 % g.n_freq;
+        U[c2 * g.fstride + w2 * g.n_slots + q2 * ex + x] = S[rr * SP + x];
     }
 }
 
@@ -236,7 +283,15 @@ __device__ __forceinline__ int lat_offset(int p, int L, bool &used) {
     return 2 * p < L ? p : p - L;
 }
 
-// One (omega, pz) plane per workgroup: gather K_d, DFT along x then y, into S.
+// stored frequency index -> block frequency omega (ky, kz in [0, N/2])
+__device__ __forceinline__ int stored_omega(int wr, int N) {
+    const int Hh = N / 2 + 1;
+    const int kx = wr % Hh, ky = (wr / Hh) % Hh, kz = wr / (Hh * Hh);
+    return (kz * N + ky) * Hh + kx;
+}
+
+// One (stored omega, pz) plane per workgroup: gather K_d, DFT along x then
+// y, into S[wl][pz][ky][kx].
 template <typename R, int LX, int LY>
 __global__ void __launch_bounds__(kLatThreads) latspec_xy(LatSpecGeom s, const cplx<R> *__restrict__ T,
                                                           cplx<R> *__restrict__ S, int w0, int nw) {
@@ -244,7 +299,7 @@ __global__ void __launch_bounds__(kLatThreads) latspec_xy(LatSpecGeom s, const c
     const int t = threadIdx.x;
     const int wl = blockIdx.x / s.lz, pz = blockIdx.x % s.lz;
     if (wl >= nw) return;
-    const int w = w0 + wl;
+    const int w = stored_omega(w0 + wl, s.N);
     bool uz;
     const int dz = lat_offset(pz, s.lz, uz);
     for (int py = t; py < LY; py += kLatThreads) {
@@ -273,7 +328,8 @@ __global__ void __launch_bounds__(kLatThreads) latspec_xy(LatSpecGeom s, const c
     }
 }
 
-// z DFT of each column of S; the real part, scaled, into Khat.
+// z DFT of each column of S; the real part, scaled, into
+// Khat[wr][kx][kz][ky].
 template <typename R, int LZ>
 __global__ void __launch_bounds__(kLatThreads) latspec_z(LatSpecGeom s, const cplx<R> *__restrict__ S,
                                                          R *__restrict__ Khat, int w0, int nw, R scale) {
@@ -281,13 +337,14 @@ __global__ void __launch_bounds__(kLatThreads) latspec_z(LatSpecGeom s, const cp
     const int64_t col = (int64_t)blockIdx.x * kLatThreads + threadIdx.x;
     if (col >= (int64_t)nw * plane) return;
     const int64_t wl = col / plane, q = col % plane;
+    const int ky = (int)(q / s.lx), kx = (int)(q % s.lx);
     cplx<R> a[LZ];
 #pragma unroll
     for (int pz = 0; pz < LZ; ++pz) a[pz] = S[(wl * LZ + pz) * plane + q];
     fft_reg<R, LZ, false>(a);
-    R *out = Khat + ((int64_t)(w0 + wl) * LZ) * plane + q;
+    R *out = Khat + ((int64_t)(w0 + wl) * s.lx + kx) * LZ * s.ly + ky;
 #pragma unroll
-    for (int kz = 0; kz < LZ; ++kz) out[kz * plane] = a[kz].x * scale;
+    for (int kz = 0; kz < LZ; ++kz) out[kz * s.ly] = a[kz].x * scale;
 }
 
 // ---- dispatch over the compiled lattice lengths ----
@@ -303,38 +360,37 @@ template <typename F> hipError_t with_len(int L, F &&f) {
 }
 
 template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void *H, hipStream_t s) {
-    const int64_t items = (int64_t)g.nc * g.n_freq * g.ez;
+    const int64_t rows = (int64_t)g.nc * g.n_freq * g.ey * g.ez;
+    const unsigned blocks = (unsigned)((rows + kLatThreads / 2 - 1) / (kLatThreads / 2));
     return with_len(g.lx, [&](auto lx) {
-        return with_len(g.ly, [&](auto ly) {
-            constexpr int LX = decltype(lx)::value, LY = decltype(ly)::value;
-            constexpr int PL = kLatThreads / LX;
-            hipLaunchKernelGGL((lat_fwd_xy<R, LX, LY>), dim3((unsigned)((items + PL - 1) / PL)), dim3(kLatThreads),
-                               0, s, g, (const cplx<R> *)F, (cplx<R> *)H);
-            return hipGetLastError();
-        });
-    });
-}
-
-template <typename R> hipError_t z_impl(const LatGeom &g, void *H, const void *Khat, hipStream_t s) {
-    const int64_t lanes = 2 * (int64_t)g.n_freq * g.lx * g.ly;   // two lanes per z line
-    return with_len(g.lz, [&](auto lz) {
-        constexpr int LZ = decltype(lz)::value;
-        hipLaunchKernelGGL((lat_z<R, LZ>), dim3((unsigned)((lanes + kLatThreads - 1) / kLatThreads)),
-                           dim3(kLatThreads), 0, s, g, (cplx<R> *)H, (const R *)Khat);
+        constexpr int LX = decltype(lx)::value;
+        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)F,
+                           (cplx<R> *)H);
         return hipGetLastError();
     });
 }
 
-template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
-    const int64_t items = (int64_t)g.nc * g.n_freq * g.ez;
-    return with_len(g.lx, [&](auto lx) {
-        return with_len(g.ly, [&](auto ly) {
-            constexpr int LX = decltype(lx)::value, LY = decltype(ly)::value;
-            constexpr int PL = kLatThreads / LX;
-            hipLaunchKernelGGL((lat_inv_xy<R, LX, LY>), dim3((unsigned)((items + PL - 1) / PL)), dim3(kLatThreads),
-                               0, s, g, (const cplx<R> *)H, (cplx<R> *)U);
+template <typename R> hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, hipStream_t s) {
+    const int64_t slabs = (int64_t)g.nc * g.n_freq * g.lx;
+    return with_len(g.ly, [&](auto ly) {
+        return with_len(g.lz, [&](auto lz) {
+            constexpr int LY = decltype(ly)::value, LZ = decltype(lz)::value;
+            constexpr int SL = kLatThreads / (2 * LY);
+            hipLaunchKernelGGL((lat_yz<R, LY, LZ>), dim3((unsigned)((slabs + SL - 1) / SL)), dim3(kLatThreads), 0,
+                               s, g, (cplx<R> *)H, (const R *)Khat);
             return hipGetLastError();
         });
+    });
+}
+
+template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
+    const int64_t rows = (int64_t)g.nc * g.n_freq * g.ey * g.ez;
+    const unsigned blocks = (unsigned)((rows + kLatThreads / 2 - 1) / (kLatThreads / 2));
+    return with_len(g.lx, [&](auto lx) {
+        constexpr int LX = decltype(lx)::value;
+        hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)H,
+                           (cplx<R> *)U);
+        return hipGetLastError();
     });
 }
 
@@ -343,8 +399,9 @@ template <typename R> hipError_t spec_impl(const LatSpecGeom &sg, const void *T,
     const int64_t per_w = (int64_t)sg.lx * sg.ly * sg.lz;
     const int64_t chunk = std::max<int64_t>(1, (int64_t)(scratch_bytes / (sizeof(cplx<R>) * per_w)));
     const R scale = (R)(1.0 / (double)per_w);
-    for (int64_t w0 = 0; w0 < sg.n_freq; w0 += chunk) {
-        const int nw = (int)std::min<int64_t>(chunk, sg.n_freq - w0);
+    const int n_stored = lattice_stored_freqs(sg.N);
+    for (int64_t w0 = 0; w0 < n_stored; w0 += chunk) {
+        const int nw = (int)std::min<int64_t>(chunk, n_stored - w0);
         hipError_t e = with_len(sg.lx, [&](auto lx) {
             return with_len(sg.ly, [&](auto ly) {
                 constexpr int LX = decltype(lx)::value, LY = decltype(ly)::value;
@@ -376,9 +433,12 @@ int lattice_len(int extent) {
     return L;
 }
 
+int lattice_stored_freqs(int N) { return (N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1); }
+
 static bool geom_ok(const LatGeom &g) {
     return lattice_len_ok(g.lx) && lattice_len_ok(g.ly) && lattice_len_ok(g.lz) && g.nc >= 1 && g.ex >= 1 &&
-           g.ey >= 1 && g.ez >= 1 && 2 * g.ex <= g.lx && 2 * g.ey <= g.ly && 2 * g.ez <= g.lz;
+           g.ey >= 1 && g.ez >= 1 && 2 * g.ex <= g.lx && 2 * g.ey <= g.ly && 2 * g.ez <= g.lz && g.N >= 2 &&
+           g.n_freq == g.N * g.N * (g.N / 2 + 1);
 }
 
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s) {
@@ -386,9 +446,9 @@ hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, h
     return fp32 ? fwd_impl<float>(g, Fhat, H, s) : fwd_impl<double>(g, Fhat, H, s);
 }
 
-hipError_t lattice_z(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s) {
+hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s) {
     if (!geom_ok(g)) return hipErrorInvalidValue;
-    return fp32 ? z_impl<float>(g, H, Khat, s) : z_impl<double>(g, H, Khat, s);
+    return fp32 ? yz_impl<float>(g, H, Khat, s) : yz_impl<double>(g, H, Khat, s);
 }
 
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s) {
@@ -399,7 +459,7 @@ hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, h
 hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, void *Uhat,
                         hipStream_t s) {
     hipError_t e = lattice_fwd(g, fp32, Fhat, H, s);
-    if (e == hipSuccess) e = lattice_z(g, fp32, H, Khat, s);
+    if (e == hipSuccess) e = lattice_yz(g, fp32, H, Khat, s);
     if (e == hipSuccess) e = lattice_inv(g, fp32, H, Uhat, s);
     return e;
 }

@@ -208,12 +208,13 @@ LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, in
     t->lz = lz;
     t->n_freq = oct->n_freq;
     const size_t per_w = (size_t)lx * ly * lz;
-    t->data.alloc(ctx, (fp32 ? 4 : 8) * per_w * t->n_freq, "lattice spectra");
+    const size_t n_stored = (size_t)lattice_stored_freqs(2 * nb);
+    t->data.alloc(ctx, (fp32 ? 4 : 8) * per_w * n_stored, "lattice spectra");
     const size_t ec = fp32 ? 8 : 16;
-    const size_t chunk = std::max<size_t>(1, std::min<size_t>(t->n_freq, (size_t(256) << 20) / (ec * per_w)));
+    const size_t chunk = std::max<size_t>(1, std::min<size_t>(n_stored, (size_t(256) << 20) / (ec * per_w)));
     DeviceBuffer scratch;
     scratch.alloc(ctx, chunk * per_w * ec, "lattice spectra scratch");
-    LatSpecGeom sg{2 * nb, lx, ly, lz, oct->XH + 1, oct->YH + 1, oct->ZH + 1, t->n_freq};
+    LatSpecGeom sg{2 * nb, lx, ly, lz, oct->XH + 1, oct->YH + 1, oct->ZH + 1};
     hip_check(lattice_spectra(sg, fp32, oct->data.ptr, t->data.ptr, scratch.ptr, scratch.bytes, ctx->stream),
               "lattice spectra");
     hip_check(hipStreamSynchronize(ctx->stream), "lattice spectra sync");
@@ -313,10 +314,11 @@ LatGeom lat_geom(const Conv &c, int nc) {
     g.ly = c.ly;
     g.lz = c.lz;
     g.nc = nc;
+    g.N = 2 * c.spec->nb;
     g.n_freq = c.spec->n_freq;
     g.n_slots = c.n_slots;
     g.fstride = (int64_t)c.spec->n_freq * c.n_slots;
-    g.hstride = (int64_t)c.spec->n_freq * c.lx * c.ly * c.ez;
+    g.hstride = (int64_t)c.spec->n_freq * c.lx * c.ey * c.ez;
     return g;
 }
 
@@ -571,7 +573,8 @@ static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
 // Models of a MAC launch in milliseconds, used when the tuning table has no
 // entry: block pairs at the measured arithmetic rate of the pair kernel,
 // the lattice FFT at half the HBM bandwidth over its streamed bytes (Fhat
-// read, H written, read and written, read, Uhat written, Khat read).
+// read, H written, read and written, read, Uhat written, the stored
+// spectra read).
 static double model_pairs_ms(const Conv &c, int nc) {
     double cmacs = 0;   // complex multiply-adds per frequency
     for (const auto &p : c.parts) cmacs += (double)p->n_rows * p->n_tiles * c.ty * c.tz * c.bx * c.bx;
@@ -580,11 +583,11 @@ static double model_pairs_ms(const Conv &c, int nc) {
 static double model_lattice_ms(int nb, bool fp32, int nc, const std::vector<Blk> &src, const std::vector<Blk> &tgt) {
     int lo[3], ext[3];
     box_extent(src, tgt, lo, ext);
-    const double nf = 4.0 * nb * nb * (nb + 1);
+    const double nf = 4.0 * nb * nb * (nb + 1), ns = lattice_stored_freqs(2 * nb);
     const double ec = fp32 ? 8 : 16, er = fp32 ? 4 : 8;
     const double lx = lattice_len(ext[0]), ly = lattice_len(ext[1]), lz = lattice_len(ext[2]);
-    const double box = (double)ext[0] * ext[1] * ext[2], hcol = lx * ly * ext[2];
-    return 0.02 + nf * (ec * nc * (2 * box + 4 * hcol) + er * lx * ly * lz) / 4e9;
+    const double box = (double)ext[0] * ext[1] * ext[2], h = lx * ext[1] * ext[2];
+    return 0.02 + (nf * ec * nc * (2 * box + 4 * h) + ns * er * lx * ly * lz) / 4e9;
 }
 
 // Build a convolution with the MAC method of the context's tuning table for
@@ -940,15 +943,15 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     if (c.method == kMethodLattice) {
         const LatGeom g = lat_geom(c, nc);
         {
-            StageTimer t(plan->ctx, kStageLatXY, s);
-            hip_check(lattice_fwd(g, c.fp32, plan->Fhat.ptr, plan->ws_lat.ptr, s), "lattice x/y DFT");
+            StageTimer t(plan->ctx, kStageLatX, s);
+            hip_check(lattice_fwd(g, c.fp32, plan->Fhat.ptr, plan->ws_lat.ptr, s), "lattice x DFT");
         }
         {
-            StageTimer t(plan->ctx, kStageLatZ, s);
-            hip_check(lattice_z(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, s), "lattice z line");
+            StageTimer t(plan->ctx, kStageLatYZ, s);
+            hip_check(lattice_yz(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, s), "lattice y/z slabs");
         }
         StageTimer t(plan->ctx, kStageLatInv, s);
-        hip_check(lattice_inv(g, c.fp32, plan->ws_lat.ptr, plan->Uhat.ptr, s), "lattice inverse x/y DFT");
+        hip_check(lattice_inv(g, c.fp32, plan->ws_lat.ptr, plan->Uhat.ptr, s), "lattice inverse x DFT");
     } else if (c.parts.empty()) {   // no source or no target: the convolution is zero
         hip_check(zero_fill(plan->Uhat.ptr, plan->Uhat.bytes, s), "clear Uhat");
     }

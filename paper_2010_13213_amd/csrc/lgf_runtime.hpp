@@ -74,8 +74,9 @@ struct JobRing {
     int next = 0;
 };
 
-// Real lattice spectra Khat[omega][kz][ky][kx] for lattice DFT lengths
-// (lx, ly, lz) (lgf_lattice.hip), shared by every plan of the context.
+// Real lattice spectra Khat[omega_r][kx][kz][ky] of the stored frequencies
+// for lattice DFT lengths (lx, ly, lz) (lgf_lattice.hip), shared by every
+// plan of the context.
 struct LatSpec {
     int nb = 0;
     bool fp32 = false;
@@ -223,10 +224,10 @@ struct lgf_plan {
 
 namespace lgf {
 // Timed stages: block FFT forward, block-pair MAC, block FFT inverse, other,
-// lattice x/y DFTs, lattice z line (DFT, product, inverse), lattice inverse
-// x/y DFTs.
+// lattice x DFTs, lattice y/z slabs (DFTs, product, inverse DFTs), lattice
+// inverse x DFTs.
 constexpr int kStages = 7;
-enum { kStageFwd = 0, kStagePairs = 1, kStageInv = 2, kStageOther = 3, kStageLatXY = 4, kStageLatZ = 5,
+enum { kStageFwd = 0, kStagePairs = 1, kStageInv = 2, kStageOther = 3, kStageLatX = 4, kStageLatYZ = 5,
        kStageLatInv = 6 };
 // Records an event before/after a stage launch when timing is on.
 struct StageTimer {

@@ -436,15 +436,15 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
         if (k.c->method == kMethodLattice) {
             const LatGeom g = lat_geom(*k.c, 1);
             {
-                StageTimer t(ctx, kStageLatXY, s);
-                hip_check(lattice_fwd(g, k.c->fp32, k.p->Fhat.ptr, k.p->ws_lat.ptr, s), "lattice x/y DFT");
+                StageTimer t(ctx, kStageLatX, s);
+                hip_check(lattice_fwd(g, k.c->fp32, k.p->Fhat.ptr, k.p->ws_lat.ptr, s), "lattice x DFT");
             }
             {
-                StageTimer t(ctx, kStageLatZ, s);
-                hip_check(lattice_z(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, s), "lattice z line");
+                StageTimer t(ctx, kStageLatYZ, s);
+                hip_check(lattice_yz(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, s), "lattice y/z slabs");
             }
             StageTimer t(ctx, kStageLatInv, s);
-            hip_check(lattice_inv(g, k.c->fp32, k.p->ws_lat.ptr, k.p->Uhat.ptr, s), "lattice inverse x/y DFT");
+            hip_check(lattice_inv(g, k.c->fp32, k.p->ws_lat.ptr, k.p->Uhat.ptr, s), "lattice inverse x DFT");
         } else if (k.c->parts.empty()) {
             hip_check(zero_fill(k.p->Uhat.ptr, k.p->Uhat.bytes, s), "clear Uhat");
         }

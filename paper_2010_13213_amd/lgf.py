@@ -173,7 +173,7 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("fwd_fft", "smac", "inv_fft", "other", "lat_xy", "lat_z", "lat_inv")
+    STAGES = ("fwd_fft", "smac", "inv_fft", "other", "lat_x", "lat_yz", "lat_xinv")
 
     MAC_METHODS = {"auto": 0, "pairs": 1, "lattice": 2}
 
