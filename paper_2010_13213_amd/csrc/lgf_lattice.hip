@@ -31,7 +31,9 @@
 // Three kernels, each streaming its data once from HBM:
 //   lat_x_fwd  x lines of Fhat -> H (a lane pair per line);
 //   lat_yz     one (omega, kx) slab per 2 Ly lanes, in LDS: y DFT, z DFT,
-//              product with Khat, inverse z and y DFTs, in place in H;
+//              product with Khat, inverse z and y DFTs, in place in H (the
+//              two halves of a line on lanes of different waves, meeting
+//              through LDS);
 //   lat_x_inv  inverse x lines of H, cropped, -> Uhat.
 // Inputs beyond E are zero (E <= L/2) and outputs beyond E are dropped, so
 // every line is split over a lane pair by the radix-2 identities
@@ -126,17 +128,25 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
 }
 
 // One (c, omega, kx) slab of H per 2 Ly lanes: y DFT, z DFT, product with
-// the spectra, inverse z and y DFTs, in place.
+// the spectra, inverse z and y DFTs, in place.  The two halves of every
+// line are taken by lanes of different waves (waves 0-1 the even half,
+// waves 2-3 the odd half), so the half a lane computes is uniform over its
+// wave: the odd-half twiddles are a branch, not a select, and the halves
+// meet through LDS.
 template <typename R, int LY, int LZ>
 __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat) {
-    constexpr int SL = kLatThreads / (2 * LY);          // slabs per workgroup
+    constexpr int HL = kLatThreads / 2;                 // lanes per half
+    constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
     constexpr int MY = LY / 2, MZ = LZ / 2;
     // lines padded by one element: unpadded, the lines a wave reads at once
     // start 256 B apart and fall into one LDS bank
     constexpr int PY = MY + 1, QZ = MZ + 1;
+    constexpr int YLINES = SL * MZ;                     // y lines (s, z), z < MZ
+    constexpr int YROUNDS = (YLINES + HL - 1) / HL;
     __shared__ cplx<R> P[SL * MZ * PY];   // slab [s][z][y]
     __shared__ cplx<R> Q[SL * LY * QZ];   // after the y DFT [s][ky][z]
     const int t = threadIdx.x;
+    const int half = t / HL, lane = t % HL;            // half: uniform per wave
     const int ey = g.ey, ez = g.ez, slab = ey * ez;
     const int64_t per_c = (int64_t)g.n_freq * g.lx;     // slabs per component
     const int64_t n_slabs = (int64_t)g.nc * per_c;
@@ -149,24 +159,31 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         P[(sl * MZ + q / ey) * PY + q % ey] = H[(si / per_c) * g.hstride + (si % per_c) * slab + q];
     }
     __syncthreads();
-    // 2. y lines (s, z), z < ez: Ey inputs -> Ly outputs
-    for (int e = t; e < SL * MZ * 2; e += kLatThreads) {
-        const int odd = e & 1, line = e >> 1, sl = line / MZ, z = line % MZ;
+    // 2. y lines (s, z), z < ez: Ey inputs -> this half's Ly/2 outputs
+    for (int line = lane; line < YLINES; line += HL) {
+        const int sl = line / MZ, z = line % MZ;
         if (z >= ez || s0 + sl >= n_slabs) continue;
         cplx<R> a[MY];
 #pragma unroll
         for (int n = 0; n < MY; ++n) a[n] = n < ey ? P[(sl * MZ + z) * PY + n] : czero<R>();
-        pair_fwd<R, LY>(a, odd);
+        if (half) {
 #pragma unroll
-        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + odd) * QZ + z] = a[m];
+            for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
+        }
+        fft_reg<R, MY, false>(a);
+#pragma unroll
+        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + half) * QZ + z] = a[m];
     }
     __syncthreads();
-    // 3. z lines (s, ky): exactly one lane pair per line (SL * LY * 2 lanes)
+    // 3. z lines (s, ky): X[2m + half] of the line, product with the
+    // spectra, inverse half DFT; then the halves combine through the line
+    const int zsl = lane / LY, ky = lane % LY;
+    const int64_t zsi = s0 + zsl;
+    const bool zlive = zsi < n_slabs;
+    cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
+    cplx<R> a[MZ];
     {
-        const int odd = t & 1, line = t >> 1, sl = line / LY, ky = line % LY;
-        const int64_t si = s0 + sl;
-        const bool live = si < n_slabs;
-        const int64_t wk = live ? si % per_c : 0;
+        const int64_t wk = zlive ? zsi % per_c : 0;
         const int w = (int)(wk / g.lx), kx = (int)(wk % g.lx);
         // stored frequency and reflections of omega = (kz N + ky) Hh + kx
         const int N = g.N, Hh = N / 2 + 1;
@@ -175,44 +192,71 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         const int wr = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
         const int kyk = ry ? (LY - ky) % LY : ky;
         const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;   // [kz][ky] plane of the slab
-        cplx<R> *qline = Q + (sl * LY + ky) * QZ;
-        cplx<R> a[MZ];
 #pragma unroll
         for (int n = 0; n < MZ; ++n) a[n] = n < ez ? qline[n] : czero<R>();
-        pair_fwd<R, LZ>(a, odd);
+        if (half) {
+#pragma unroll
+            for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
+        }
+        fft_reg<R, MZ, false>(a);
 #pragma unroll
         for (int m = 0; m < MZ; ++m) {
-            const int kz = 2 * m + odd;
-            const R k = live ? kc[(rz ? (LZ - kz) % LZ : kz) * LY] : (R)0;
+            const int kz = 2 * m + half;
+            const R k = zlive ? kc[(rz ? (LZ - kz) % LZ : kz) * LY] : (R)0;
             a[m] = cmake<R>(a[m].x * k, a[m].y * k);
         }
-        cplx<R> out[LZ / 4];
-        pair_inv<R, LZ>(a, odd, out);
+        fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
+    }
+    __syncthreads();   // every lane has read its line
+    // y[n] = E[n] + w^-n O[n]: the even half keeps n < MZ/2, the odd half the rest
+    if (half) {
 #pragma unroll
-        for (int j = 0; j < LZ / 4; ++j) {
-            const int n = odd ? MZ / 2 + j : j;
-            if (n < ez) qline[n] = out[j];
-        }
+        for (int j = 0; j < (MZ + 1) / 2; ++j) qline[j] = a[j];                      // O[j] for the even half
+    } else {
+#pragma unroll
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = a[j];                           // E[j] for the odd half
     }
     __syncthreads();
-    // 4. inverse y lines (s, z): Ly inputs -> Ey outputs; every lane takes
-    // part in each round (the exchange), idle ones with zeros
-    for (int base = 0; base < SL * MZ * 2; base += kLatThreads) {
-        const int e = base + t;
-        const int odd = e & 1, line = e >> 1, sl = line / MZ, z = line % MZ;
-        const bool on = e < SL * MZ * 2 && z < ez && s0 + sl < n_slabs;
-        cplx<R> a[MY];
+    if (half) {
 #pragma unroll
-        for (int m = 0; m < MY; ++m) a[m] = on ? Q[(sl * LY + 2 * m + odd) * QZ + z] : czero<R>();
-        cplx<R> out[LY / 4];
-        pair_inv<R, LY>(a, odd, out);
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
+    } else {
 #pragma unroll
-        for (int j = 0; j < LY / 4; ++j) {
-            const int n = odd ? MY / 2 + j : j;
-            if (on && n < ey) P[(sl * MZ + z) * PY + n] = out[j];
-        }
+        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
     }
     __syncthreads();
+    // 4. inverse y lines (s, z), z < ez: this half's Ly/2 inputs -> Ey
+    // outputs, combined through the line's slab row in P
+    for (int r = 0; r < YROUNDS; ++r) {
+        const int line = lane + r * HL;
+        const int sl = line / MZ, z = line % MZ;
+        const bool on = line < YLINES && z < ez && s0 + sl < n_slabs;
+        cplx<R> *prow = P + (sl * MZ + z) * PY;
+        cplx<R> b[MY];
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < MY; ++m) b[m] = Q[(sl * LY + 2 * m + half) * QZ + z];
+            fft_reg<R, MY, true>(b);
+            if (half) {
+#pragma unroll
+                for (int j = 0; j < (MY + 1) / 2; ++j) prow[j] = b[j];
+            } else {
+#pragma unroll
+                for (int j = MY / 2; j < MY; ++j) prow[j] = b[j];
+            }
+        }
+        __syncthreads();
+        if (on) {
+            if (half) {
+#pragma unroll
+                for (int j = MY / 2; j < MY; ++j) prow[j] = cadd(prow[j], cmul(b[j], twiddle<R, LY, true>(j)));
+            } else {
+#pragma unroll
+                for (int j = 0; j < MY / 2; ++j) prow[j] = cadd(b[j], cmul(prow[j], twiddle<R, LY, true>(j)));
+            }
+        }
+        __syncthreads();
+    }
     // 5. store the slabs back
     for (int e = t; e < SL * slab; e += kLatThreads) {
         const int sl = e / slab, q = e % slab;
