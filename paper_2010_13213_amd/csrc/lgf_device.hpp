@@ -83,10 +83,12 @@ template <typename R, int N, bool INV> __device__ __forceinline__ void fft_reg(c
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const int j = bitrev<N>::of(i);
-        if (j > i) {
-            cplx<R> t = a[i];
-            a[i] = a[j];
-            a[j] = t;
+        if (j > i) {   // per component: a struct copy can be lowered through private memory
+            const R tx = a[i].x, ty = a[i].y;
+            a[i].x = a[j].x;
+            a[i].y = a[j].y;
+            a[j].x = tx;
+            a[j].y = ty;
         }
     }
 #pragma unroll
