@@ -132,10 +132,12 @@ int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (
 // lattice_yz (y and z DFTs, product, inverse z and y DFTs in H),
 // lattice_inv (inverse x DFTs into Uhat), or all three by lattice_conv.
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s);
-hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s);
+// worder: the n_freq block frequencies in the order lattice_yz takes them
+// (any permutation; reflection partners adjacent lets them share Khat in L2).
+hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, const int *worder, hipStream_t s);
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s);
-hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, void *Uhat,
-                        hipStream_t s);
+hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, const int *worder,
+                        void *Uhat, hipStream_t s);
 // Khat for lattice lengths (lx, ly, lz) from the octant table (same
 // precision), scaled by 1 / (lx ly lz); scratch holds the complex
 // intermediate of a chunk of frequencies.

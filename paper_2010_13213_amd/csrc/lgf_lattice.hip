@@ -42,6 +42,7 @@
 //   y[n]  = IDFT_M(X[2m])[n] + w^-n IDFT_M(X[2m+1])[n],  n < M      (inverse)
 // the inverse with one exchange of half a line between the two lanes.
 #include <algorithm>
+#include <cstdint>
 #include <type_traits>
 
 #include "lgf_device.hpp"
@@ -127,89 +128,65 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
     for (int m = 0; m < M; ++m) out[(2 * m + odd) * per_w] = a[m];
 }
 
-// One (c, omega, kx) slab of H per 2 Ly lanes: y DFT, z DFT, product with
-// the spectra, inverse z and y DFTs, in place.  The two halves of every
-// line are taken by lanes of different waves (waves 0-1 the even half,
-// waves 2-3 the odd half), so the half a lane computes is uniform over its
-// wave: the odd-half twiddles are a branch, not a select, and the halves
-// meet through LDS.
-template <typename R, int LY, int LZ>
-__global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat) {
-    constexpr int HL = kLatThreads / 2;                 // lanes per half
-    constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
+// Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
+// the zero-padded slabs in P.  Every index that depends on the half is a
+// constant here; both halves pass the same barriers in the same order.
+template <typename R, int LY, int LZ, int HF>
+__device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
+                                        const int (*sinfo)[2], int lane, int ez) {
+    constexpr int HL = kLatThreads / 2;
+    constexpr int SL = HL / LY;
     constexpr int MY = LY / 2, MZ = LZ / 2;
-    // lines padded by one element: unpadded, the lines a wave reads at once
-    // start 256 B apart and fall into one LDS bank
     constexpr int PY = MY + 1, QZ = MZ + 1;
-    constexpr int YLINES = SL * MZ;                     // y lines (s, z), z < MZ
+    constexpr int YLINES = SL * MZ;
     constexpr int YROUNDS = (YLINES + HL - 1) / HL;
-    __shared__ cplx<R> P[SL * MZ * PY];   // slab [s][z][y]
-    __shared__ cplx<R> Q[SL * LY * QZ];   // after the y DFT [s][ky][z]
-    const int t = threadIdx.x;
-    const int half = t / HL, lane = t % HL;            // half: uniform per wave
-    const int ey = g.ey, ez = g.ez, slab = ey * ez;
-    const int64_t per_c = (int64_t)g.n_freq * g.lx;     // slabs per component
-    const int64_t n_slabs = (int64_t)g.nc * per_c;
-    const int64_t s0 = (int64_t)blockIdx.x * SL;
-    // 1. load the slabs ([c][omega][kx] slabs are consecutive within a component)
-    for (int e = t; e < SL * slab; e += kLatThreads) {
-        const int sl = e / slab, q = e % slab;
-        const int64_t si = s0 + sl;
-        if (si >= n_slabs) break;
-        P[(sl * MZ + q / ey) * PY + q % ey] = H[(si / per_c) * g.hstride + (si % per_c) * slab + q];
-    }
-    __syncthreads();
-    // 2. y lines (s, z), z < ez: Ey inputs -> this half's Ly/2 outputs
+    // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
     for (int line = lane; line < YLINES; line += HL) {
         const int sl = line / MZ, z = line % MZ;
-        if (z >= ez || s0 + sl >= n_slabs) continue;
+        const cplx<R> *prow = P + (sl * MZ + z) * PY;
         cplx<R> a[MY];
 #pragma unroll
-        for (int n = 0; n < MY; ++n) a[n] = n < ey ? P[(sl * MZ + z) * PY + n] : czero<R>();
-        if (half) {
+        for (int n = 0; n < MY; ++n) a[n] = prow[n];
+        if (HF) {
 #pragma unroll
             for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
         }
         fft_reg<R, MY, false>(a);
 #pragma unroll
-        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + half) * QZ + z] = a[m];
+        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + HF) * QZ + z] = a[m];
     }
     __syncthreads();
-    // 3. z lines (s, ky): X[2m + half] of the line, product with the
-    // spectra, inverse half DFT; then the halves combine through the line
+    // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
+    // inverse half DFT; then the halves combine through the line
     const int zsl = lane / LY, ky = lane % LY;
-    const int64_t zsi = s0 + zsl;
-    const bool zlive = zsi < n_slabs;
     cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
     cplx<R> a[MZ];
     {
-        const int64_t wk = zlive ? zsi % per_c : 0;
-        const int w = (int)(wk / g.lx), kx = (int)(wk % g.lx);
-        // stored frequency and reflections of omega = (kz N + ky) Hh + kx
-        const int N = g.N, Hh = N / 2 + 1;
-        const int fx = w % Hh, fyv = (w / Hh) % N, fzv = w / (Hh * N);
-        const bool ry = fyv > N / 2, rz = fzv > N / 2;
-        const int wr = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
+        const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
+        const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
         const int kyk = ry ? (LY - ky) % LY : ky;
-        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;   // [kz][ky] plane of the slab
+        // [kz][ky] plane of the slab; a reflected kz runs backwards from kz = LZ
+        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
+        const int ks = rz ? -LY : LY;
+        const R *kp = (rz ? kc + LZ * LY : kc) + HF * ks;   // kz = HF
 #pragma unroll
-        for (int n = 0; n < MZ; ++n) a[n] = n < ez ? qline[n] : czero<R>();
-        if (half) {
+        for (int n = 0; n < MZ; ++n) a[n] = qline[n];
+        if (HF) {
 #pragma unroll
             for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
         }
         fft_reg<R, MZ, false>(a);
 #pragma unroll
         for (int m = 0; m < MZ; ++m) {
-            const int kz = 2 * m + half;
-            const R k = zlive ? kc[(rz ? (LZ - kz) % LZ : kz) * LY] : (R)0;
+            const R k = (HF == 0 && m == 0) ? kc[0] : *kp;
+            kp += 2 * ks;
             a[m] = cmake<R>(a[m].x * k, a[m].y * k);
         }
         fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
     }
     __syncthreads();   // every lane has read its line
     // y[n] = E[n] + w^-n O[n]: the even half keeps n < MZ/2, the odd half the rest
-    if (half) {
+    if (HF) {
 #pragma unroll
         for (int j = 0; j < (MZ + 1) / 2; ++j) qline[j] = a[j];                      // O[j] for the even half
     } else {
@@ -217,7 +194,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         for (int j = MZ / 2; j < MZ; ++j) qline[j] = a[j];                           // E[j] for the odd half
     }
     __syncthreads();
-    if (half) {
+    if (HF) {
 #pragma unroll
         for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
     } else {
@@ -225,19 +202,19 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
     }
     __syncthreads();
-    // 4. inverse y lines (s, z), z < ez: this half's Ly/2 inputs -> Ey
+    // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
     // outputs, combined through the line's slab row in P
     for (int r = 0; r < YROUNDS; ++r) {
         const int line = lane + r * HL;
         const int sl = line / MZ, z = line % MZ;
-        const bool on = line < YLINES && z < ez && s0 + sl < n_slabs;
+        const bool on = line < YLINES && z < ez;
         cplx<R> *prow = P + (sl * MZ + z) * PY;
         cplx<R> b[MY];
         if (on) {
 #pragma unroll
-            for (int m = 0; m < MY; ++m) b[m] = Q[(sl * LY + 2 * m + half) * QZ + z];
+            for (int m = 0; m < MY; ++m) b[m] = Q[(sl * LY + 2 * m + HF) * QZ + z];
             fft_reg<R, MY, true>(b);
-            if (half) {
+            if (HF) {
 #pragma unroll
                 for (int j = 0; j < (MY + 1) / 2; ++j) prow[j] = b[j];
             } else {
@@ -247,7 +224,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         }
         __syncthreads();
         if (on) {
-            if (half) {
+            if (HF) {
 #pragma unroll
                 for (int j = MY / 2; j < MY; ++j) prow[j] = cadd(prow[j], cmul(b[j], twiddle<R, LY, true>(j)));
             } else {
@@ -257,12 +234,73 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         }
         __syncthreads();
     }
+}
+
+// One (c, omega, kx) slab of H per 2 Ly lanes: y DFT, z DFT, product with
+// the spectra, inverse z and y DFTs, in place.  The two halves of every
+// line are taken by lanes of different waves (waves 0-1 the even half,
+// waves 2-3 the odd half); each half runs its own copy of the line code
+// (yz_half), so no index or twiddle depends on the half at run time, and
+// the halves meet through LDS.
+// Frequencies are taken in the order worder[] (a permutation of the
+// n_freq block frequencies that puts the y/z reflections of a frequency
+// next to each other), and workgroups are renumbered so that consecutive
+// ones run on one XCD: the reflections share one stored Khat plane, which
+// is then read from HBM once and from that XCD's L2 for the others.
+template <typename R, int LY, int LZ>
+__global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
+                                                      const int *__restrict__ worder) {
+    constexpr int HL = kLatThreads / 2;                 // lanes per half
+    constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
+    constexpr int MY = LY / 2, MZ = LZ / 2;
+    // lines padded by one element: unpadded, the lines a wave reads at once
+    // start 256 B apart and fall into one LDS bank
+    constexpr int PY = MY + 1, QZ = MZ + 1;
+    constexpr int CELLS = SL * MZ * MY;                 // slab cells zero-padded to MZ x MY
+    __shared__ cplx<R> P[SL * MZ * PY];   // slab [s][z][y]
+    __shared__ cplx<R> Q[SL * LY * QZ];   // after the y DFT [s][ky][z]
+    // per slab: H offset (-1 past the last slab), stored frequency, kx and reflections
+    __shared__ int64_t hbase[SL];
+    __shared__ int sinfo[SL][2];
+    const int t = threadIdx.x;
+    const int half = __builtin_amdgcn_readfirstlane(t / HL), lane = t % HL;   // half: uniform per wave
+    const int ey = g.ey, ez = g.ez;
+    const int slab = ey * ez;
+    // slab counts fit in 32 bits (the launch checks nc * n_freq * lx)
+    const int per_c = g.n_freq * g.lx;                  // slabs per component
+    const int n_slabs = g.nc * per_c;
+    const int s0 = (int)xcd_order(blockIdx.x, gridDim.x) * SL;
+    if (t < SL) {
+        const int si = s0 + t;
+        const bool live = si < n_slabs;
+        const int wk = live ? si % per_c : 0;
+        const int w = worder[wk / g.lx], kx = wk % g.lx;
+        // omega = (kz N + ky) Hh + kx -> stored frequency (ky, kz in [0, N/2]) and reflections
+        const int N = g.N, Hh = N / 2 + 1;
+        const int fx = w % Hh, fyv = (w / Hh) % N, fzv = w / (Hh * N);
+        const int ry = fyv > N / 2, rz = fzv > N / 2;
+        hbase[t] = live ? (int64_t)(si / per_c) * g.hstride + ((int64_t)w * g.lx + kx) * slab : -1;
+        sinfo[t][0] = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
+        sinfo[t][1] = kx | ry << 8 | rz << 9;
+    }
+    __syncthreads();
+    // 1. load the slabs, zero-padded to MZ x MY (slabs past the end: zero)
+    for (int e = t; e < CELLS; e += kLatThreads) {
+        const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
+        const int64_t hb = hbase[sl];
+        cplx<R> v = czero<R>();
+        if (hb >= 0 && y < ey && z < ez) v = H[hb + z * ey + y];
+        P[(sl * MZ + z) * PY + y] = v;
+    }
+    __syncthreads();
+    // 2-4, each wave in its half's copy (the same barriers in both)
+    if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
+    else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
     // 5. store the slabs back
-    for (int e = t; e < SL * slab; e += kLatThreads) {
-        const int sl = e / slab, q = e % slab;
-        const int64_t si = s0 + sl;
-        if (si >= n_slabs) break;
-        H[(si / per_c) * g.hstride + (si % per_c) * slab + q] = P[(sl * MZ + q / ey) * PY + q % ey];
+    for (int e = t; e < CELLS; e += kLatThreads) {
+        const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
+        const int64_t hb = hbase[sl];
+        if (hb >= 0 && y < ey && z < ez) H[hb + z * ey + y] = P[(sl * MZ + z) * PY + y];
     }
 }
 
@@ -414,14 +452,16 @@ template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void 
     });
 }
 
-template <typename R> hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, hipStream_t s) {
+template <typename R>
+hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worder, hipStream_t s) {
     const int64_t slabs = (int64_t)g.nc * g.n_freq * g.lx;
+    if (slabs >= INT32_MAX) return hipErrorInvalidValue;   // the kernel counts slabs in 32 bits
     return with_len(g.ly, [&](auto ly) {
         return with_len(g.lz, [&](auto lz) {
             constexpr int LY = decltype(ly)::value, LZ = decltype(lz)::value;
             constexpr int SL = kLatThreads / (2 * LY);
             hipLaunchKernelGGL((lat_yz<R, LY, LZ>), dim3((unsigned)((slabs + SL - 1) / SL)), dim3(kLatThreads), 0,
-                               s, g, (cplx<R> *)H, (const R *)Khat);
+                               s, g, (cplx<R> *)H, (const R *)Khat, worder);
             return hipGetLastError();
         });
     });
@@ -490,9 +530,9 @@ hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, h
     return fp32 ? fwd_impl<float>(g, Fhat, H, s) : fwd_impl<double>(g, Fhat, H, s);
 }
 
-hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, hipStream_t s) {
-    if (!geom_ok(g)) return hipErrorInvalidValue;
-    return fp32 ? yz_impl<float>(g, H, Khat, s) : yz_impl<double>(g, H, Khat, s);
+hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, const int *worder, hipStream_t s) {
+    if (!geom_ok(g) || worder == nullptr) return hipErrorInvalidValue;
+    return fp32 ? yz_impl<float>(g, H, Khat, worder, s) : yz_impl<double>(g, H, Khat, worder, s);
 }
 
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s) {
@@ -500,10 +540,10 @@ hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, h
     return fp32 ? inv_impl<float>(g, H, Uhat, s) : inv_impl<double>(g, H, Uhat, s);
 }
 
-hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, void *Uhat,
-                        hipStream_t s) {
+hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, const int *worder,
+                        void *Uhat, hipStream_t s) {
     hipError_t e = lattice_fwd(g, fp32, Fhat, H, s);
-    if (e == hipSuccess) e = lattice_yz(g, fp32, H, Khat, s);
+    if (e == hipSuccess) e = lattice_yz(g, fp32, H, Khat, worder, s);
     if (e == hipSuccess) e = lattice_inv(g, fp32, H, Uhat, s);
     return e;
 }

@@ -207,6 +207,7 @@ LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, in
     t->ly = ly;
     t->lz = lz;
     t->n_freq = oct->n_freq;
+    t->order = (const int *)oct->perm.ptr;
     const size_t per_w = (size_t)lx * ly * lz;
     const size_t n_stored = (size_t)lattice_stored_freqs(2 * nb);
     t->data.alloc(ctx, (fp32 ? 4 : 8) * per_w * n_stored, "lattice spectra");
@@ -537,7 +538,7 @@ static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
     hip_check(zero_fill(F.ptr, bytes, ctx->stream), "tuning clear");
     auto run = [&] {
         if (c.method == kMethodLattice) {
-            hip_check(lattice_conv(lat_geom(c, nc), c.fp32, F.ptr, Hb.ptr, c.lspec->data.ptr, U.ptr, ctx->stream),
+            hip_check(lattice_conv(lat_geom(c, nc), c.fp32, F.ptr, Hb.ptr, c.lspec->data.ptr, c.lspec->order, U.ptr, ctx->stream),
                       "tuning lattice MAC");
             return;
         }
@@ -948,7 +949,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
         }
         {
             StageTimer t(plan->ctx, kStageLatYZ, s);
-            hip_check(lattice_yz(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, s), "lattice y/z slabs");
+            hip_check(lattice_yz(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, c.lspec->order, s), "lattice y/z slabs");
         }
         StageTimer t(plan->ctx, kStageLatInv, s);
         hip_check(lattice_inv(g, c.fp32, plan->ws_lat.ptr, plan->Uhat.ptr, s), "lattice inverse x DFT");

@@ -83,6 +83,7 @@ struct LatSpec {
     int lx = 0, ly = 0, lz = 0;
     int n_freq = 0;
     DeviceBuffer data;
+    const int *order = nullptr;   // reflection-grouped frequency order (the octant table's perm)
 };
 
 // Tuning-table entry: the chosen MAC method ("pairs TYxTZ": the block-pair

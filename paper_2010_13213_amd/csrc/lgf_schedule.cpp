@@ -441,7 +441,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
             }
             {
                 StageTimer t(ctx, kStageLatYZ, s);
-                hip_check(lattice_yz(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, s), "lattice y/z slabs");
+                hip_check(lattice_yz(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, k.c->lspec->order, s), "lattice y/z slabs");
             }
             StageTimer t(ctx, kStageLatInv, s);
             hip_check(lattice_inv(g, k.c->fp32, k.p->ws_lat.ptr, k.p->Uhat.ptr, s), "lattice inverse x DFT");
