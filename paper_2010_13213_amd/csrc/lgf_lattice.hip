@@ -140,6 +140,24 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     constexpr int PY = MY + 1, QZ = MZ + 1;
     constexpr int YLINES = SL * MZ;
     constexpr int YROUNDS = (YLINES + HL - 1) / HL;
+    const int zsl = lane / LY, ky = lane % LY;
+    // the spectra this lane's z line is multiplied by in step 3 (kz = 2m + HF),
+    // loaded first so that steps 2 and 3 hide the latency
+    R kv[MZ];
+    {
+        const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
+        const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
+        const int kyk = ry ? (LY - ky) % LY : ky;
+        // [kz][ky] plane of the slab; a reflected kz runs backwards from kz = LZ
+        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
+        const int ks = rz ? -LY : LY;
+        const R *kp = (rz ? kc + LZ * LY : kc) + HF * ks;   // kz = HF
+#pragma unroll
+        for (int m = 0; m < MZ; ++m) {
+            kv[m] = (HF == 0 && m == 0) ? kc[0] : *kp;
+            kp += 2 * ks;
+        }
+    }
     // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
     for (int line = lane; line < YLINES; line += HL) {
         const int sl = line / MZ, z = line % MZ;
@@ -158,32 +176,18 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     __syncthreads();
     // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
     // inverse half DFT; then the halves combine through the line
-    const int zsl = lane / LY, ky = lane % LY;
     cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
     cplx<R> a[MZ];
-    {
-        const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
-        const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
-        const int kyk = ry ? (LY - ky) % LY : ky;
-        // [kz][ky] plane of the slab; a reflected kz runs backwards from kz = LZ
-        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
-        const int ks = rz ? -LY : LY;
-        const R *kp = (rz ? kc + LZ * LY : kc) + HF * ks;   // kz = HF
 #pragma unroll
-        for (int n = 0; n < MZ; ++n) a[n] = qline[n];
-        if (HF) {
+    for (int n = 0; n < MZ; ++n) a[n] = qline[n];
+    if (HF) {
 #pragma unroll
-            for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
-        }
-        fft_reg<R, MZ, false>(a);
-#pragma unroll
-        for (int m = 0; m < MZ; ++m) {
-            const R k = (HF == 0 && m == 0) ? kc[0] : *kp;
-            kp += 2 * ks;
-            a[m] = cmake<R>(a[m].x * k, a[m].y * k);
-        }
-        fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
+        for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
     }
+    fft_reg<R, MZ, false>(a);
+#pragma unroll
+    for (int m = 0; m < MZ; ++m) a[m] = cmake<R>(a[m].x * kv[m], a[m].y * kv[m]);
+    fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
     __syncthreads();   // every lane has read its line
     // y[n] = E[n] + w^-n O[n]: the even half keeps n < MZ/2, the odd half the rest
     if (HF) {
@@ -284,22 +288,36 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         sinfo[t][1] = kx | ry << 8 | rz << 9;
     }
     __syncthreads();
-    // 1. load the slabs, zero-padded to MZ x MY (slabs past the end: zero)
-    for (int e = t; e < CELLS; e += kLatThreads) {
+    // 1. load the slabs, zero-padded to MZ x MY (slabs past the end: zero);
+    // all loads are issued before the first is waited on (cells outside the
+    // data read element 0 and are replaced by zero)
+    constexpr int NI = (CELLS + kLatThreads - 1) / kLatThreads;
+    cplx<R> v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
         const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
-        const int64_t hb = hbase[sl];
-        cplx<R> v = czero<R>();
-        if (hb >= 0 && y < ey && z < ez) v = H[hb + z * ey + y];
-        P[(sl * MZ + z) * PY + y] = v;
+        const int64_t hb = e < CELLS ? hbase[sl] : -1;
+        const bool ok = hb >= 0 && y < ey && z < ez;
+        const cplx<R> x = H[ok ? hb + z * ey + y : 0];
+        v[i] = csel(ok, x, czero<R>());
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
+        const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
+        if (e < CELLS) P[(sl * MZ + z) * PY + y] = v[i];
     }
     __syncthreads();
     // 2-4, each wave in its half's copy (the same barriers in both)
     if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
     else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
     // 5. store the slabs back
-    for (int e = t; e < CELLS; e += kLatThreads) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
         const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
-        const int64_t hb = hbase[sl];
+        const int64_t hb = e < CELLS ? hbase[sl] : -1;
         if (hb >= 0 && y < ey && z < ez) H[hb + z * ey + y] = P[(sl * MZ + z) * PY + y];
     }
 }
