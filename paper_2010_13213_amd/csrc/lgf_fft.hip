@@ -52,16 +52,20 @@ template <typename R, int N, int M> __device__ __forceinline__ void odd_twiddle(
     for (int n = 1; n < M; ++n) a[n] = cmul(a[n], twiddle<R, N, false>(n));
 }
 
+// Spectrum value omega of slot sl at Fhat[omega * ws + sl * ss]:
+// frequency-major (ws = n_slots, ss = 1) or block-major (ws = 1, ss = n_freq).
+template <int NB> constexpr int64_t fft_freqs = 4 * NB * NB * (NB + 1);   // (2nb)^2 (nb + 1)
+
 template <int NB, typename R>
 __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
-                                         const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t n_slots,
-                                         double scale, int b) {
+                                         const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t ws,
+                                         int64_t ss, double scale, int b) {
     using S = FftShape<NB, R>;
     constexpr int N = S::N, M = S::M, H = S::H, HH = S::HH, HL = S::HL;
     __shared__ cplx<R> A[S::A_ELEMS];
     __shared__ cplx<R> B[S::B_ELEMS];
     const double *in = src + blk_off[b];
-    const int64_t sl = slot[b];
+    cplx<R> *Fb = Fhat + slot[b] * ss;
     const int t = threadIdx.x;
     const int half = t / HL, lane = t % HL;
 
@@ -107,7 +111,7 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int64_t omega = ((int64_t)(2 * m + half) * N + ky) * H + kx;
-                Fhat[omega * n_slots + sl] = a[m];
+                Fb[omega * ws] = a[m];
             }
         }
         __syncthreads();
@@ -117,8 +121,9 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
 template <int NB, typename R>
 __global__ void __launch_bounds__(fft_threads<NB>) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                                   const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
-                                                  int64_t n_slots, double scale) {
-    fwd_body<NB, R>(src, blk_off, slot, Fhat, n_slots, scale, (int)xcd_order(blockIdx.x, gridDim.x));
+                                                  int64_t n_slots, int block_major, double scale) {
+    fwd_body<NB, R>(src, blk_off, slot, Fhat, block_major ? 1 : n_slots, block_major ? fft_freqs<NB> : 1, scale,
+                    (int)xcd_order(blockIdx.x, gridDim.x));
 }
 
 __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
@@ -135,7 +140,8 @@ template <int NB, typename R>
 __global__ void __launch_bounds__(fft_threads<NB>) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
     const int b = (int)xcd_order(blockIdx.x, gridDim.x);
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
-    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, b - j.blk_begin);
+    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.block_major ? 1 : j.n_slots,
+                    j.block_major ? fft_freqs<NB> : 1, j.scale, b - j.blk_begin);
 }
 
 // The inverse keeps one thread per whole line (256 threads): splitting its
@@ -144,14 +150,14 @@ __global__ void __launch_bounds__(fft_threads<NB>) fwd_batch_kernel(const FftJob
 constexpr int kInvThreads = 256;
 
 template <int NB, typename R>
-__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t ws, int64_t ss,
                                          const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
                                          double *__restrict__ dst, double scale, int accumulate, int b) {
     using S = FftShape<NB, R>;
     constexpr int N = S::N, H = S::H, HH = S::HH;
     __shared__ cplx<R> D[S::A_ELEMS];   // [z][y][kx] after the z and y passes
     __shared__ cplx<R> C[S::B_ELEMS];   // [z][ky][kxl]
-    const int64_t sl = slot[b];
+    const cplx<R> *Ub = Uhat + slot[b] * ss;
     const int t = threadIdx.x;
 
     for (int half = 0; half < 2; ++half) {
@@ -165,7 +171,7 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
 #pragma unroll
             for (int kz = 0; kz < N; ++kz) {
                 const int64_t omega = ((int64_t)kz * N + ky) * H + kx;
-                a[kz] = Uhat[omega * n_slots + sl];
+                a[kz] = Ub[omega * ws];
             }
             fft_reg<R, N, true>(a);
 #pragma unroll
@@ -206,17 +212,19 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(kInvThreads) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
-                                                  const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
-                                                  double *__restrict__ dst, double scale, int accumulate) {
-    inv_body<NB, R>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, (int)xcd_order(blockIdx.x, gridDim.x));
+                                                  int block_major, const int *__restrict__ slot,
+                                                  const int64_t *__restrict__ blk_off, double *__restrict__ dst,
+                                                  double scale, int accumulate) {
+    inv_body<NB, R>(Uhat, block_major ? 1 : n_slots, block_major ? fft_freqs<NB> : 1, slot, blk_off, dst, scale,
+                    accumulate, (int)xcd_order(blockIdx.x, gridDim.x));
 }
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(kInvThreads) inv_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
     const int b = (int)xcd_order(blockIdx.x, gridDim.x);
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
-    inv_body<NB, R>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
-                    b - j.blk_begin);
+    inv_body<NB, R>((const cplx<R> *)j.spec, j.block_major ? 1 : j.n_slots, j.block_major ? fft_freqs<NB> : 1, j.slot,
+                    j.blk_off, j.dst, j.scale, j.accumulate, b - j.blk_begin);
 }
 
 template <int NB, typename R>
@@ -231,32 +239,32 @@ hipError_t batch_launch(bool inverse, const FftJob *jobs, int n_jobs, int total_
 
 template <int NB, typename R>
 hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
-                      int64_t n_slots, double scale, hipStream_t s) {
+                      int64_t n_slots, bool block_major, double scale, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
-                       n_slots, scale);
+                       n_slots, (int)block_major, scale);
     return hipGetLastError();
 }
 
 template <int NB, typename R>
-hipError_t inv_launch(const void *Uhat, int64_t n_slots, const int *slot, const int64_t *blk_off, int n_blocks,
-                      double *dst, double scale, int accumulate, hipStream_t s) {
+hipError_t inv_launch(const void *Uhat, int64_t n_slots, bool block_major, const int *slot, const int64_t *blk_off,
+                      int n_blocks, double *dst, double scale, int accumulate, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((inv_kernel<NB, R>), dim3(n_blocks), dim3(kInvThreads), 0, s, (const cplx<R> *)Uhat, n_slots, slot,
-                       blk_off, dst, scale, accumulate);
+    hipLaunchKernelGGL((inv_kernel<NB, R>), dim3(n_blocks), dim3(kInvThreads), 0, s, (const cplx<R> *)Uhat, n_slots,
+                       (int)block_major, slot, blk_off, dst, scale, accumulate);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t *blk_off, const int *slot,
-                             int n_blocks, void *Fhat, int64_t n_slots, double scale, hipStream_t s) {
+                             int n_blocks, void *Fhat, int64_t n_slots, bool block_major, double scale, hipStream_t s) {
     if (nb == 16)
-        return fp32 ? fwd_launch<16, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s)
-                    : fwd_launch<16, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s);
+        return fp32 ? fwd_launch<16, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, block_major, scale, s)
+                    : fwd_launch<16, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, block_major, scale, s);
     if (nb == 8)
-        return fp32 ? fwd_launch<8, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s)
-                    : fwd_launch<8, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, scale, s);
+        return fp32 ? fwd_launch<8, float>(src, blk_off, slot, n_blocks, Fhat, n_slots, block_major, scale, s)
+                    : fwd_launch<8, double>(src, blk_off, slot, n_blocks, Fhat, n_slots, block_major, scale, s);
     return hipErrorInvalidValue;
 }
 
@@ -282,15 +290,17 @@ hipError_t block_fft_inverse_batch(int nb, bool fp32, const FftJob *jobs, int n_
     return hipErrorInvalidValue;
 }
 
-hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, const int *slot,
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, bool block_major, const int *slot,
                              const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
                              hipStream_t s) {
     if (nb == 16)
-        return fp32 ? inv_launch<16, float>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s)
-                    : inv_launch<16, double>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s);
+        return fp32 ? inv_launch<16, float>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate, s)
+                    : inv_launch<16, double>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate,
+                                             s);
     if (nb == 8)
-        return fp32 ? inv_launch<8, float>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s)
-                    : inv_launch<8, double>(Uhat, n_slots, slot, blk_off, n_blocks, dst, scale, accumulate, s);
+        return fp32 ? inv_launch<8, float>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate, s)
+                    : inv_launch<8, double>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate,
+                                            s);
     return hipErrorInvalidValue;
 }
 

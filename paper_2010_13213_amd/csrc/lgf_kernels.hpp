@@ -17,15 +17,18 @@ hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bo
                          void *scratch, size_t scratch_bytes, hipStream_t s);
 
 // ---- block FFTs (lgf_fft.hip) ----
+// Spectral workspaces hold spectrum value omega (of n_freq = (2nb)^2 (nb + 1))
+// of slot sl at omega * n_slots + sl (frequency-major: the block-pair MAC)
+// or at sl * n_freq + omega (block_major: the lattice MAC).
 // Forward: for each listed block i, read the nb^3 float64 values at
 // src + blk_off[i] (elements), multiply by `scale`, zero-pad to (2nb)^3,
-// r2c-transform and store spectrum value omega at Fhat[omega * n_slots + slot[i]].
+// r2c-transform and store the spectrum of slot[i] in Fhat.
 hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t *blk_off, const int *slot,
-                             int n_blocks, void *Fhat, int64_t n_slots, double scale, hipStream_t s);
-// Inverse: for each listed block i, gather Uhat[omega * n_slots + slot[i]],
+                             int n_blocks, void *Fhat, int64_t n_slots, bool block_major, double scale, hipStream_t s);
+// Inverse: for each listed block i, gather the spectrum of slot[i] from Uhat,
 // c2r-transform, keep the [0, nb)^3 corner, multiply by `scale` and write
 // (accumulate = 0) or add (accumulate = 1) into dst + blk_off[i].
-hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, const int *slot,
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, bool block_major, const int *slot,
                              const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
                              hipStream_t s);
 
@@ -37,6 +40,7 @@ struct FftJob {
     const int *slot;        // per block: slot in the spectral workspace
     void *spec;             // forward: Fhat; inverse: Uhat
     int64_t n_slots;
+    int block_major;        // spectral layout (see block_fft_forward)
     double scale;
     int accumulate;
     int blk_begin;
@@ -104,8 +108,9 @@ hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const 
 // ---- spectral MAC by an FFT over the block lattice (lgf_lattice.hip) ----
 // Box E = (ex, ey, ez) blocks, lattice DFT lengths (lx, ly, lz), each a
 // compiled length (4, 8, 16, 32) with 2 e <= l; N = 2 nb is the block FFT
-// edge (n_freq = N^2 (N/2 + 1)).  Fhat / Uhat: [c][omega][slot] (slot =
-// (z ey + y) ex + x), components fstride elements apart; H:
+// edge (n_freq = N^2 (N/2 + 1)).  Fhat / Uhat block-major: [c][slot][omega]
+// (slot = (z ey + y) ex + x, n_slots = ex ey ez), components fstride
+// (>= n_freq n_slots) elements apart; H:
 // [c][omega][kx][z][y] workspace, components hstride (>= n_freq lx ey ez)
 // elements apart; Khat: real [omega_r][kx][kz][ky] over the stored
 // frequencies (ky, kz in [0, N/2]).

@@ -24,12 +24,15 @@
 // block pairs.
 //
 // Layouts (complex R, per component region):
-//   Fhat, Uhat [omega][slot], slot = (z Ey + y) Ex + x over the box E;
+//   Fhat, Uhat [slot][omega] (block-major: the block FFTs stream whole
+//              spectra), slot = (z Ey + y) Ex + x over the box E;
 //   H          [omega][kx][z][y]: the box after the x DFT (kx < Lx);
 //   Khat       [omega_r][kx][kz][ky] (real R), omega_r over the stored
 //              frequencies.
 // Three kernels, each streaming its data once from HBM:
-//   lat_x_fwd  x lines of Fhat -> H (a lane pair per line);
+//   lat_x_fwd  x lines of Fhat -> H (a lane pair per line; a workgroup takes
+//              8 frequencies x 16 (y, z) rows, so each slot's 8 frequencies
+//              are one 128-byte line);
 //   lat_yz     one (omega, kx) slab per 2 Ly lanes, in LDS: y DFT, z DFT,
 //              product with Khat, inverse z and y DFTs, in place in H (the
 //              two halves of a line on lanes of different waves, meeting
@@ -94,38 +97,60 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
     }
 }
 
-// x lines of Fhat -> H.  128 lines per workgroup, a lane pair each; the
-// lines are staged through LDS so that the loads are coalesced.
+// Tile of the x kernels: kTW consecutive frequencies x kTQ consecutive (y, z)
+// rows q of one component = 128 lines, a lane pair each; row rl = wl kTQ + ql.
+constexpr int kTW = 8, kTQ = kLatThreads / (2 * kTW);
+
+struct XTile {
+    int c, w0, q0;
+};
+__device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
+    const int per_w = g.ey * g.ez;
+    const int wt = (g.n_freq + kTW - 1) / kTW, qt = (per_w + kTQ - 1) / kTQ;
+    return XTile{b / (wt * qt), (b % wt) * kTW, ((b / wt) % qt) * kTQ};
+}
+
+// x lines of Fhat -> H.  The tile's lines are staged through LDS: the loads
+// read each slot's kTW frequencies as one run, all issued before the first
+// is waited on.
 template <typename R, int LX>
 __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
                                                          cplx<R> *__restrict__ H) {
-    constexpr int M = LX / 2, RW = kLatThreads / 2, SP = M + 1;   // rows padded against bank conflicts
-    __shared__ cplx<R> S[RW * SP];
+    constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
+    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kLatThreads - 1) / kLatThreads;
+    __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
-    const int ex = g.ex;
-    const int64_t per_w = (int64_t)g.ey * g.ez, n_rows = (int64_t)g.nc * g.n_freq * per_w;
-    const int64_t row0 = (int64_t)blockIdx.x * RW;
-    for (int e = t; e < RW * ex; e += kLatThreads) {
-        const int rl = e / ex, x = e % ex;
-        const int64_t r = row0 + rl;
-        if (r >= n_rows) break;
-        const int64_t cw = r / per_w, q = r % per_w;
-        const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-        S[rl * SP + x] = F[c * g.fstride + w * g.n_slots + q * ex + x];
+    const int ex = g.ex, per_w = g.ey * g.ez;
+    const XTile tl = x_tile(g, blockIdx.x);
+    const cplx<R> *Fc = F + (int64_t)tl.c * g.fstride;
+    cplx<R> v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
+        const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
+        const int q = tl.q0 + ql, w = tl.w0 + wl;
+        const bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
+        const cplx<R> y = Fc[ok ? (int64_t)(q * ex + x) * g.n_freq + w : 0];
+        v[i] = csel(ok, y, czero<R>());
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
+        const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
+        if (e < CELLS) S[(wl * kTQ + ql) * SP + x] = v[i];
     }
     __syncthreads();
     const int rl = t >> 1, odd = t & 1;
-    const int64_t r = row0 + rl;
-    if (r >= n_rows) return;
+    const int q = tl.q0 + rl % kTQ, w = tl.w0 + rl / kTQ;
     cplx<R> a[M];
 #pragma unroll
-    for (int n = 0; n < M; ++n) a[n] = n < ex ? S[rl * SP + n] : czero<R>();
+    for (int n = 0; n < M; ++n) a[n] = S[rl * SP + n];
     pair_fwd<R, LX>(a, odd);
-    const int64_t cw = r / per_w, q = r % per_w;
-    const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-    cplx<R> *out = H + c * g.hstride + w * LX * per_w + q;
+    if (q < per_w && w < g.n_freq) {
+        cplx<R> *out = H + (int64_t)tl.c * g.hstride + (int64_t)w * LX * per_w + q;
 #pragma unroll
-    for (int m = 0; m < M; ++m) out[(2 * m + odd) * per_w] = a[m];
+        for (int m = 0; m < M; ++m) out[(2 * m + odd) * per_w] = a[m];
+    }
 }
 
 // Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
@@ -322,38 +347,39 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
     }
 }
 
-// Inverse x lines of H, cropped to the box, -> Uhat (staged through LDS for
-// coalesced stores).  Every lane reaches the exchange.
+// Inverse x lines of H, cropped to the box, -> Uhat, tile by tile as in
+// lat_x_fwd (staged through LDS so that each slot's kTW frequencies are
+// stored as one run).  Every lane reaches the exchange.
 template <typename R, int LX>
 __global__ void __launch_bounds__(kLatThreads) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
                                                          cplx<R> *__restrict__ U) {
-    constexpr int M = LX / 2, RW = kLatThreads / 2, SP = M + 1;   // rows padded against bank conflicts
-    __shared__ cplx<R> S[RW * SP];
+    constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
+    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kLatThreads - 1) / kLatThreads;
+    __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
-    const int ex = g.ex;
-    const int64_t per_w = (int64_t)g.ey * g.ez, n_rows = (int64_t)g.nc * g.n_freq * per_w;
-    const int64_t row0 = (int64_t)blockIdx.x * RW;
+    const int ex = g.ex, per_w = g.ey * g.ez;
+    const XTile tl = x_tile(g, blockIdx.x);
     const int rl = t >> 1, odd = t & 1;
-    const int64_t r = row0 + rl;
-    const bool on = r < n_rows;
-    const int64_t cw = on ? r / per_w : 0, q = on ? r % per_w : 0;
-    const int64_t c = cw / g.n_freq, w = cw % g.n_freq;
-    const cplx<R> *in = H + c * g.hstride + w * LX * per_w + q;
+    const int q = tl.q0 + rl % kTQ, w = tl.w0 + rl / kTQ;
+    const bool on = q < per_w && w < g.n_freq;
+    // lines outside the data read the tile's first line (their results are dropped)
+    const cplx<R> *in = H + (int64_t)tl.c * g.hstride + (on ? (int64_t)w * LX * per_w + q : 0);
     cplx<R> a[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) a[m] = on ? in[(2 * m + odd) * per_w] : czero<R>();
+    for (int m = 0; m < M; ++m) a[m] = in[(2 * m + odd) * per_w];
     cplx<R> out[LX / 4];
     pair_inv<R, LX>(a, odd, out);
 #pragma unroll
     for (int j = 0; j < LX / 4; ++j) S[rl * SP + (odd ? M / 2 + j : j)] = out[j];
     __syncthreads();
-    for (int e = t; e < RW * ex; e += kLatThreads) {
-        const int rr = e / ex, x = e % ex;
-        const int64_t r2 = row0 + rr;
-        if (r2 >= n_rows) break;
-        const int64_t cw2 = r2 / per_w, q2 = r2 % per_w;
-        const int64_t c2 = cw2 / g.n_freq, w2 = cw2 % g.n_freq;
-        U[c2 * g.fstride + w2 * g.n_slots + q2 * ex + x] = S[rr * SP + x];
+    cplx<R> *Uc = U + (int64_t)tl.c * g.fstride;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kLatThreads;
+        const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
+        const int q2 = tl.q0 + ql, w2 = tl.w0 + wl;
+        if (e < CELLS && x < ex && q2 < per_w && w2 < g.n_freq)
+            Uc[(int64_t)(q2 * ex + x) * g.n_freq + w2] = S[(wl * kTQ + ql) * SP + x];
     }
 }
 
@@ -459,9 +485,14 @@ template <typename F> hipError_t with_len(int L, F &&f) {
     }
 }
 
+// workgroups of the x kernels: one per (component, frequency tile, row tile)
+unsigned x_tiles(const LatGeom &g) {
+    const int per_w = g.ey * g.ez;
+    return (unsigned)((int64_t)g.nc * ((g.n_freq + kTW - 1) / kTW) * ((per_w + kTQ - 1) / kTQ));
+}
+
 template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void *H, hipStream_t s) {
-    const int64_t rows = (int64_t)g.nc * g.n_freq * g.ey * g.ez;
-    const unsigned blocks = (unsigned)((rows + kLatThreads / 2 - 1) / (kLatThreads / 2));
+    const unsigned blocks = x_tiles(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
         hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)F,
@@ -486,8 +517,7 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
 }
 
 template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
-    const int64_t rows = (int64_t)g.nc * g.n_freq * g.ey * g.ez;
-    const unsigned blocks = (unsigned)((rows + kLatThreads / 2 - 1) / (kLatThreads / 2));
+    const unsigned blocks = x_tiles(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
         hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)H,
@@ -540,7 +570,9 @@ int lattice_stored_freqs(int N) { return (N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1)
 static bool geom_ok(const LatGeom &g) {
     return lattice_len_ok(g.lx) && lattice_len_ok(g.ly) && lattice_len_ok(g.lz) && g.nc >= 1 && g.ex >= 1 &&
            g.ey >= 1 && g.ez >= 1 && 2 * g.ex <= g.lx && 2 * g.ey <= g.ly && 2 * g.ez <= g.lz && g.N >= 2 &&
-           g.n_freq == g.N * g.N * (g.N / 2 + 1);
+           g.n_freq == g.N * g.N * (g.N / 2 + 1) && g.n_slots == (int64_t)g.ex * g.ey * g.ez &&
+           g.fstride >= (int64_t)g.n_freq * g.n_slots &&
+           g.hstride >= (int64_t)g.n_freq * g.lx * g.ey * g.ez;
 }
 
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s) {

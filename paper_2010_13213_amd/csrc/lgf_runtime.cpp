@@ -938,7 +938,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
         StageTimer t(plan->ctx, 0, s);
         hip_check(block_fft_forward(nb, c.fp32, src + (size_t)k * sstride, (const int64_t *)c.d_src_off.ptr,
                                     (const int *)c.d_src_slot.ptr, c.n_src, (char *)plan->Fhat.ptr + k * fs * elem,
-                                    c.n_slots, 1.0, s),
+                                    c.n_slots, c.method == kMethodLattice, 1.0, s),
                   "forward block FFT");
     }
     if (c.method == kMethodLattice) {
@@ -967,7 +967,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 2, s);
         hip_check(block_fft_inverse(nb, c.fp32, (char *)plan->Uhat.ptr + k * fs * elem, c.n_slots,
-                                    (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
+                                    c.method == kMethodLattice, (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
                                     dst + (size_t)k * dstride, dx * dx / N3, accumulate, s),
                   "inverse block FFT");
     }

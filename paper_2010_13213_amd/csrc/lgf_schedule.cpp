@@ -420,6 +420,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
             j.slot = (const int *)k.c->d_src_slot.ptr;
             j.spec = k.p->Fhat.ptr;
             j.n_slots = k.c->n_slots;
+            j.block_major = k.c->method == kMethodLattice;
             j.scale = 1.0;
             j.blk_begin = total;
             total += k.c->n_src;
@@ -499,6 +500,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
             j.slot = (const int *)k.c->d_tgt_slot.ptr;
             j.spec = k.p->Uhat.ptr;
             j.n_slots = k.c->n_slots;
+            j.block_major = k.c->method == kMethodLattice;
             j.scale = k.dx * k.dx / N3;
             j.accumulate = k.accumulate;
             j.blk_begin = total;
