@@ -111,9 +111,10 @@ hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const 
 // edge (n_freq = N^2 (N/2 + 1)).  Fhat / Uhat block-major: [c][slot][omega]
 // (slot = (z ey + y) ex + x, n_slots = ex ey ez), components fstride
 // (>= n_freq n_slots) elements apart; H:
-// [c][omega][kx][z][y] workspace, components hstride (>= n_freq lx ey ez)
-// elements apart; Khat: real [omega_r][kx][kz][ky] over the stored
-// frequencies (ky, kz in [0, N/2]).
+// [c][omega][kx][z][y] workspace, (omega, kx) slabs of ey ez elements
+// hslab (>= ey ez) apart, components hstride (>= n_freq lx hslab) elements
+// apart; Khat: real [omega_r][kx][kz][ky] over the stored frequencies
+// (ky, kz in [0, N/2]).
 struct LatGeom {
     int ex, ey, ez;
     int lx, ly, lz;
@@ -122,6 +123,7 @@ struct LatGeom {
     int n_freq;
     int64_t n_slots;        // ex * ey * ez
     int64_t fstride, hstride;
+    int hslab;
 };
 // Octant block-spectra table (offsets 0..XD-1 etc.) of FFT edge N = 2 nb.
 struct LatSpecGeom {

@@ -98,8 +98,9 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
 }
 
 // Tile of the x kernels: kTW consecutive frequencies x kTQ consecutive (y, z)
-// rows q of one component = 128 lines, a lane pair each; row rl = wl kTQ + ql.
-constexpr int kTW = 8, kTQ = kLatThreads / (2 * kTW);
+// rows q of one component, a lane pair per line (kXThreads threads); row
+// rl = wl kTQ + ql.
+constexpr int kTW = 8, kTQ = 16, kXThreads = 2 * kTW * kTQ;
 
 struct XTile {
     int c, w0, q0;
@@ -114,10 +115,10 @@ __device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
 // read each slot's kTW frequencies as one run, all issued before the first
 // is waited on.
 template <typename R, int LX>
-__global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
+__global__ void __launch_bounds__(kXThreads) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
                                                          cplx<R> *__restrict__ H) {
     constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
-    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kLatThreads - 1) / kLatThreads;
+    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kXThreads - 1) / kXThreads;
     __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
     const int ex = g.ex, per_w = g.ey * g.ez;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
     cplx<R> v[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int e = t + i * kLatThreads;
+        const int e = t + i * kXThreads;
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         const int q = tl.q0 + ql, w = tl.w0 + wl;
         const bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
@@ -135,7 +136,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int e = t + i * kLatThreads;
+        const int e = t + i * kXThreads;
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         if (e < CELLS) S[(wl * kTQ + ql) * SP + x] = v[i];
     }
@@ -147,11 +148,25 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
     for (int n = 0; n < M; ++n) a[n] = S[rl * SP + n];
     pair_fwd<R, LX>(a, odd);
     if (q < per_w && w < g.n_freq) {
-        cplx<R> *out = H + (int64_t)tl.c * g.hstride + (int64_t)w * LX * per_w + q;
+        cplx<R> *out = H + (int64_t)tl.c * g.hstride + (int64_t)w * LX * g.hslab + q;
 #pragma unroll
-        for (int m = 0; m < M; ++m) out[(2 * m + odd) * per_w] = a[m];
+        for (int m = 0; m < M; ++m) out[(2 * m + odd) * g.hslab] = a[m];
     }
 }
+
+// LDS of lat_yz: the zero-padded slabs P [s][z][y] (rows of MY + 1) and the
+// slabs after the y DFT Q [s][ky][z] (lines of MZ + 1; the padding element
+// keeps the lines a wave reads at once out of one bank).  When every lane
+// has at most one y line (LZ <= 2 LY), P lives at the start of Q: each
+// step reads its inputs into registers, and a barrier separates those
+// reads from the first write into the shared space.
+template <int LY, int LZ> struct YzLds {
+    static constexpr int SL = kLatThreads / (2 * LY);
+    static constexpr int MY = LY / 2, MZ = LZ / 2, PY = MY + 1, QZ = MZ + 1;
+    static constexpr int P_ELEMS = SL * MZ * PY, Q_ELEMS = SL * LY * QZ;
+    static constexpr bool ALIAS = SL * MZ <= kLatThreads / 2 && P_ELEMS <= Q_ELEMS;
+    static constexpr int ELEMS = ALIAS ? Q_ELEMS : P_ELEMS + Q_ELEMS;
+};
 
 // Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
 // the zero-padded slabs in P.  Every index that depends on the half is a
@@ -159,6 +174,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_fwd(LatGeom g, const cplx<R
 template <typename R, int LY, int LZ, int HF>
 __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
                                         const int (*sinfo)[2], int lane, int ez) {
+    using L = YzLds<LY, LZ>;
     constexpr int HL = kLatThreads / 2;
     constexpr int SL = HL / LY;
     constexpr int MY = LY / 2, MZ = LZ / 2;
@@ -184,19 +200,40 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
         }
     }
     // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
-    for (int line = lane; line < YLINES; line += HL) {
-        const int sl = line / MZ, z = line % MZ;
-        const cplx<R> *prow = P + (sl * MZ + z) * PY;
+    if (L::ALIAS) {
+        const int sl = lane / MZ, z = lane % MZ;
+        const bool on = lane < YLINES;
         cplx<R> a[MY];
+        if (on) {
+            const cplx<R> *prow = P + (sl * MZ + z) * PY;
 #pragma unroll
-        for (int n = 0; n < MY; ++n) a[n] = prow[n];
-        if (HF) {
+            for (int n = 0; n < MY; ++n) a[n] = prow[n];
+            if (HF) {
 #pragma unroll
-            for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
+                for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
+            }
+            fft_reg<R, MY, false>(a);
         }
-        fft_reg<R, MY, false>(a);
+        __syncthreads();   // P (inside Q) is read
+        if (on) {
 #pragma unroll
-        for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + HF) * QZ + z] = a[m];
+            for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + HF) * QZ + z] = a[m];
+        }
+    } else {
+        for (int line = lane; line < YLINES; line += HL) {
+            const int sl = line / MZ, z = line % MZ;
+            const cplx<R> *prow = P + (sl * MZ + z) * PY;
+            cplx<R> a[MY];
+#pragma unroll
+            for (int n = 0; n < MY; ++n) a[n] = prow[n];
+            if (HF) {
+#pragma unroll
+                for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
+            }
+            fft_reg<R, MY, false>(a);
+#pragma unroll
+            for (int m = 0; m < MY; ++m) Q[(sl * LY + 2 * m + HF) * QZ + z] = a[m];
+        }
     }
     __syncthreads();
     // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
@@ -243,6 +280,9 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
 #pragma unroll
             for (int m = 0; m < MY; ++m) b[m] = Q[(sl * LY + 2 * m + HF) * QZ + z];
             fft_reg<R, MY, true>(b);
+        }
+        if (L::ALIAS) __syncthreads();   // Q is read before P (inside Q) is written
+        if (on) {
             if (HF) {
 #pragma unroll
                 for (int j = 0; j < (MY + 1) / 2; ++j) prow[j] = b[j];
@@ -277,7 +317,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
 // ones run on one XCD: the reflections share one stored Khat plane, which
 // is then read from HBM once and from that XCD's L2 for the others.
 template <typename R, int LY, int LZ>
-__global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
+__global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(4))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
                                                       const int *__restrict__ worder) {
     constexpr int HL = kLatThreads / 2;                 // lanes per half
     constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
@@ -286,15 +326,16 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
     // start 256 B apart and fall into one LDS bank
     constexpr int PY = MY + 1, QZ = MZ + 1;
     constexpr int CELLS = SL * MZ * MY;                 // slab cells zero-padded to MZ x MY
-    __shared__ cplx<R> P[SL * MZ * PY];   // slab [s][z][y]
-    __shared__ cplx<R> Q[SL * LY * QZ];   // after the y DFT [s][ky][z]
+    using L = YzLds<LY, LZ>;
+    __shared__ cplx<R> lds[L::ELEMS];
+    cplx<R> *Q = lds;                                   // after the y DFT [s][ky][z]
+    cplx<R> *P = L::ALIAS ? lds : lds + L::Q_ELEMS;     // slab [s][z][y]
     // per slab: H offset (-1 past the last slab), stored frequency, kx and reflections
     __shared__ int64_t hbase[SL];
     __shared__ int sinfo[SL][2];
     const int t = threadIdx.x;
     const int half = __builtin_amdgcn_readfirstlane(t / HL), lane = t % HL;   // half: uniform per wave
     const int ey = g.ey, ez = g.ez;
-    const int slab = ey * ez;
     // slab counts fit in 32 bits (the launch checks nc * n_freq * lx)
     const int per_c = g.n_freq * g.lx;                  // slabs per component
     const int n_slabs = g.nc * per_c;
@@ -308,7 +349,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
         const int N = g.N, Hh = N / 2 + 1;
         const int fx = w % Hh, fyv = (w / Hh) % N, fzv = w / (Hh * N);
         const int ry = fyv > N / 2, rz = fzv > N / 2;
-        hbase[t] = live ? (int64_t)(si / per_c) * g.hstride + ((int64_t)w * g.lx + kx) * slab : -1;
+        hbase[t] = live ? (int64_t)(si / per_c) * g.hstride + ((int64_t)w * g.lx + kx) * g.hslab : -1;
         sinfo[t][0] = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
         sinfo[t][1] = kx | ry << 8 | rz << 9;
     }
@@ -351,10 +392,10 @@ __global__ void __launch_bounds__(kLatThreads) lat_yz(LatGeom g, cplx<R> *__rest
 // lat_x_fwd (staged through LDS so that each slot's kTW frequencies are
 // stored as one run).  Every lane reaches the exchange.
 template <typename R, int LX>
-__global__ void __launch_bounds__(kLatThreads) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
+__global__ void __launch_bounds__(kXThreads) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
                                                          cplx<R> *__restrict__ U) {
     constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
-    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kLatThreads - 1) / kLatThreads;
+    constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kXThreads - 1) / kXThreads;
     __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
     const int ex = g.ex, per_w = g.ey * g.ez;
@@ -363,10 +404,10 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_inv(LatGeom g, const cplx<R
     const int q = tl.q0 + rl % kTQ, w = tl.w0 + rl / kTQ;
     const bool on = q < per_w && w < g.n_freq;
     // lines outside the data read the tile's first line (their results are dropped)
-    const cplx<R> *in = H + (int64_t)tl.c * g.hstride + (on ? (int64_t)w * LX * per_w + q : 0);
+    const cplx<R> *in = H + (int64_t)tl.c * g.hstride + (on ? (int64_t)w * LX * g.hslab + q : 0);
     cplx<R> a[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) a[m] = in[(2 * m + odd) * per_w];
+    for (int m = 0; m < M; ++m) a[m] = in[(2 * m + odd) * g.hslab];
     cplx<R> out[LX / 4];
     pair_inv<R, LX>(a, odd, out);
 #pragma unroll
@@ -375,7 +416,7 @@ __global__ void __launch_bounds__(kLatThreads) lat_x_inv(LatGeom g, const cplx<R
     cplx<R> *Uc = U + (int64_t)tl.c * g.fstride;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int e = t + i * kLatThreads;
+        const int e = t + i * kXThreads;
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         const int q2 = tl.q0 + ql, w2 = tl.w0 + wl;
         if (e < CELLS && x < ex && q2 < per_w && w2 < g.n_freq)
@@ -495,7 +536,7 @@ template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void 
     const unsigned blocks = x_tiles(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
-        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)F,
+        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(kXThreads), 0, s, g, (const cplx<R> *)F,
                            (cplx<R> *)H);
         return hipGetLastError();
     });
@@ -520,7 +561,7 @@ template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void 
     const unsigned blocks = x_tiles(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
-        hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(kLatThreads), 0, s, g, (const cplx<R> *)H,
+        hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(kXThreads), 0, s, g, (const cplx<R> *)H,
                            (cplx<R> *)U);
         return hipGetLastError();
     });
@@ -572,7 +613,7 @@ static bool geom_ok(const LatGeom &g) {
            g.ey >= 1 && g.ez >= 1 && 2 * g.ex <= g.lx && 2 * g.ey <= g.ly && 2 * g.ez <= g.lz && g.N >= 2 &&
            g.n_freq == g.N * g.N * (g.N / 2 + 1) && g.n_slots == (int64_t)g.ex * g.ey * g.ez &&
            g.fstride >= (int64_t)g.n_freq * g.n_slots &&
-           g.hstride >= (int64_t)g.n_freq * g.lx * g.ey * g.ez;
+           g.hslab >= g.ey * g.ez && g.hstride >= (int64_t)g.n_freq * g.lx * g.hslab;
 }
 
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s) {

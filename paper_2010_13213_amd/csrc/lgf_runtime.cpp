@@ -319,7 +319,12 @@ LatGeom lat_geom(const Conv &c, int nc) {
     g.n_freq = c.spec->n_freq;
     g.n_slots = c.n_slots;
     g.fstride = (int64_t)c.spec->n_freq * c.n_slots;
-    g.hstride = (int64_t)c.spec->n_freq * c.lx * c.ey * c.ez;
+    // slabs of a multiple of 32 elements are padded by 8 (one 128-byte line
+    // in float64): unpadded, the lx slabs a lattice x line touches are a
+    // power-of-two stride apart
+    const int per_w = c.ey * c.ez;
+    g.hslab = per_w % 32 == 0 ? per_w + 8 : per_w;
+    g.hstride = (int64_t)c.spec->n_freq * c.lx * g.hslab;
     return g;
 }
 
