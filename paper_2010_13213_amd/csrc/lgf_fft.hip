@@ -5,12 +5,16 @@
 // convolution of an nb^3 block with a (2nb-1)^3 kernel window; zero-padding
 // the block to (2nb)^3 makes the circular convolution of the FFT exact.
 //
-// Forward (one workgroup per source block):
-//   x: nb^2 rows of nb reals, zero-padded to N = 2nb -> N/2+1 complex  (LDS A)
-//   y: nb (N/2+1) columns, zero-padded to N                            (LDS B, half of kx at a time)
-//   z: N (N/2+1) columns, zero-padded to N -> written frequency-major to HBM
+// Forward (three workgroups per source block, one per third of the kx range):
+//   x: nb^2 rows of nb reals, zero-padded to N = 2nb -> N/2+1 complex, the
+//      chunk's kx kept                                                 (LDS A)
+//   y: nb x (chunk) columns, zero-padded to N                          (LDS B)
+//   z: N x (chunk) columns, zero-padded to N -> written to HBM
+// (a third of the LDS each: two workgroups fit a CU in float64)
 // The zero half of the input is never loaded.  Inverse runs the same stages
-// backwards and keeps only the [0, nb)^3 corner of the result.
+// backwards and keeps only the [0, nb)^3 corner of the result (one
+// workgroup per block: two per block, each keeping half of the z outputs,
+// was slower, 0.44 against 0.42 ms for the 256^3 box).
 //
 // Every forward line has nb nonzero inputs out of N = 2nb, so it is split
 // in halves by the radix-2 identities (M = nb, w = exp(-2 pi i / N)):
@@ -21,10 +25,11 @@
 // halve the registers of a lane and double the waves of a block.  The
 // inverse keeps one thread per whole line.
 //
-// A block's spectrum is one 16-byte (8 in float32) entry per frequency row
-// of the frequency-major arrays, so neighbouring slots share HBM lines;
-// blocks are renumbered so that consecutive blocks (consecutive slots) run
-// at the same time on one XCD and meet in its L2.
+// Spectra are stored block-major (a block's spectrum is one contiguous run;
+// the lattice MAC) or frequency-major (one 16-byte entry, 8 in float32, per
+// frequency row, so neighbouring slots share HBM lines; the block-pair MAC).
+// Workgroups are renumbered so that consecutive ones (the chunks of a block,
+// neighbouring slots) run at the same time on one XCD and meet in its L2.
 #include "lgf_device.hpp"
 #include "lgf_kernels.hpp"
 
@@ -36,12 +41,17 @@ template <int NB, typename R> struct FftShape {
     static constexpr int N = 2 * NB;
     static constexpr int M = NB;                // half-line length
     static constexpr int H = NB + 1;            // r2c length along x
-    static constexpr int HH = (H + 1) / 2;      // kx handled per half
-    static constexpr int A_ELEMS = NB * NB * H; // [z][y][kx]
-    static constexpr int B_ELEMS = NB * N * HH; // [z][ky][kxl]
+    static constexpr int HH = (H + 1) / 2;      // inverse: kx handled per pass
+    static constexpr int A_ELEMS = NB * NB * H; // inverse: [z][y][kx]
+    static constexpr int B_ELEMS = NB * N * HH; // inverse: [z][ky][kxl]
     static constexpr int HL = NB * NB;          // lanes per half
     static constexpr int NT = 2 * HL;           // threads per block
+    // forward: kx in kFwdChunks chunks of KC, one workgroup each
+    static constexpr int KC = (H + 2) / 3;
+    static constexpr int FA_ELEMS = NB * NB * KC;   // [z][y][kxl]
+    static constexpr int FB_ELEMS = NB * N * KC;    // [z][ky][kxl]
 };
+constexpr int kFwdChunks = 3;
 
 template <int NB> constexpr int fft_threads = 2 * NB * NB;   // FftShape<NB, R>::NT, usable in a macro
 
@@ -56,20 +66,24 @@ template <typename R, int N, int M> __device__ __forceinline__ void odd_twiddle(
 // frequency-major (ws = n_slots, ss = 1) or block-major (ws = 1, ss = n_freq).
 template <int NB> constexpr int64_t fft_freqs = 4 * NB * NB * (NB + 1);   // (2nb)^2 (nb + 1)
 
+// Forward transform of block b, kx chunk `chunk` (kx in [chunk KC, ...)):
+// the x pass is computed whole and only the chunk's kx are kept, so three
+// workgroups share a block and each needs a third of the LDS.
 template <int NB, typename R>
 __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                          const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t ws,
-                                         int64_t ss, double scale, int b) {
+                                         int64_t ss, double scale, int b, int chunk) {
     using S = FftShape<NB, R>;
-    constexpr int N = S::N, M = S::M, H = S::H, HH = S::HH, HL = S::HL;
-    __shared__ cplx<R> A[S::A_ELEMS];
-    __shared__ cplx<R> B[S::B_ELEMS];
+    constexpr int N = S::N, M = S::M, H = S::H, KC = S::KC, HL = S::HL;
+    __shared__ cplx<R> A[S::FA_ELEMS];
+    __shared__ cplx<R> B[S::FB_ELEMS];
     const double *in = src + blk_off[b];
     cplx<R> *Fb = Fhat + slot[b] * ss;
     const int t = threadIdx.x;
     const int half = t / HL, lane = t % HL;
+    const int k0 = chunk * KC, nk = min(KC, H - k0);
 
-    // x pass: row (y, z) = lane; this half's outputs kx = 2m + half <= nb
+    // x pass: row (y, z) = lane; this half's outputs kx = 2m + half, kept in the chunk
     {
         const int y = lane % NB, z = lane / NB;
         const double *row = in + ((size_t)z * NB + y) * NB;
@@ -79,51 +93,50 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
         if (half) odd_twiddle<R, N, M>(a);
         fft_reg<R, M, false>(a);
 #pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (2 * m + half < H) A[(z * NB + y) * H + 2 * m + half] = a[m];
+        for (int m = 0; m < M; ++m) {
+            const int kxl = 2 * m + half - k0;
+            if (kxl >= 0 && kxl < nk) A[(z * NB + y) * KC + kxl] = a[m];
+        }
     }
     __syncthreads();
-
-    for (int hk = 0; hk < 2; ++hk) {
-        const int k0 = hk * HH;
-        const int nk = (hk == 0) ? HH : H - HH;
-        // y pass: column (z, kx)
-        for (int line = lane; line < NB * nk; line += HL) {
-            const int kxl = line % nk, z = line / nk;
-            cplx<R> a[M];
+    // y pass: column (z, kxl)
+    for (int line = lane; line < NB * nk; line += HL) {
+        const int kxl = line % nk, z = line / nk;
+        cplx<R> a[M];
 #pragma unroll
-            for (int y = 0; y < M; ++y) a[y] = A[(z * NB + y) * H + k0 + kxl];
-            if (half) odd_twiddle<R, N, M>(a);
-            fft_reg<R, M, false>(a);
+        for (int y = 0; y < M; ++y) a[y] = A[(z * NB + y) * KC + kxl];
+        if (half) odd_twiddle<R, N, M>(a);
+        fft_reg<R, M, false>(a);
 #pragma unroll
-            for (int m = 0; m < M; ++m) B[(z * N + 2 * m + half) * HH + kxl] = a[m];
+        for (int m = 0; m < M; ++m) B[(z * N + 2 * m + half) * KC + kxl] = a[m];
+    }
+    __syncthreads();
+    // z pass: column (ky, kxl) -> HBM
+    for (int line = lane; line < N * nk; line += HL) {
+        const int kxl = line % nk, ky = line / nk;
+        cplx<R> a[M];
+#pragma unroll
+        for (int z = 0; z < M; ++z) a[z] = B[(z * N + ky) * KC + kxl];
+        if (half) odd_twiddle<R, N, M>(a);
+        fft_reg<R, M, false>(a);
+        const int kx = k0 + kxl;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int64_t omega = ((int64_t)(2 * m + half) * N + ky) * H + kx;
+            Fb[omega * ws] = a[m];
         }
-        __syncthreads();
-        // z pass: column (ky, kx) -> HBM
-        for (int line = lane; line < N * nk; line += HL) {
-            const int kxl = line % nk, ky = line / nk;
-            cplx<R> a[M];
-#pragma unroll
-            for (int z = 0; z < M; ++z) a[z] = B[(z * N + ky) * HH + kxl];
-            if (half) odd_twiddle<R, N, M>(a);
-            fft_reg<R, M, false>(a);
-            const int kx = k0 + kxl;
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int64_t omega = ((int64_t)(2 * m + half) * N + ky) * H + kx;
-                Fb[omega * ws] = a[m];
-            }
-        }
-        __syncthreads();
     }
 }
 
+// workgroup -> (block, chunk); the chunks of a block are consecutive and run
+// on one XCD (they read the same input block)
 template <int NB, typename R>
 __global__ void __launch_bounds__(fft_threads<NB>) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                                   const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
                                                   int64_t n_slots, int block_major, double scale) {
+    const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
     fwd_body<NB, R>(src, blk_off, slot, Fhat, block_major ? 1 : n_slots, block_major ? fft_freqs<NB> : 1, scale,
-                    (int)xcd_order(blockIdx.x, gridDim.x));
+                    wg / kFwdChunks, wg % kFwdChunks);
 }
 
 __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
@@ -138,10 +151,11 @@ __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_j
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(fft_threads<NB>) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
-    const int b = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int b = wg / kFwdChunks;
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
     fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.block_major ? 1 : j.n_slots,
-                    j.block_major ? fft_freqs<NB> : 1, j.scale, b - j.blk_begin);
+                    j.block_major ? fft_freqs<NB> : 1, j.scale, b - j.blk_begin, wg % kFwdChunks);
 }
 
 // The inverse keeps one thread per whole line (256 threads): splitting its
@@ -233,7 +247,8 @@ hipError_t batch_launch(bool inverse, const FftJob *jobs, int n_jobs, int total_
     if (inverse)
         hipLaunchKernelGGL((inv_batch_kernel<NB, R>), dim3(total_blocks), dim3(kInvThreads), 0, s, jobs, n_jobs);
     else
-        hipLaunchKernelGGL((fwd_batch_kernel<NB, R>), dim3(total_blocks), dim3(FftShape<NB, R>::NT), 0, s, jobs, n_jobs);
+        hipLaunchKernelGGL((fwd_batch_kernel<NB, R>), dim3(total_blocks * kFwdChunks), dim3(FftShape<NB, R>::NT), 0, s,
+                           jobs, n_jobs);
     return hipGetLastError();
 }
 
@@ -241,7 +256,7 @@ template <int NB, typename R>
 hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
                       int64_t n_slots, bool block_major, double scale, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
+    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks * kFwdChunks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
                        n_slots, (int)block_major, scale);
     return hipGetLastError();
 }
