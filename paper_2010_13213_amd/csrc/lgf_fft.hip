@@ -12,9 +12,8 @@
 //   z: N x (chunk) columns, zero-padded to N -> written to HBM
 // (a third of the LDS each: two workgroups fit a CU in float64)
 // The zero half of the input is never loaded.  Inverse runs the same stages
-// backwards and keeps only the [0, nb)^3 corner of the result (one
-// workgroup per block: two per block, each keeping half of the z outputs,
-// was slower, 0.44 against 0.42 ms for the 256^3 box).
+// backwards, chunk by chunk in one workgroup per block, and keeps only the
+// [0, nb)^3 corner of the result.
 //
 // Every forward line has nb nonzero inputs out of N = 2nb, so it is split
 // in halves by the radix-2 identities (M = nb, w = exp(-2 pi i / N)):
@@ -41,17 +40,14 @@ template <int NB, typename R> struct FftShape {
     static constexpr int N = 2 * NB;
     static constexpr int M = NB;                // half-line length
     static constexpr int H = NB + 1;            // r2c length along x
-    static constexpr int HH = (H + 1) / 2;      // inverse: kx handled per pass
-    static constexpr int A_ELEMS = NB * NB * H; // inverse: [z][y][kx]
-    static constexpr int B_ELEMS = NB * N * HH; // inverse: [z][ky][kxl]
     static constexpr int HL = NB * NB;          // lanes per half
     static constexpr int NT = 2 * HL;           // threads per block
-    // forward: kx in kFwdChunks chunks of KC, one workgroup each
+    // kx in kSpecChunks chunks of KC (spec_chunk): one forward workgroup
+    // each; the inverse walks them in turn
     static constexpr int KC = (H + 2) / 3;
     static constexpr int FA_ELEMS = NB * NB * KC;   // [z][y][kxl]
     static constexpr int FB_ELEMS = NB * N * KC;    // [z][ky][kxl]
 };
-constexpr int kFwdChunks = 3;
 
 template <int NB> constexpr int fft_threads = 2 * NB * NB;   // FftShape<NB, R>::NT, usable in a macro
 
@@ -69,16 +65,18 @@ template <int NB> constexpr int64_t fft_freqs = 4 * NB * NB * (NB + 1);   // (2n
 // Forward transform of block b, kx chunk `chunk` (kx in [chunk KC, ...)):
 // the x pass is computed whole and only the chunk's kx are kept, so three
 // workgroups share a block and each needs a third of the LDS.
-template <int NB, typename R>
+// BM: block-major (chunk-major within a block, spec_pos) or frequency-major
+// spectra.  A, B: the workgroup's LDS (FA_ELEMS, FB_ELEMS).
+template <int NB, typename R, bool BM>
 __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
-                                         const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t ws,
-                                         int64_t ss, double scale, int b, int chunk) {
+                                         const int *__restrict__ slot, cplx<R> *__restrict__ Fhat, int64_t n_slots,
+                                         double scale, int b, int chunk, cplx<R> *A, cplx<R> *B) {
     using S = FftShape<NB, R>;
     constexpr int N = S::N, M = S::M, H = S::H, KC = S::KC, HL = S::HL;
-    __shared__ cplx<R> A[S::FA_ELEMS];
-    __shared__ cplx<R> B[S::FB_ELEMS];
+    static_assert(KC * kSpecChunks >= H && KC * (kSpecChunks - 1) < H, "kx chunks");
     const double *in = src + blk_off[b];
-    cplx<R> *Fb = Fhat + slot[b] * ss;
+    const int64_t ws = BM ? 1 : n_slots;
+    cplx<R> *Fb = Fhat + slot[b] * (BM ? fft_freqs<NB> : 1);
     const int t = threadIdx.x;
     const int half = t / HL, lane = t % HL;
     const int k0 = chunk * KC, nk = min(KC, H - k0);
@@ -122,8 +120,10 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
         const int kx = k0 + kxl;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const int64_t omega = ((int64_t)(2 * m + half) * N + ky) * H + kx;
-            Fb[omega * ws] = a[m];
+            // block-major: the chunk's run [kz][ky][kxl] (spec_pos); frequency-major: omega
+            const int kz = 2 * m + half;
+            const int64_t pos = BM ? (int64_t)N * N * k0 + (kz * N + ky) * nk + kxl : ((int64_t)kz * N + ky) * H + kx;
+            Fb[pos * ws] = a[m];
         }
     }
 }
@@ -131,12 +131,17 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
 // workgroup -> (block, chunk); the chunks of a block are consecutive and run
 // on one XCD (they read the same input block)
 template <int NB, typename R>
-__global__ void __launch_bounds__(fft_threads<NB>) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
+__global__ void __launch_bounds__(fft_threads<NB>) __attribute__((amdgpu_waves_per_eu(4))) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                                   const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
                                                   int64_t n_slots, int block_major, double scale) {
+    using S = FftShape<NB, R>;
+    __shared__ cplx<R> A[S::FA_ELEMS];
+    __shared__ cplx<R> B[S::FB_ELEMS];
     const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
-    fwd_body<NB, R>(src, blk_off, slot, Fhat, block_major ? 1 : n_slots, block_major ? fft_freqs<NB> : 1, scale,
-                    wg / kFwdChunks, wg % kFwdChunks);
+    if (block_major)
+        fwd_body<NB, R, true>(src, blk_off, slot, Fhat, n_slots, scale, wg / kSpecChunks, wg % kSpecChunks, A, B);
+    else
+        fwd_body<NB, R, false>(src, blk_off, slot, Fhat, n_slots, scale, wg / kSpecChunks, wg % kSpecChunks, A, B);
 }
 
 __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
@@ -150,75 +155,106 @@ __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_j
 }
 
 template <int NB, typename R>
-__global__ void __launch_bounds__(fft_threads<NB>) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
+__global__ void __launch_bounds__(fft_threads<NB>) __attribute__((amdgpu_waves_per_eu(4))) fwd_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
     const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
-    const int b = wg / kFwdChunks;
+    using S = FftShape<NB, R>;
+    __shared__ cplx<R> A[S::FA_ELEMS];
+    __shared__ cplx<R> B[S::FB_ELEMS];
+    const int b = wg / kSpecChunks;
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
-    fwd_body<NB, R>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.block_major ? 1 : j.n_slots,
-                    j.block_major ? fft_freqs<NB> : 1, j.scale, b - j.blk_begin, wg % kFwdChunks);
+    if (j.block_major)
+        fwd_body<NB, R, true>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, b - j.blk_begin,
+                              wg % kSpecChunks, A, B);
+    else
+        fwd_body<NB, R, false>(j.src, j.blk_off, j.slot, (cplx<R> *)j.spec, j.n_slots, j.scale, b - j.blk_begin,
+                               wg % kSpecChunks, A, B);
 }
 
-// The inverse keeps one thread per whole line (256 threads): splitting its
-// lines in halves, as the forward does, needs an exchange per line and was
-// slower (0.85 against 0.75 ms for the 256^3 box).
+// The inverse keeps one thread per whole line (256 threads) and walks the
+// kx chunks of the forward: per chunk an inverse z pass from HBM (one
+// contiguous run of a block-major spectrum), an inverse y pass, and the
+// chunk's share of the complex-to-real x sums, accumulated in registers by
+// the thread that owns the row.  LDS holds one chunk (73.7 KB in float64),
+// so two workgroups fit a CU.
 constexpr int kInvThreads = 256;
 
-template <int NB, typename R>
-__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t ws, int64_t ss,
-                                         const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
-                                         double *__restrict__ dst, double scale, int accumulate, int b) {
-    using S = FftShape<NB, R>;
-    constexpr int N = S::N, H = S::H, HH = S::HH;
-    __shared__ cplx<R> D[S::A_ELEMS];   // [z][y][kx] after the z and y passes
-    __shared__ cplx<R> C[S::B_ELEMS];   // [z][ky][kxl]
-    const cplx<R> *Ub = Uhat + slot[b] * ss;
-    const int t = threadIdx.x;
+// Re(v exp(+2 pi i j / N)), j a compile-time value after unrolling
+template <typename R, int N> __device__ __forceinline__ R re_rot(cplx<R> v, int j) {
+    const int q = (j % N) * (32 / N);   // in 32nds of a turn
+    const R c = q < 16 ? (R)kTw32[q][0] : -(R)kTw32[q - 16][0];
+    const R s = q < 16 ? -(R)kTw32[q][1] : (R)kTw32[q - 16][1];   // sin(2 pi q / 32)
+    return v.x * c - v.y * s;
+}
 
-    for (int half = 0; half < 2; ++half) {
-        const int k0 = half * HH;
-        const int nk = (half == 0) ? HH : H - HH;
-        // inverse z pass: column (ky, kx) from HBM, keep z < nb
+// C: [z][ky][kxl] after the z pass (FB_ELEMS), D: [z][y][kxl] after the y
+// pass (FA_ELEMS), the workgroup's LDS.
+template <int NB, typename R, bool BM>
+__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+                                         const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
+                                         double *__restrict__ dst, double scale, int accumulate, int b, cplx<R> *C,
+                                         cplx<R> *D) {
+    using S = FftShape<NB, R>;
+    constexpr int N = S::N, H = S::H, KC = S::KC;
+    static_assert(NB * NB <= kInvThreads, "one x row per thread");
+    const int64_t ws = BM ? 1 : n_slots;
+    const cplx<R> *Ub = Uhat + slot[b] * (BM ? fft_freqs<NB> : 1);
+    const int t = threadIdx.x;
+    R acc[NB];
+#pragma unroll
+    for (int x = 0; x < NB; ++x) acc[x] = (R)0;
+
+#pragma unroll
+    for (int c = 0; c < kSpecChunks; ++c) {
+        const int k0 = c * KC;
+        const int nk = KC < H - k0 ? KC : H - k0;
+        // inverse z pass: column (ky, kxl) from HBM, keep z < nb
         for (int line = t; line < N * nk; line += kInvThreads) {
             const int kxl = line % nk, ky = line / nk;
-            const int kx = k0 + kxl;
             cplx<R> a[N];
 #pragma unroll
             for (int kz = 0; kz < N; ++kz) {
-                const int64_t omega = ((int64_t)kz * N + ky) * H + kx;
-                a[kz] = Ub[omega * ws];
+                const int64_t pos =
+                    BM ? (int64_t)N * N * k0 + (kz * N + ky) * nk + kxl : ((int64_t)kz * N + ky) * H + k0 + kxl;
+                a[kz] = Ub[pos * ws];
             }
             fft_reg<R, N, true>(a);
 #pragma unroll
-            for (int z = 0; z < NB; ++z) C[(z * N + ky) * HH + kxl] = a[z];
+            for (int z = 0; z < NB; ++z) C[(z * N + ky) * KC + kxl] = a[z];
         }
         __syncthreads();
-        // inverse y pass: column (z, kx), keep y < nb
+        // inverse y pass: column (z, kxl), keep y < nb
         for (int line = t; line < NB * nk; line += kInvThreads) {
             const int kxl = line % nk, z = line / nk;
             cplx<R> a[N];
 #pragma unroll
-            for (int ky = 0; ky < N; ++ky) a[ky] = C[(z * N + ky) * HH + kxl];
+            for (int ky = 0; ky < N; ++ky) a[ky] = C[(z * N + ky) * KC + kxl];
             fft_reg<R, N, true>(a);
 #pragma unroll
-            for (int y = 0; y < NB; ++y) D[(z * NB + y) * H + k0 + kxl] = a[y];
+            for (int y = 0; y < NB; ++y) D[(z * NB + y) * KC + kxl] = a[y];
         }
         __syncthreads();
+        // x sums of row (y, z) = t: u[x] += c_kx Re(X[kx] exp(2 pi i kx x / N)),
+        // c_kx = 1 at kx = 0 and N/2 (real by symmetry), 2 otherwise
+        if (t < NB * NB) {
+            const cplx<R> *row = D + t * KC;
+#pragma unroll
+            for (int kxl = 0; kxl < KC; ++kxl) {
+                const int kx = c * KC + kxl;
+                if (kx < H) {
+                    const cplx<R> v = row[kxl];
+                    const R w = (kx == 0 || kx == N / 2) ? (R)1 : (R)2;
+#pragma unroll
+                    for (int x = 0; x < NB; ++x) acc[x] += w * re_rot<R, N>(v, kx * x);
+                }
+            }
+        }
+        __syncthreads();   // C and D are rewritten by the next chunk
     }
-    // inverse x pass (complex-to-real): row (y, z), keep x < nb
-    double *out = dst + blk_off[b];
-    for (int line = t; line < NB * NB; line += kInvThreads) {
-        const int y = line % NB, z = line / NB;
-        cplx<R> a[N];
-        const cplx<R> *row = D + (z * NB + y) * H;
-#pragma unroll
-        for (int k = 0; k < H; ++k) a[k] = row[k];
-#pragma unroll
-        for (int k = 1; k < N / 2; ++k) a[N - k] = cmake<R>(row[k].x, -row[k].y);
-        fft_reg<R, N, true>(a);
-        double *o = out + ((size_t)z * NB + y) * NB;
+    if (t < NB * NB) {
+        double *o = dst + blk_off[b] + (size_t)t * NB;   // row (y, z) = t: z = t / NB, y = t % NB
 #pragma unroll
         for (int x = 0; x < NB; ++x) {
-            const double v = (double)a[x].x * scale;
+            const double v = (double)acc[x] * scale;
             o[x] = accumulate ? o[x] + v : v;
         }
     }
@@ -229,16 +265,27 @@ __global__ void __launch_bounds__(kInvThreads) inv_kernel(const cplx<R> *__restr
                                                   int block_major, const int *__restrict__ slot,
                                                   const int64_t *__restrict__ blk_off, double *__restrict__ dst,
                                                   double scale, int accumulate) {
-    inv_body<NB, R>(Uhat, block_major ? 1 : n_slots, block_major ? fft_freqs<NB> : 1, slot, blk_off, dst, scale,
-                    accumulate, (int)xcd_order(blockIdx.x, gridDim.x));
+    using S = FftShape<NB, R>;
+    __shared__ cplx<R> C[S::FB_ELEMS];
+    __shared__ cplx<R> D[S::FA_ELEMS];
+    const int b = (int)xcd_order(blockIdx.x, gridDim.x);
+    if (block_major) inv_body<NB, R, true>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
+    else inv_body<NB, R, false>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
 }
 
 template <int NB, typename R>
 __global__ void __launch_bounds__(kInvThreads) inv_batch_kernel(const FftJob *__restrict__ jobs, int n_jobs) {
+    using S = FftShape<NB, R>;
+    __shared__ cplx<R> C[S::FB_ELEMS];
+    __shared__ cplx<R> D[S::FA_ELEMS];
     const int b = (int)xcd_order(blockIdx.x, gridDim.x);
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
-    inv_body<NB, R>((const cplx<R> *)j.spec, j.block_major ? 1 : j.n_slots, j.block_major ? fft_freqs<NB> : 1, j.slot,
-                    j.blk_off, j.dst, j.scale, j.accumulate, b - j.blk_begin);
+    if (j.block_major)
+        inv_body<NB, R, true>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
+                              b - j.blk_begin, C, D);
+    else
+        inv_body<NB, R, false>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
+                               b - j.blk_begin, C, D);
 }
 
 template <int NB, typename R>
@@ -247,7 +294,7 @@ hipError_t batch_launch(bool inverse, const FftJob *jobs, int n_jobs, int total_
     if (inverse)
         hipLaunchKernelGGL((inv_batch_kernel<NB, R>), dim3(total_blocks), dim3(kInvThreads), 0, s, jobs, n_jobs);
     else
-        hipLaunchKernelGGL((fwd_batch_kernel<NB, R>), dim3(total_blocks * kFwdChunks), dim3(FftShape<NB, R>::NT), 0, s,
+        hipLaunchKernelGGL((fwd_batch_kernel<NB, R>), dim3(total_blocks * kSpecChunks), dim3(FftShape<NB, R>::NT), 0, s,
                            jobs, n_jobs);
     return hipGetLastError();
 }
@@ -256,7 +303,7 @@ template <int NB, typename R>
 hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
                       int64_t n_slots, bool block_major, double scale, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks * kFwdChunks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
+    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks * kSpecChunks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
                        n_slots, (int)block_major, scale);
     return hipGetLastError();
 }

@@ -17,9 +17,27 @@ hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bo
                          void *scratch, size_t scratch_bytes, hipStream_t s);
 
 // ---- block FFTs (lgf_fft.hip) ----
-// Spectral workspaces hold spectrum value omega (of n_freq = (2nb)^2 (nb + 1))
-// of slot sl at omega * n_slots + sl (frequency-major: the block-pair MAC)
-// or at sl * n_freq + omega (block_major: the lattice MAC).
+// Spectral workspaces hold spectrum value omega = (kz N + ky) H + kx (of
+// n_freq = N^2 H, N = 2 nb, H = nb + 1) of slot sl at omega * n_slots + sl
+// (frequency-major: the block-pair MAC) or at sl * n_freq + spec_pos(omega)
+// (block-major: the lattice MAC).  Block-major spectra are stored in
+// kSpecChunks kx ranges of spec_chunk(N) (the last one shorter), each range
+// [kz][ky][kx - k0], the ranges the FFT workgroups of a block work on.
+constexpr int kSpecChunks = 3;
+__host__ __device__ inline int spec_chunk(int N) { return (N / 2 + 3) / 3; }   // ceil(H / 3)
+__host__ __device__ inline int spec_pos(int N, int kx, int ky, int kz) {
+    const int kc = spec_chunk(N), k0 = kx / kc * kc;
+    const int nk = kc < N / 2 + 1 - k0 ? kc : N / 2 + 1 - k0;
+    return N * N * k0 + (kz * N + ky) * nk + (kx - k0);
+}
+__host__ __device__ inline void spec_freq(int N, int p, int &kx, int &ky, int &kz) {
+    const int kc = spec_chunk(N), k0 = p / (N * N * kc) * kc;
+    const int nk = kc < N / 2 + 1 - k0 ? kc : N / 2 + 1 - k0;
+    const int r = p - N * N * k0;
+    kx = k0 + r % nk;
+    ky = (r / nk) % N;
+    kz = r / (nk * N);
+}
 // Forward: for each listed block i, read the nb^3 float64 values at
 // src + blk_off[i] (elements), multiply by `scale`, zero-pad to (2nb)^3,
 // r2c-transform and store the spectrum of slot[i] in Fhat.
@@ -139,8 +157,9 @@ int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (
 // lattice_yz (y and z DFTs, product, inverse z and y DFTs in H),
 // lattice_inv (inverse x DFTs into Uhat), or all three by lattice_conv.
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s);
-// worder: the n_freq block frequencies in the order lattice_yz takes them
-// (any permutation; reflection partners adjacent lets them share Khat in L2).
+// worder: the n_freq spectrum positions (spec_pos) in the order lattice_yz
+// takes them (any permutation; reflection partners adjacent lets them share
+// Khat in L2).
 hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, const int *worder, hipStream_t s);
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s);
 hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, const int *worder,

@@ -24,8 +24,10 @@
 // block pairs.
 //
 // Layouts (complex R, per component region):
-//   Fhat, Uhat [slot][omega] (block-major: the block FFTs stream whole
-//              spectra), slot = (z Ey + y) Ex + x over the box E;
+//   Fhat, Uhat [slot][p] (block-major: the block FFTs stream whole
+//              spectra; p = spec_pos(omega), chunk-major in kx), slot =
+//              (z Ey + y) Ex + x over the box E; the x kernels take p as
+//              an opaque index and H is indexed by it;
 //   H          [omega][kx][z][y]: the box after the x DFT (kx < Lx);
 //   Khat       [omega_r][kx][kz][ky] (real R), omega_r over the stored
 //              frequencies.
@@ -311,11 +313,12 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
 // waves 2-3 the odd half); each half runs its own copy of the line code
 // (yz_half), so no index or twiddle depends on the half at run time, and
 // the halves meet through LDS.
-// Frequencies are taken in the order worder[] (a permutation of the
-// n_freq block frequencies that puts the y/z reflections of a frequency
-// next to each other), and workgroups are renumbered so that consecutive
-// ones run on one XCD: the reflections share one stored Khat plane, which
-// is then read from HBM once and from that XCD's L2 for the others.
+// Frequencies are taken in the order worder[] (spectrum positions, a
+// permutation of the n_freq block frequencies that puts the y/z reflections
+// of a frequency next to each other), and workgroups are renumbered so that
+// consecutive ones run on one XCD: the reflections share one stored Khat
+// plane, which is then read from HBM once and from that XCD's L2 for the
+// others.
 template <typename R, int LY, int LZ>
 __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(4))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
                                                       const int *__restrict__ worder) {
@@ -344,12 +347,14 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         const int si = s0 + t;
         const bool live = si < n_slabs;
         const int wk = live ? si % per_c : 0;
-        const int w = worder[wk / g.lx], kx = wk % g.lx;
-        // omega = (kz N + ky) Hh + kx -> stored frequency (ky, kz in [0, N/2]) and reflections
+        const int p = worder[wk / g.lx], kx = wk % g.lx;
+        // spectrum position p -> block frequency (fx, fyv, fzv) -> stored
+        // frequency (ky, kz in [0, N/2]) and reflections
         const int N = g.N, Hh = N / 2 + 1;
-        const int fx = w % Hh, fyv = (w / Hh) % N, fzv = w / (Hh * N);
+        int fx, fyv, fzv;
+        spec_freq(N, p, fx, fyv, fzv);
         const int ry = fyv > N / 2, rz = fzv > N / 2;
-        hbase[t] = live ? (int64_t)(si / per_c) * g.hstride + ((int64_t)w * g.lx + kx) * g.hslab : -1;
+        hbase[t] = live ? (int64_t)(si / per_c) * g.hstride + ((int64_t)p * g.lx + kx) * g.hslab : -1;
         sinfo[t][0] = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
         sinfo[t][1] = kx | ry << 8 | rz << 9;
     }

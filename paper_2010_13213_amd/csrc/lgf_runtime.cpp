@@ -207,7 +207,22 @@ LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, in
     t->ly = ly;
     t->lz = lz;
     t->n_freq = oct->n_freq;
-    t->order = (const int *)oct->perm.ptr;
+    {
+        // the octant table's frequency order (reflection partners adjacent)
+        // as positions of the block-major spectra
+        const int N = 2 * nb, Hh = nb + 1;
+        std::vector<int> perm(t->n_freq), pos(t->n_freq);
+        hip_check(hipMemcpy(perm.data(), oct->perm.ptr, sizeof(int) * perm.size(), hipMemcpyDeviceToHost),
+                  "read frequency order");
+        for (int i = 0; i < t->n_freq; ++i) {
+            const int w = perm[i];
+            pos[i] = spec_pos(N, w % Hh, (w / Hh) % N, w / (Hh * N));
+        }
+        t->order_buf.alloc(ctx, sizeof(int) * pos.size(), "lattice frequency order");
+        hip_check(hipMemcpy(t->order_buf.ptr, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice),
+                  "upload lattice frequency order");
+        t->order = (const int *)t->order_buf.ptr;
+    }
     const size_t per_w = (size_t)lx * ly * lz;
     const size_t n_stored = (size_t)lattice_stored_freqs(2 * nb);
     t->data.alloc(ctx, (fp32 ? 4 : 8) * per_w * n_stored, "lattice spectra");

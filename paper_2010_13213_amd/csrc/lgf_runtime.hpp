@@ -83,7 +83,8 @@ struct LatSpec {
     int lx = 0, ly = 0, lz = 0;
     int n_freq = 0;
     DeviceBuffer data;
-    const int *order = nullptr;   // reflection-grouped frequency order (the octant table's perm)
+    DeviceBuffer order_buf;       // the octant table's reflection-grouped order, as spectrum positions
+    const int *order = nullptr;   // order_buf
 };
 
 // Tuning-table entry: the chosen MAC method ("pairs TYxTZ": the block-pair
