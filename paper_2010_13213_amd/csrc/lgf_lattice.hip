@@ -33,8 +33,8 @@
 //              frequencies.
 // Three kernels, each streaming its data once from HBM:
 //   lat_x_fwd  x lines of Fhat -> H (a lane pair per line; a workgroup takes
-//              8 frequencies x 16 (y, z) rows, so each slot's 8 frequencies
-//              are one 128-byte line);
+//              one 128-byte run of frequencies (8 in float64, 16 in float32)
+//              x 16 (y, z) rows);
 //   lat_yz     one (omega, kx) slab per 2 Ly lanes, in LDS: y DFT, z DFT,
 //              product with Khat, inverse z and y DFTs, in place in H (the
 //              two halves of a line on lanes of different waves, meeting
@@ -99,32 +99,35 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
     }
 }
 
-// Tile of the x kernels: kTW consecutive frequencies x kTQ consecutive (y, z)
-// rows q of one component, a lane pair per line (kXThreads threads); row
+// Tile of the x kernels: xtw<R> consecutive frequencies (one 128-byte run
+// per slot: 8 in float64, 16 in float32) x kTQ consecutive (y, z) rows q of
+// one component, a lane pair per line (xthreads<R> threads); row
 // rl = wl kTQ + ql.
-constexpr int kTW = 8, kTQ = 16, kXThreads = 2 * kTW * kTQ;
+template <typename R> constexpr int xtw = 128 / (int)sizeof(cplx<R>);
+constexpr int kTQ = 16;
+template <typename R> constexpr int xthreads = 2 * xtw<R> * kTQ;
 
 struct XTile {
     int c, w0, q0;
 };
-__device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
+template <int TW> __device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
     const int per_w = g.ey * g.ez;
-    const int wt = (g.n_freq + kTW - 1) / kTW, qt = (per_w + kTQ - 1) / kTQ;
-    return XTile{b / (wt * qt), (b % wt) * kTW, ((b / wt) % qt) * kTQ};
+    const int wt = (g.n_freq + TW - 1) / TW, qt = (per_w + kTQ - 1) / kTQ;
+    return XTile{b / (wt * qt), (b % wt) * TW, ((b / wt) % qt) * kTQ};
 }
 
 // x lines of Fhat -> H.  The tile's lines are staged through LDS: the loads
 // read each slot's kTW frequencies as one run, all issued before the first
 // is waited on.
 template <typename R, int LX>
-__global__ void __launch_bounds__(kXThreads) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
+__global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
                                                          cplx<R> *__restrict__ H) {
-    constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
+    constexpr int M = LX / 2, SP = M + 1, kTW = xtw<R>, kXThreads = xthreads<R>;   // rows padded against bank conflicts
     constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kXThreads - 1) / kXThreads;
     __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
     const int ex = g.ex, per_w = g.ey * g.ez;
-    const XTile tl = x_tile(g, blockIdx.x);
+    const XTile tl = x_tile<kTW>(g, blockIdx.x);
     const cplx<R> *Fc = F + (int64_t)tl.c * g.fstride;
     cplx<R> v[NI];
 #pragma unroll
@@ -397,14 +400,14 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
 // lat_x_fwd (staged through LDS so that each slot's kTW frequencies are
 // stored as one run).  Every lane reaches the exchange.
 template <typename R, int LX>
-__global__ void __launch_bounds__(kXThreads) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
+__global__ void __launch_bounds__(xthreads<R>) lat_x_inv(LatGeom g, const cplx<R> *__restrict__ H,
                                                          cplx<R> *__restrict__ U) {
-    constexpr int M = LX / 2, SP = M + 1;   // rows padded against bank conflicts
+    constexpr int M = LX / 2, SP = M + 1, kTW = xtw<R>, kXThreads = xthreads<R>;   // rows padded against bank conflicts
     constexpr int CELLS = kTW * kTQ * M, NI = (CELLS + kXThreads - 1) / kXThreads;
     __shared__ cplx<R> S[kTW * kTQ * SP];
     const int t = threadIdx.x;
     const int ex = g.ex, per_w = g.ey * g.ez;
-    const XTile tl = x_tile(g, blockIdx.x);
+    const XTile tl = x_tile<kTW>(g, blockIdx.x);
     const int rl = t >> 1, odd = t & 1;
     const int q = tl.q0 + rl % kTQ, w = tl.w0 + rl / kTQ;
     const bool on = q < per_w && w < g.n_freq;
@@ -532,16 +535,16 @@ template <typename F> hipError_t with_len(int L, F &&f) {
 }
 
 // workgroups of the x kernels: one per (component, frequency tile, row tile)
-unsigned x_tiles(const LatGeom &g) {
+template <typename R> unsigned x_tiles(const LatGeom &g) {
     const int per_w = g.ey * g.ez;
-    return (unsigned)((int64_t)g.nc * ((g.n_freq + kTW - 1) / kTW) * ((per_w + kTQ - 1) / kTQ));
+    return (unsigned)((int64_t)g.nc * ((g.n_freq + xtw<R> - 1) / xtw<R>) * ((per_w + kTQ - 1) / kTQ));
 }
 
 template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void *H, hipStream_t s) {
-    const unsigned blocks = x_tiles(g);
+    const unsigned blocks = x_tiles<R>(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
-        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(kXThreads), 0, s, g, (const cplx<R> *)F,
+        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)F,
                            (cplx<R> *)H);
         return hipGetLastError();
     });
@@ -563,10 +566,10 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
 }
 
 template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
-    const unsigned blocks = x_tiles(g);
+    const unsigned blocks = x_tiles<R>(g);
     return with_len(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
-        hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(kXThreads), 0, s, g, (const cplx<R> *)H,
+        hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)H,
                            (cplx<R> *)U);
         return hipGetLastError();
     });

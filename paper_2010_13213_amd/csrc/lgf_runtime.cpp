@@ -950,8 +950,9 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
         throw Failure(LGF_E_INVALID, "internal: component count outside the spectral workspace");
     // empty slots of Fhat must read as zero; the forward FFT writes only
     // occupied slots, so clear when another slot map used the buffer last
+    // (a convolution with a source in every slot overwrites all it reads)
     if (plan->fhat_conv != &c) {
-        hip_check(zero_fill(plan->Fhat.ptr, plan->Fhat.bytes, s), "clear Fhat");
+        if (!fhat_full(c)) hip_check(zero_fill(plan->Fhat.ptr, plan->Fhat.bytes, s), "clear Fhat");
         plan->fhat_conv = &c;
     }
     for (int k = 0; k < nc; ++k) {

@@ -195,6 +195,9 @@ struct LevelSched {
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
 LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz);
 LatGeom lat_geom(const Conv &c, int nc);
+// every slot of the convolution holds a source block: its forward FFTs
+// write the whole spectral region it reads
+inline bool fhat_full(const Conv &c) { return (int64_t)c.n_src == c.n_slots; }
 SmacGeom conv_geom(const Conv &c, const SubConv &p);
 
 }  // namespace lgf

@@ -402,7 +402,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     if (calls.empty()) return;
     for (const ConvCall &k : calls)
         if (k.p->fhat_conv != k.c) {
-            hip_check(zero_fill(k.p->Fhat.ptr, k.p->Fhat.bytes, s), "clear Fhat");
+            if (!fhat_full(*k.c)) hip_check(zero_fill(k.p->Fhat.ptr, k.p->Fhat.bytes, s), "clear Fhat");
             k.p->fhat_conv = k.c;
         }
     const int nb = calls[0].p->nb;
