@@ -90,12 +90,24 @@ __global__ void __launch_bounds__(256) residual_kernel(RefGeom g, const int *__r
         if (sh >= 0 && depth[(size_t)sh * NB3 + li] < 2) return 0.0;
         return ut[(size_t)t * NB3 + li];
     };
+    // w at local cell j of this block (no block lookup)
+    auto w_own = [&](int j) -> double {
+        if (sh_b >= 0 && depth[(size_t)sh_b * NB3 + j] < 2) return 0.0;
+        return ut[(size_t)b * NB3 + j];
+    };
     for (int i = threadIdx.x; i < NB3; i += 256) {
-        const int x = Bx * NB + i % NB, y = By * NB + (i / NB) % NB, z = Bz * NB + i / (NB * NB);
+        const int lx = i % NB, ly = (i / NB) % NB, lz = i / (NB * NB);
+        const int x = Bx * NB + lx, y = By * NB + ly, z = Bz * NB + lz;
         const int d = sh_b >= 0 ? depth[(size_t)sh_b * NB3 + i] : 3;
         const double wc = d >= 2 ? ut[(size_t)b * NB3 + i] : 0.0;
-        const double lap = w_at(x + 1, y, z) + w_at(x - 1, y, z) + w_at(x, y + 1, z) + w_at(x, y - 1, z) +
-                           w_at(x, y, z + 1) + w_at(x, y, z - 1) - 6.0 * wc;
+        // neighbours inside the block read it directly; across a face, by lookup
+        const double wxp = lx + 1 < NB ? w_own(i + 1) : w_at(x + 1, y, z);
+        const double wxm = lx > 0 ? w_own(i - 1) : w_at(x - 1, y, z);
+        const double wyp = ly + 1 < NB ? w_own(i + NB) : w_at(x, y + 1, z);
+        const double wym = ly > 0 ? w_own(i - NB) : w_at(x, y - 1, z);
+        const double wzp = lz + 1 < NB ? w_own(i + NB * NB) : w_at(x, y, z + 1);
+        const double wzm = lz > 0 ? w_own(i - NB * NB) : w_at(x, y, z - 1);
+        const double lap = wxp + wxm + wyp + wym + wzp + wzm - 6.0 * wc;
         const double gv = gofs[b] >= 0 ? src[gofs[b] + i] : 0.0;
         const double r = gv - idx2 * lap;
         double *dp = dst + dofs[b] + i;
