@@ -42,9 +42,10 @@ template <int NB, typename R> struct FftShape {
     static constexpr int H = NB + 1;            // r2c length along x
     static constexpr int HL = NB * NB;          // lanes per half
     static constexpr int NT = 2 * HL;           // threads per block
-    // kx in kSpecChunks chunks of KC (spec_chunk): one forward workgroup
-    // each; the inverse walks them in turn
+    // kx in kSpecChunks chunks of KC (= spec_chunk(N)): one forward
+    // workgroup each; the inverse walks them in turn
     static constexpr int KC = (H + 2) / 3;
+    static_assert(kSpecChunks == 3, "KC is a third of the kx range");
     static constexpr int FA_ELEMS = NB * NB * KC;   // [z][y][kxl]
     static constexpr int FB_ELEMS = NB * N * KC;    // [z][ky][kxl]
 };
@@ -58,8 +59,9 @@ template <typename R, int N, int M> __device__ __forceinline__ void odd_twiddle(
     for (int n = 1; n < M; ++n) a[n] = cmul(a[n], twiddle<R, N, false>(n));
 }
 
-// Spectrum value omega of slot sl at Fhat[omega * ws + sl * ss]:
-// frequency-major (ws = n_slots, ss = 1) or block-major (ws = 1, ss = n_freq).
+// Spectrum position p of slot sl at Fhat[p * ws + sl * ss]: frequency-major
+// (p = omega, ws = n_slots, ss = 1) or block-major (p = spec_pos(omega),
+// ws = 1, ss = n_freq).
 template <int NB> constexpr int64_t fft_freqs = 4 * NB * NB * (NB + 1);   // (2nb)^2 (nb + 1)
 
 // Forward transform of block b, kx chunk `chunk` (kx in [chunk KC, ...)):

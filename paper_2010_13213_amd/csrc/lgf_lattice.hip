@@ -28,7 +28,8 @@
 //              spectra; p = spec_pos(omega), chunk-major in kx), slot =
 //              (z Ey + y) Ex + x over the box E; the x kernels take p as
 //              an opaque index and H is indexed by it;
-//   H          [omega][kx][z][y]: the box after the x DFT (kx < Lx);
+//   H          [p][kx][z][y]: the box after the x DFT (kx < Lx), slabs
+//              hslab apart (padded against power-of-two strides);
 //   Khat       [omega_r][kx][kz][ky] (real R), omega_r over the stored
 //              frequencies.
 // Three kernels, each streaming its data once from HBM:
