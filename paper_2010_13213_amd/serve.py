@@ -159,7 +159,7 @@ def main():
     ctx = lgf.Context(0)
     reqs = inputs.served_stream(args.requests)
     pool = PlanPool(ctx)
-    serve(ctx, reqs[:32], None, pool=pool)                 # warm plans and spectra
+    serve(ctx, reqs, None, pool=pool)                     # create the resident plans and spectra
     cap = serve(ctx, reqs, None, pool=pool)               # all at t = 0: capacity
     rows = [dict(cap, label="all at once")]
     print(json.dumps({k: v for k, v in rows[0].items()}), flush=True)
