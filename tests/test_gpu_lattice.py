@@ -201,3 +201,31 @@ def test_box_longer_than_16_blocks_uses_pairs(lat_ctx):
     u = gpu_solve(lat_ctx, _problem(blocks, nb, f))[0]
     idx = rng.choice(len(c), 2000, replace=False)
     assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 1.0)) < TOL64
+
+
+def test_batch_mixing_pair_and_lattice_plans_equals_alone_bitwise():
+    # one lgf_solve_batch call over plans whose convolutions use different
+    # spectral layouts (block pairs: frequency-major; lattice: block-major):
+    # the batched block FFTs take the layout per job
+    import torch
+    from paper_2010_13213_amd import lgf
+    ctx = lgf.Context(0)
+    try:
+        probs = [inputs.gaussian_box(n_blk=4, nb=8), inputs.gaussian_box(n_blk=6, nb=8),
+                 inputs.gaussian_box(n_blk=3, nb=8), inputs.gaussian_box(n_blk=5, nb=8)]
+        setup = [("pairs", "fp64"), ("lattice", "fp64"), ("pairs", "fp32_refine"), ("lattice", "fp32_refine")]
+        plans = []
+        for p, (method, precision) in zip(probs, setup):
+            ctx.set_mac_method(method)
+            plans.append(lgf.Plan.for_problem(ctx, p, precision))
+        fs = [torch.from_numpy(p.flat_source()).cuda() for p in probs]
+        alone = [pl.solve(f).cpu().numpy() for pl, f in zip(plans, fs)]
+        us = [torch.empty_like(f) for f in fs]
+        lgf.solve_batch(ctx, plans, fs, us)
+        torch.cuda.synchronize()
+        for i, (a, u) in enumerate(zip(alone, us)):
+            assert np.array_equal(a, u.cpu().numpy()), setup[i]
+        for pl in plans:
+            pl.close()
+    finally:
+        ctx.close()
