@@ -120,13 +120,12 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
         if (half) odd_twiddle<R, N, M>(a);
         fft_reg<R, M, false>(a);
         const int kx = k0 + kxl;
+        // position of kz = half, and the step between kz and kz + 2:
+        // block-major the chunk's run [kz][ky][kxl] (spec_pos), frequency-major omega
+        cplx<R> *o = Fb + (BM ? (int64_t)N * N * k0 + (half * N + ky) * nk + kxl : ((int64_t)half * N + ky) * H + kx) * ws;
+        const int64_t step = (BM ? 2 * N * nk : 2 * N * H) * ws;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            // block-major: the chunk's run [kz][ky][kxl] (spec_pos); frequency-major: omega
-            const int kz = 2 * m + half;
-            const int64_t pos = BM ? (int64_t)N * N * k0 + (kz * N + ky) * nk + kxl : ((int64_t)kz * N + ky) * H + kx;
-            Fb[pos * ws] = a[m];
-        }
+        for (int m = 0; m < M; ++m) o[m * step] = a[m];
     }
 }
 
