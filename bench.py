@@ -326,11 +326,21 @@ def main():
         bytes_yz = n_freq * 2 * 16 * h + n_stored * 8 * L[0] * L[1] * L[2]
         yz_ms = st["lat_yz"][0] / st["lat_yz"][1]
         achieved = bytes_yz / (yz_ms * 1e-3) / 1e9
+        # the whole convolution (every kernel of a solve, algorithmic bytes):
+        # block FFTs read/write the field (8 B per cell) and the spectra
+        # (16 B per frequency per block), the lattice x passes read/write
+        # Fhat/Uhat and H once each
+        n_slots = ext[0] * ext[1] * ext[2]
+        bytes_fft = n_blocks * (nb ** 3 * 8 + n_freq * 16)
+        bytes_x = n_freq * 16 * (n_slots + h)
+        solve_bytes = 2 * bytes_fft + 2 * bytes_x + bytes_yz
         roof = {"bound": "hbm", "kernel": KERNELS["lat_yz"][0], "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("lat_yz"),
                 "traffic_unit": "bytes per launch (HBM, counters)", "algorithmic_bytes_per_launch": bytes_yz,
                 "avg_launch_ms": yz_ms, "lattice_lengths": L,
-                "mac_stage_ms_per_step": sum(st[k][0] for k in ("lat_x", "lat_yz", "lat_xinv")) / args.steps}
+                "mac_stage_ms_per_step": sum(st[k][0] for k in ("lat_x", "lat_yz", "lat_xinv")) / args.steps,
+                "solve_algorithmic_bytes": solve_bytes,
+                "solve_frac": solve_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
     else:
         pairs = n_blocks * n_blocks
         flops_mac = 8.0 * pairs * n_freq                       # one complex MAC = 8 flops
