@@ -1,10 +1,10 @@
 // Device-side building blocks shared by the LGF kernels (gfx950).
 //
 // * cplx<R>: a 2-vector complex number in float or double.
-// * fft_reg<N, INV>: an in-register radix-2 FFT of length N (2 to 32) on a
+// * fft_reg<N, INV>: an in-register radix-2 FFT of length N (2 to 64) on a
 //   per-thread array; all indices are compile-time so the array lives in
 //   VGPRs.  Forward uses exp(-2 pi i k / N), inverse exp(+2 pi i k / N), no
-//   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 32),
+//   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 64),
 //   folded into the unrolled butterflies.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -40,36 +40,54 @@ template <typename R> __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<
     return acc;
 }
 
-// exp(-2 pi i k / 32), k = 0..15, as (cos, -sin) pairs.
-constexpr double kTw32[16][2] = {
+// exp(-2 pi i k / 64), k = 0..31, as (cos, -sin) pairs (the even entries are
+// the 32nds of a turn).
+constexpr double kTw64[32][2] = {
     {1.0, 0.0},
+    {9.95184726672196928732e-01, -9.80171403295606036288e-02},
     {9.80785280403230449126e-1, -1.95090322016128267848e-1},
+    {9.56940335732208824382e-01, -2.90284677254462331053e-01},
     {9.23879532511286756128e-1, -3.82683432365089771728e-1},
+    {8.81921264348355049556e-01, -4.71396736825997642040e-01},
     {8.31469612302545237079e-1, -5.55570233019602224743e-1},
+    {7.73010453362736993377e-01, -6.34393284163645487794e-01},
     {7.07106781186547524401e-1, -7.07106781186547524401e-1},
+    {6.34393284163645487794e-01, -7.73010453362736993377e-01},
     {5.55570233019602224743e-1, -8.31469612302545237079e-1},
+    {4.71396736825997808573e-01, -8.81921264348354938534e-01},
     {3.82683432365089771728e-1, -9.23879532511286756128e-1},
+    {2.90284677254462331053e-01, -9.56940335732208935404e-01},
     {1.95090322016128267848e-1, -9.80785280403230449126e-1},
+    {9.80171403295607701622e-02, -9.95184726672196817709e-01},
     {0.0, -1.0},
+    {-9.80171403295606452621e-02, -9.95184726672196928732e-01},
     {-1.95090322016128267848e-1, -9.80785280403230449126e-1},
+    {-2.90284677254462164520e-01, -9.56940335732208935404e-01},
     {-3.82683432365089771728e-1, -9.23879532511286756128e-1},
+    {-4.71396736825997697551e-01, -8.81921264348355049556e-01},
     {-5.55570233019602224743e-1, -8.31469612302545237079e-1},
+    {-6.34393284163645376772e-01, -7.73010453362737104399e-01},
     {-7.07106781186547524401e-1, -7.07106781186547524401e-1},
+    {-7.73010453362736993377e-01, -6.34393284163645487794e-01},
     {-8.31469612302545237079e-1, -5.55570233019602224743e-1},
+    {-8.81921264348354938534e-01, -4.71396736825997864084e-01},
     {-9.23879532511286756128e-1, -3.82683432365089771728e-1},
+    {-9.56940335732208824382e-01, -2.90284677254462386564e-01},
     {-9.80785280403230449126e-1, -1.95090322016128267848e-1},
+    {-9.95184726672196817709e-01, -9.80171403295608256734e-02},
 };
 
 template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle(int k) {
-    // exp(-+2 pi i k / N) = table entry k * (32 / N)
-    const int j = k * (32 / N);
-    const R c = (R)kTw32[j][0];
-    const R s = (R)kTw32[j][1];
+    // exp(-+2 pi i k / N) = table entry k * (64 / N), k < N / 2
+    static_assert(N >= 2 && N <= 64 && 64 % N == 0, "twiddle length");
+    const int j = k * (64 / N);
+    const R c = (R)kTw64[j][0];
+    const R s = (R)kTw64[j][1];
     return INV ? cmake(c, -s) : cmake(c, s);
 }
 
 template <int N> struct bitrev {
-    static constexpr int L = (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : (N == 4) ? 2 : 1;
+    static constexpr int L = (N == 64) ? 6 : (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : (N == 4) ? 2 : 1;
     static __host__ __device__ constexpr int of(int i) {
         int r = 0;
         for (int b = 0; b < L; ++b)

@@ -181,9 +181,9 @@ constexpr int kInvThreads = 256;
 
 // Re(v exp(+2 pi i j / N)), j a compile-time value after unrolling
 template <typename R, int N> __device__ __forceinline__ R re_rot(cplx<R> v, int j) {
-    const int q = (j % N) * (32 / N);   // in 32nds of a turn
-    const R c = q < 16 ? (R)kTw32[q][0] : -(R)kTw32[q - 16][0];
-    const R s = q < 16 ? -(R)kTw32[q][1] : (R)kTw32[q - 16][1];   // sin(2 pi q / 32)
+    const int q = (j % N) * (64 / N);   // in 64ths of a turn
+    const R c = q < 32 ? (R)kTw64[q][0] : -(R)kTw64[q - 32][0];
+    const R s = q < 32 ? -(R)kTw64[q][1] : (R)kTw64[q - 32][1];   // sin(2 pi q / 64)
     return v.x * c - v.y * s;
 }
 

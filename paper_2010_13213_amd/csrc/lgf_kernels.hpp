@@ -125,7 +125,7 @@ hipError_t smac_launch(const SmacGeom &g, bool fp32, bool sparse, int nc, const 
 
 // ---- spectral MAC by an FFT over the block lattice (lgf_lattice.hip) ----
 // Box E = (ex, ey, ez) blocks, lattice DFT lengths (lx, ly, lz), each a
-// compiled length (4, 8, 16, 32) with 2 e <= l; N = 2 nb is the block FFT
+// compiled length (4, 8, 16, 32; lz also 64) with 2 e <= l; N = 2 nb is the block FFT
 // edge (n_freq = N^2 (N/2 + 1)).  Fhat / Uhat block-major: [c][slot][omega]
 // (slot = (z ey + y) ex + x, n_slots = ex ey ez), components fstride
 // (>= n_freq n_slots) elements apart; H:
@@ -149,8 +149,9 @@ struct LatSpecGeom {
     int lx, ly, lz;
     int XD, YD, ZD;
 };
-bool lattice_len_ok(int L);
-int lattice_len(int extent);   // smallest length L >= max(4, 2 extent - 1) (compiled up to 32)
+bool lattice_len_ok(int L);    // compiled x and y lengths: 4, 8, 16, 32
+bool lattice_zlen_ok(int L);   // compiled z lengths: also 64
+int lattice_len(int extent);   // smallest length L >= max(4, 2 extent - 1)
 int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (N/2 + 1)^3
 // Uhat[c] = the lattice convolution of Fhat[c] with the kernel whose
 // spectrum is Khat, for the nc components: lattice_fwd (x DFTs into H),

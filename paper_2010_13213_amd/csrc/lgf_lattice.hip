@@ -323,8 +323,10 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
 // consecutive ones run on one XCD: the reflections share one stored Khat
 // plane, which is then read from HBM once and from that XCD's L2 for the
 // others.
+// Occupancy: 4 workgroups per CU up to LZ = 32; at LZ = 64 the z lines
+// of a lane take twice the registers and Q twice the LDS, so 2.
 template <typename R, int LY, int LZ>
-__global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(4))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
+__global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(LZ <= 32 ? 4 : 2))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
                                                       const int *__restrict__ worder) {
     constexpr int HL = kLatThreads / 2;                 // lanes per half
     constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
@@ -535,6 +537,13 @@ template <typename F> hipError_t with_len(int L, F &&f) {
     }
 }
 
+// z lengths: also 64 (boxes up to 32 blocks along z; the z lines are the
+// only ones held whole per lane pair, the x and y lengths stay <= 32)
+template <typename F> hipError_t with_zlen(int L, F &&f) {
+    if (L == 64) return f(std::integral_constant<int, 64>());
+    return with_len(L, static_cast<F &&>(f));
+}
+
 // workgroups of the x kernels: one per (component, frequency tile, row tile)
 template <typename R> unsigned x_tiles(const LatGeom &g) {
     const int per_w = g.ey * g.ez;
@@ -556,7 +565,7 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
     const int64_t slabs = (int64_t)g.nc * g.n_freq * g.lx;
     if (slabs >= INT32_MAX) return hipErrorInvalidValue;   // the kernel counts slabs in 32 bits
     return with_len(g.ly, [&](auto ly) {
-        return with_len(g.lz, [&](auto lz) {
+        return with_zlen(g.lz, [&](auto lz) {
             constexpr int LY = decltype(ly)::value, LZ = decltype(lz)::value;
             constexpr int SL = kLatThreads / (2 * LY);
             hipLaunchKernelGGL((lat_yz<R, LY, LZ>), dim3((unsigned)((slabs + SL - 1) / SL)), dim3(kLatThreads), 0,
@@ -594,7 +603,7 @@ template <typename R> hipError_t spec_impl(const LatSpecGeom &sg, const void *T,
         });
         if (e != hipSuccess) return e;
         const int64_t cols = (int64_t)nw * sg.lx * sg.ly;
-        e = with_len(sg.lz, [&](auto lz) {
+        e = with_zlen(sg.lz, [&](auto lz) {
             constexpr int LZ = decltype(lz)::value;
             hipLaunchKernelGGL((latspec_z<R, LZ>), dim3((unsigned)((cols + kLatThreads - 1) / kLatThreads)),
                                dim3(kLatThreads), 0, s, sg, (const cplx<R> *)scratch, (R *)Khat, (int)w0, nw, scale);
@@ -609,6 +618,8 @@ template <typename R> hipError_t spec_impl(const LatSpecGeom &sg, const void *T,
 
 bool lattice_len_ok(int L) { return L == 4 || L == 8 || L == 16 || L == 32; }
 
+bool lattice_zlen_ok(int L) { return lattice_len_ok(L) || L == 64; }
+
 int lattice_len(int extent) {
     int L = 4;
     while (L < 2 * extent - 1) L *= 2;
@@ -618,7 +629,7 @@ int lattice_len(int extent) {
 int lattice_stored_freqs(int N) { return (N / 2 + 1) * (N / 2 + 1) * (N / 2 + 1); }
 
 static bool geom_ok(const LatGeom &g) {
-    return lattice_len_ok(g.lx) && lattice_len_ok(g.ly) && lattice_len_ok(g.lz) && g.nc >= 1 && g.ex >= 1 &&
+    return lattice_len_ok(g.lx) && lattice_len_ok(g.ly) && lattice_zlen_ok(g.lz) && g.nc >= 1 && g.ex >= 1 &&
            g.ey >= 1 && g.ez >= 1 && 2 * g.ex <= g.lx && 2 * g.ey <= g.ly && 2 * g.ez <= g.lz && g.N >= 2 &&
            g.n_freq == g.N * g.N * (g.N / 2 + 1) && g.n_slots == (int64_t)g.ex * g.ey * g.ez &&
            g.fstride >= (int64_t)g.n_freq * g.n_slots &&
@@ -650,7 +661,7 @@ hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, 
 
 hipError_t lattice_spectra(const LatSpecGeom &sg, bool fp32, const void *octant, void *Khat, void *scratch,
                            size_t scratch_bytes, hipStream_t s) {
-    if (!lattice_len_ok(sg.lx) || !lattice_len_ok(sg.ly) || !lattice_len_ok(sg.lz) || sg.XD < sg.lx / 2 ||
+    if (!lattice_len_ok(sg.lx) || !lattice_len_ok(sg.ly) || !lattice_zlen_ok(sg.lz) || sg.XD < sg.lx / 2 ||
         sg.YD < sg.ly / 2 || sg.ZD < sg.lz / 2)
         return hipErrorInvalidValue;
     return fp32 ? spec_impl<float>(sg, octant, Khat, scratch, scratch_bytes, s)

@@ -277,9 +277,8 @@ static bool lattice_feasible(const std::vector<Blk> &src, const std::vector<Blk>
     if (src.empty() || tgt.empty()) return false;
     int lo[3], ext[3];
     box_extent(src, tgt, lo, ext);
-    for (int a = 0; a < 3; ++a)
-        if (!lattice_len_ok(lattice_len(ext[a]))) return false;
-    return true;
+    return lattice_len_ok(lattice_len(ext[0])) && lattice_len_ok(lattice_len(ext[1])) &&
+           lattice_zlen_ok(lattice_len(ext[2]));
 }
 
 // A convolution whose MAC is the lattice FFT: slots over the tight bounding
@@ -613,7 +612,7 @@ static double model_lattice_ms(int nb, bool fp32, int nc, const std::vector<Blk>
 
 // Build a convolution with the MAC method of the context's tuning table for
 // its shape: block pairs with one of the compiled tile shapes, or (boxes up
-// to 16 blocks per axis) the lattice FFT.  With autotuning on and no entry
+// to 16 blocks along x and y, 32 along z) the lattice FFT.  With autotuning on and no entry
 // yet, every candidate is built and timed on this convolution's own
 // geometry; the fastest is recorded if it beats the default (pairs with the
 // first tile shape) by more than the 3% that repeated timings of one

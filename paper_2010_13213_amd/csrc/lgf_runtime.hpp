@@ -141,7 +141,8 @@ struct SubConv {
 
 // One blockwise LGF convolution on a level (sources -> targets).  The
 // spectral MAC runs either as block pairs (parts, below) or, for boxes of at
-// most 16 blocks per axis, as an FFT over the block lattice (method 1).
+// most 16 blocks along x and y and 32 along z, as an FFT over the block
+// lattice (method 1).
 constexpr int kMethodPairs = 0, kMethodLattice = 1;
 struct Conv {
     int method = kMethodPairs;

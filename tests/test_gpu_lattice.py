@@ -59,7 +59,7 @@ def _box(ex, ey, ez, lo=(0, 0, 0)):
 @pytest.mark.parametrize("ext,nb,dx", [((1, 1, 1), 8, 1.0), ((2, 3, 1), 8, 0.5), ((4, 4, 4), 8, 1.0),
                                        ((5, 7, 3), 8, 0.3), ((16, 2, 2), 8, 1.0), ((3, 2, 9), 16, 0.25)])
 def test_lattice_boxes_full_parity(lat_ctx, ext, nb, dx):
-    """Every compiled DFT length (4, 8, 16, 32) along every axis, ragged
+    """Every DFT length up to 32 (4, 8, 16, 32) along every axis, ragged
     extents, single blocks and one-block-thick boxes."""
     rng = np.random.default_rng(sum(ext) * 7 + nb)
     blocks = _box(*ext, lo=(-3, 5, 2))
@@ -73,6 +73,21 @@ def test_lattice_boxes_full_parity(lat_ctx, ext, nb, dx):
         idx = rng.choice(len(c), 3000, replace=False)
         ref = direct.direct_sum(c, f, c[idx], dx)
         assert rel_l2(u[idx], ref) < TOL64
+
+
+@pytest.mark.parametrize("ext,nb,precision,tol", [((2, 2, 20), 8, "fp64", TOL64), ((3, 3, 18), 16, "fp64", TOL64),
+                                                   ((2, 3, 32), 8, "fp32_refine", TOLMIX),
+                                                   ((5, 6, 24), 8, "fp64", TOL64), ((9, 9, 17), 8, "fp64", TOL64)])
+def test_lattice_long_z_boxes_sampled(lat_ctx, ext, nb, precision, tol):
+    """z extents 17..32 take the z DFT length 64 (x and y stay <= 32), with
+    y lengths 4, 8, 16 and 32."""
+    rng = np.random.default_rng(sum(ext) * 11 + nb)
+    blocks = _box(*ext, lo=(4, -2, -7))
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    u = gpu_solve(lat_ctx, _problem(blocks, nb, f, 0.6), precision)[0]
+    idx = np.concatenate([rng.choice(len(c), 1500, replace=False), [0, len(c) - 1]])
+    assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 0.6)) < tol
 
 
 @pytest.mark.parametrize("seed", [0, 1])
