@@ -85,9 +85,37 @@ def test_lattice_long_z_boxes_sampled(lat_ctx, ext, nb, precision, tol):
     blocks = _box(*ext, lo=(4, -2, -7))
     c = inputs.cell_coords(blocks, nb)
     f = rng.standard_normal(len(c))
-    u = gpu_solve(lat_ctx, _problem(blocks, nb, f, 0.6), precision)[0]
+    lat_ctx.set_timing(True)
+    lat_ctx.stage_times()
+    try:
+        u = gpu_solve(lat_ctx, _problem(blocks, nb, f, 0.6), precision)[0]
+        st = lat_ctx.stage_times()
+    finally:
+        lat_ctx.set_timing(False)
+    # every convolution ran on the lattice, none on block pairs
+    assert st["lat_yz"][1] > 0 and st["smac"][1] == 0, st
     idx = np.concatenate([rng.choice(len(c), 1500, replace=False), [0, len(c) - 1]])
     assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 0.6)) < tol
+
+
+def test_lattice_z_extent_33_takes_block_pairs(lat_ctx):
+    """Past 32 blocks along z there is no compiled lattice length: the
+    lattice-only setting falls back to block pairs, still exact."""
+    rng = np.random.default_rng(77)
+    nb = 8
+    blocks = _box(2, 2, 33, lo=(0, 0, -16))
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    lat_ctx.set_timing(True)
+    lat_ctx.stage_times()
+    try:
+        u = gpu_solve(lat_ctx, _problem(blocks, nb, f, 0.6))[0]
+        st = lat_ctx.stage_times()
+    finally:
+        lat_ctx.set_timing(False)
+    assert st["lat_yz"][1] == 0 and st["smac"][1] > 0, st
+    idx = rng.choice(len(c), 1500, replace=False)
+    assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 0.6)) < TOL64
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -207,13 +235,20 @@ def test_lattice_graph_replays_equal_eager(lat_ctx):
     plan.close()
 
 
-def test_box_longer_than_16_blocks_uses_pairs(lat_ctx):
+def test_box_longer_than_16_blocks_along_x_uses_pairs(lat_ctx):
     nb = 8
     blocks = _box(17, 2, 1)
     rng = np.random.default_rng(12)
     c = inputs.cell_coords(blocks, nb)
     f = rng.standard_normal(len(c))
-    u = gpu_solve(lat_ctx, _problem(blocks, nb, f))[0]
+    lat_ctx.set_timing(True)
+    lat_ctx.stage_times()
+    try:
+        u = gpu_solve(lat_ctx, _problem(blocks, nb, f))[0]
+        st = lat_ctx.stage_times()
+    finally:
+        lat_ctx.set_timing(False)
+    assert st["lat_yz"][1] == 0 and st["smac"][1] > 0, st
     idx = rng.choice(len(c), 2000, replace=False)
     assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 1.0)) < TOL64
 
