@@ -16,6 +16,17 @@ template <typename R> struct alignas(2 * sizeof(R)) cplx {
     R x, y;
 };
 
+// Streaming store of one complex value (non-temporal: the line is not kept
+// in the caches), for outputs far larger than L2 that the next kernel reads
+// back from HBM anyway.
+template <typename R> __device__ __forceinline__ void cstore_nt(cplx<R> *p, cplx<R> v) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
+}
+
 template <typename R> __device__ __forceinline__ cplx<R> cmake(R a, R b) {
     cplx<R> c;
     c.x = a;

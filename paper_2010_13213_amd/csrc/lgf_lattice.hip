@@ -389,13 +389,13 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
     // 2-4, each wave in its half's copy (the same barriers in both)
     if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
     else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
-    // 5. store the slabs back
+    // 5. store the slabs back (streaming stores: lat_x_inv reads them from HBM)
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         const int e = t + i * kLatThreads;
         const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
         const int64_t hb = e < CELLS ? hbase[sl] : -1;
-        if (hb >= 0 && y < ey && z < ez) H[hb + z * ey + y] = P[(sl * MZ + z) * PY + y];
+        if (hb >= 0 && y < ey && z < ez) cstore_nt(&H[hb + z * ey + y], P[(sl * MZ + z) * PY + y]);
     }
 }
 
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_inv(LatGeom g, const cplx<R
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         const int q2 = tl.q0 + ql, w2 = tl.w0 + wl;
         if (e < CELLS && x < ex && q2 < per_w && w2 < g.n_freq)
-            Uc[(int64_t)(q2 * ex + x) * g.n_freq + w2] = S[(wl * kTQ + ql) * SP + x];
+            cstore_nt(&Uc[(int64_t)(q2 * ex + x) * g.n_freq + w2], S[(wl * kTQ + ql) * SP + x]);
     }
 }
 
