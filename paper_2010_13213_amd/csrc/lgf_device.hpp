@@ -27,6 +27,16 @@ template <typename R> __device__ __forceinline__ void cstore_nt(cplx<R> *p, cplx
     __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
 }
 
+// Streaming load of one complex value, for data that is read exactly once.
+template <typename R> __device__ __forceinline__ cplx<R> cload_nt(const cplx<R> *p) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    cplx<R> c;
+    c.x = t.x;
+    c.y = t.y;
+    return c;
+}
+
 template <typename R> __device__ __forceinline__ cplx<R> cmake(R a, R b) {
     cplx<R> c;
     c.x = a;

@@ -125,7 +125,12 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
         cplx<R> *o = Fb + (BM ? (int64_t)N * N * k0 + (half * N + ky) * nk + kxl : ((int64_t)half * N + ky) * H + kx) * ws;
         const int64_t step = (BM ? 2 * N * nk : 2 * N * H) * ws;
 #pragma unroll
-        for (int m = 0; m < M; ++m) o[m * step] = a[m];
+        for (int m = 0; m < M; ++m) {
+            // block-major spectra go to the lattice x pass, which reads them from HBM;
+            // the frequency-major ones are re-read by the pair MAC
+            if constexpr (BM) cstore_nt(&o[m * step], a[m]);
+            else o[m * step] = a[m];
+        }
     }
 }
 

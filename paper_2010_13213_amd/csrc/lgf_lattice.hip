@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         const int q = tl.q0 + ql, w = tl.w0 + wl;
         const bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
-        const cplx<R> y = Fc[ok ? (int64_t)(q * ex + x) * g.n_freq + w : 0];
+        const cplx<R> y = cload_nt(&Fc[ok ? (int64_t)(q * ex + x) * g.n_freq + w : 0]);
         v[i] = csel(ok, y, czero<R>());
     }
 #pragma unroll
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
         const int64_t hb = e < CELLS ? hbase[sl] : -1;
         const bool ok = hb >= 0 && y < ey && z < ez;
-        const cplx<R> x = H[ok ? hb + z * ey + y : 0];
+        const cplx<R> x = cload_nt(&H[ok ? hb + z * ey + y : 0]);
         v[i] = csel(ok, x, czero<R>());
     }
 #pragma unroll
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_inv(LatGeom g, const cplx<R
     const cplx<R> *in = H + (int64_t)tl.c * g.hstride + (on ? (int64_t)w * LX * g.hslab + q : 0);
     cplx<R> a[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) a[m] = in[(2 * m + odd) * g.hslab];
+    for (int m = 0; m < M; ++m) a[m] = cload_nt(&in[(2 * m + odd) * g.hslab]);
     cplx<R> out[LX / 4];
     pair_inv<R, LX>(a, odd, out);
 #pragma unroll
