@@ -221,7 +221,8 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
             for (int kz = 0; kz < N; ++kz) {
                 const int64_t pos =
                     BM ? (int64_t)N * N * k0 + (kz * N + ky) * nk + kxl : ((int64_t)kz * N + ky) * H + k0 + kxl;
-                a[kz] = Ub[pos * ws];
+                if constexpr (BM) a[kz] = cload_nt(&Ub[pos * ws]);
+                else a[kz] = Ub[pos * ws];
             }
             fft_reg<R, N, true>(a);
 #pragma unroll
