@@ -73,7 +73,11 @@ class Box:
         return Box(cells.min(axis=0) - margin, cells.max(axis=0) + 1 + margin)
 
     def idx(self, cells):
-        c = np.asarray(cells) - self.lo
+        """Array indices of lattice cells; every cell must lie in the box
+        (a negative index would otherwise wrap around silently)."""
+        c = np.asarray(cells).reshape(-1, 3) - self.lo
+        if len(c) and (c.min() < 0 or np.any(c.max(axis=0) >= self.hi - self.lo)):
+            raise IndexError("cells outside the box [%s, %s)" % (self.lo.tolist(), self.hi.tolist()))
         return c[:, 0], c[:, 1], c[:, 2]
 
     def zeros(self):
