@@ -18,7 +18,7 @@
   the refined levels reaches the finest level as L_2^-1 P P f^_0 through
   psi_1 = P psi_0 + L_1^-1 S_1; compact middle- and fine-level sources give
   phi_2 = Psi_2 + L_2^-1 P f^_1 and phi_1 = Psi_1 + L_1^-1 (mean-8 of f^_2).
-
+"""
 import numpy as np
 
 from oracle import composite as C, direct, lgf_table as T
