@@ -141,6 +141,28 @@ lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream,
                      lgf_report *rep);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as lgf_solve(plan, f, u, stream, NULL), bit for bit, with the
+ * spectral workspace of every convolution (block spectra Fhat and Uhat and
+ * the lattice workspace) taken from a static device array of
+ * LGF_SCRATCH_MAX_BYTES bytes that the library holds on each device until
+ * the process ends, instead of from the plan.  The call allocates nothing
+ * and records no timing events; the plan's other workspaces (composite and
+ * refinement fields) are its own, allocated by lgf_plan_create.
+ * Limit: a plan whose Fhat + Uhat + lattice workspace (each rounded up to
+ * 256 bytes) exceed LGF_SCRATCH_MAX_BYTES is refused with LGF_E_INVALID
+ * before any device work.  Every such call on one device shares the one
+ * array, which keeps the last call's contents (the call clears what must
+ * start at zero): calls that overlap in time on one device race, whatever
+ * their plans, streams or threads, so the caller orders them (one stream,
+ * or events).  The context of the plan must have been created on the device
+ * (lgf_context_create looks the array's device address up).
+ */
+#define LGF_SCRATCH_MAX_BYTES (64u << 20)
+lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *stream);
+
+/*
  * Solve n independent requests with one launch per pipeline stage: the block
  * FFTs, spectral products and inverse FFTs of all requests that share block
  * size and precision run in common grids.  Each u[i] equals what

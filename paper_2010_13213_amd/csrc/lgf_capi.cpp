@@ -57,6 +57,30 @@ struct DeviceScope {
 
 using Key = std::tuple<int, int, int>;
 
+// Device scratch of lgf_solve_scratch: the spectral workspace (Fhat, Uhat,
+// lattice H) of one solve, shared by every such call on a device.  In host
+// code `scratch` names a host-side stand-in; its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels.
+constexpr size_t kScratchBytes = size_t(LGF_SCRATCH_MAX_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;     // device -> address of its copy of `scratch`
+
+void *scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw Failure(LGF_E_DEVICE, "no device address for the static scratch array");
+    g_scratch_ptr[device] = ptr;
+    return ptr;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
 void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
     require(d != nullptr, "null problem");
     require(d->n_levels >= 1 && d->n_levels <= 8, "n_levels must be in [1, 8]");
@@ -139,6 +163,7 @@ lgf_status lgf_context_create(int device, size_t hbm_budget_bytes, lgf_context *
         hip_check(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "hipStreamCreate");
         build_context_table(ctx);
         ring_init(ctx);
+        scratch_address(device);     // set-up of lgf_solve_scratch on this device
     });
     if (st != LGF_OK) {
         if (ctx) lgf_context_destroy(ctx);
@@ -224,6 +249,36 @@ lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream, l
         require(((uintptr_t)f % 8) == 0 && ((uintptr_t)u % 8) == 0, "misaligned field pointer");
         DeviceScope ds(plan->ctx->device);
         run_plan(plan, f, u, (hipStream_t)stream, rep);
+    });
+}
+
+lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *stream) {
+    return guard([&] {
+        require(plan != nullptr, "null plan");
+        require(f != nullptr && u != nullptr, "null field pointer");
+        require(((uintptr_t)f % 8) == 0 && ((uintptr_t)u % 8) == 0, "misaligned field pointer");
+        const SpecWs need = spectral_need(plan);
+        const size_t total = align256(need.fhat_bytes) + align256(need.uhat_bytes) + align256(need.lat_bytes);
+        if (total > kScratchBytes)
+            throw Failure(LGF_E_INVALID, "plan needs " + std::to_string(total) +
+                                             " bytes of spectral workspace; the static scratch holds " +
+                                             std::to_string(kScratchBytes));
+        DeviceScope ds(plan->ctx->device);
+        char *base = (char *)scratch_address(plan->ctx->device);
+        SpecWs ws = need;
+        ws.fhat = base;
+        ws.uhat = base + align256(need.fhat_bytes);
+        ws.lat = need.lat_bytes ? base + align256(need.fhat_bytes) + align256(need.uhat_bytes) : nullptr;
+        struct Restore {
+            lgf_plan *p;
+            ~Restore() {
+                p->ws_scratch = nullptr;
+                g_no_timing = false;
+            }
+        } restore{plan};
+        plan->ws_scratch = &ws;
+        g_no_timing = true;
+        run_plan(plan, f, u, (hipStream_t)stream, nullptr);
     });
 }
 

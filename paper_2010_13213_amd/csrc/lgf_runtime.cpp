@@ -24,6 +24,7 @@
 namespace lgf {
 
 thread_local std::string g_last_error;
+thread_local bool g_no_timing = false;
 
 void set_error(const std::string &m) { g_last_error = m; }
 
@@ -65,7 +66,7 @@ void DeviceBuffer::alloc(lgf_context *ctx, size_t n, const char *what) {
 // ------------------------------------------------------------------ timing
 
 StageTimer::StageTimer(lgf_context *c, int st, hipStream_t s_) : ctx(c), stage(st), s(s_) {
-    if (!ctx->timing) return;
+    if (!ctx->timing || g_no_timing) return;
     hip_check(hipEventCreate(&a), "event");
     hip_check(hipEventRecord(a, s), "event record");
 }
@@ -921,19 +922,24 @@ void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops) {
 
 // Spectral workspace large enough for every convolution of the plan, for
 // mac_nc components.
-void plan_alloc_spectral(lgf_plan *plan) {
-    size_t need = 0;
+SpecWs spectral_need(const lgf_plan *plan) {
+    SpecWs w;
+    size_t need = 0, hneed = 0;
     for (const Conv *c : plan->convs_view) {
         const size_t elem = c->fp32 ? 8 : 16;
         need = std::max(need, elem * (size_t)c->spec->n_freq * (size_t)c->n_slots);
+        if (c->method == kMethodLattice) hneed = std::max(hneed, elem * (size_t)lat_geom(*c, 1).hstride);
     }
-    need *= (size_t)plan->mac_nc;
-    plan->Fhat.alloc(plan->ctx, need, "Fhat workspace");
-    plan->Uhat.alloc(plan->ctx, need, "Uhat workspace");
-    size_t hneed = 0;
-    for (const Conv *c : plan->convs_view)
-        if (c->method == kMethodLattice) hneed = std::max(hneed, (c->fp32 ? 8 : 16) * (size_t)lat_geom(*c, 1).hstride);
-    if (hneed) plan->ws_lat.alloc(plan->ctx, hneed * (size_t)plan->mac_nc, "lattice workspace");
+    w.fhat_bytes = w.uhat_bytes = need * (size_t)plan->mac_nc;
+    w.lat_bytes = hneed * (size_t)plan->mac_nc;
+    return w;
+}
+
+void plan_alloc_spectral(lgf_plan *plan) {
+    const SpecWs w = spectral_need(plan);
+    plan->Fhat.alloc(plan->ctx, w.fhat_bytes, "Fhat workspace");
+    plan->Uhat.alloc(plan->ctx, w.uhat_bytes, "Uhat workspace");
+    if (w.lat_bytes) plan->ws_lat.alloc(plan->ctx, w.lat_bytes, "lattice workspace");
 }
 
 // Run one convolution for nc <= kMacComponents components:
@@ -945,19 +951,30 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     const double N3 = 8.0 * nb * nb * nb;
     const size_t elem = c.fp32 ? 8 : 16;
     const int64_t fs = (int64_t)c.spec->n_freq * c.n_slots;   // elements per component region
-    if (nc < 1 || nc > kMacComponents || (size_t)nc * fs * elem > plan->Fhat.bytes)
+    SpecWs own;
+    own.fhat = plan->Fhat.ptr;
+    own.uhat = plan->Uhat.ptr;
+    own.lat = plan->ws_lat.ptr;
+    own.fhat_bytes = plan->Fhat.bytes;
+    own.uhat_bytes = plan->Uhat.bytes;
+    own.lat_bytes = plan->ws_lat.bytes;
+    const SpecWs &ws = plan->ws_scratch ? *plan->ws_scratch : own;
+    if (nc < 1 || nc > kMacComponents || (size_t)nc * fs * elem > ws.fhat_bytes || (size_t)nc * fs * elem > ws.uhat_bytes)
         throw Failure(LGF_E_INVALID, "internal: component count outside the spectral workspace");
     // empty slots of Fhat must read as zero; the forward FFT writes only
     // occupied slots, so clear when another slot map used the buffer last
-    // (a convolution with a source in every slot overwrites all it reads)
-    if (plan->fhat_conv != &c) {
-        if (!fhat_full(c)) hip_check(zero_fill(plan->Fhat.ptr, plan->Fhat.bytes, s), "clear Fhat");
+    // (a convolution with a source in every slot overwrites all it reads).
+    // Shared scratch may hold anything: clear it whenever a slot is empty.
+    if (plan->ws_scratch) {
+        if (!fhat_full(c)) hip_check(zero_fill(ws.fhat, (size_t)nc * fs * elem, s), "clear Fhat");
+    } else if (plan->fhat_conv != &c) {
+        if (!fhat_full(c)) hip_check(zero_fill(ws.fhat, ws.fhat_bytes, s), "clear Fhat");
         plan->fhat_conv = &c;
     }
     for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 0, s);
         hip_check(block_fft_forward(nb, c.fp32, src + (size_t)k * sstride, (const int64_t *)c.d_src_off.ptr,
-                                    (const int *)c.d_src_slot.ptr, c.n_src, (char *)plan->Fhat.ptr + k * fs * elem,
+                                    (const int *)c.d_src_slot.ptr, c.n_src, (char *)ws.fhat + k * fs * elem,
                                     c.n_slots, c.method == kMethodLattice, 1.0, s),
                   "forward block FFT");
     }
@@ -965,28 +982,28 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
         const LatGeom g = lat_geom(c, nc);
         {
             StageTimer t(plan->ctx, kStageLatX, s);
-            hip_check(lattice_fwd(g, c.fp32, plan->Fhat.ptr, plan->ws_lat.ptr, s), "lattice x DFT");
+            hip_check(lattice_fwd(g, c.fp32, ws.fhat, ws.lat, s), "lattice x DFT");
         }
         {
             StageTimer t(plan->ctx, kStageLatYZ, s);
-            hip_check(lattice_yz(g, c.fp32, plan->ws_lat.ptr, c.lspec->data.ptr, c.lspec->order, s), "lattice y/z slabs");
+            hip_check(lattice_yz(g, c.fp32, ws.lat, c.lspec->data.ptr, c.lspec->order, s), "lattice y/z slabs");
         }
         StageTimer t(plan->ctx, kStageLatInv, s);
-        hip_check(lattice_inv(g, c.fp32, plan->ws_lat.ptr, plan->Uhat.ptr, s), "lattice inverse x DFT");
+        hip_check(lattice_inv(g, c.fp32, ws.lat, ws.uhat, s), "lattice inverse x DFT");
     } else if (c.parts.empty()) {   // no source or no target: the convolution is zero
-        hip_check(zero_fill(plan->Uhat.ptr, plan->Uhat.bytes, s), "clear Uhat");
+        hip_check(zero_fill(ws.uhat, (size_t)nc * fs * elem, s), "clear Uhat");
     }
     for (const auto &p : c.parts) {
         StageTimer t(plan->ctx, 1, s);
         SmacGeom g = conv_geom(c, *p);
         g.fstride = fs;
-        hip_check(smac_launch(g, c.fp32, p->sparse, nc, plan->Fhat.ptr, plan->Uhat.ptr, c.spec->data.ptr,
+        hip_check(smac_launch(g, c.fp32, p->sparse, nc, ws.fhat, ws.uhat, c.spec->data.ptr,
                               (const SmacRow *)p->d_rows.ptr, (const SmacTile *)p->d_tiles.ptr, s),
                   "spectral MAC");
     }
     for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 2, s);
-        hip_check(block_fft_inverse(nb, c.fp32, (char *)plan->Uhat.ptr + k * fs * elem, c.n_slots,
+        hip_check(block_fft_inverse(nb, c.fp32, (char *)ws.uhat + k * fs * elem, c.n_slots,
                                     c.method == kMethodLattice, (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
                                     dst + (size_t)k * dstride, dx * dx / N3, accumulate, s),
                   "inverse block FFT");

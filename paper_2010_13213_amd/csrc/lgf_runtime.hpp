@@ -16,6 +16,8 @@
 namespace lgf {
 
 extern thread_local std::string g_last_error;
+// While set on a thread, launches record no stage-timing events.
+extern thread_local bool g_no_timing;
 void set_error(const std::string &m);
 
 struct Failure : std::runtime_error {
@@ -177,6 +179,14 @@ struct ConvOp {
     DeviceBuffer d_map, d_tblk, d_t2sh, d_depth, d_gofs, d_dofs, d_out_src, d_out_dst;
 };
 
+// Spectral workspace of a solve: Fhat, Uhat (mac_nc component regions each)
+// and the lattice workspace H.  By default the plan's own buffers; the
+// static-scratch solve points them into the library's device array.
+struct SpecWs {
+    void *fhat = nullptr, *uhat = nullptr, *lat = nullptr;
+    size_t fhat_bytes = 0, uhat_bytes = 0, lat_bytes = 0;
+};
+
 // Per-level schedule data of a composite plan.
 struct LevelSched {
     int n_own = 0;
@@ -225,6 +235,7 @@ struct lgf_plan {
     lgf::DeviceBuffer Fhat, Uhat;                  // mac_nc component regions each
     lgf::DeviceBuffer ws_lat;                      // lattice-DFT workspace H, mac_nc regions
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
+    const lgf::SpecWs *ws_scratch = nullptr;       // set only during a static-scratch solve
     size_t workspace_bytes() const;
 };
 
@@ -256,6 +267,8 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,
                 int axis = 0);
 void plan_alloc_spectral(lgf_plan *plan);
+// Bytes of Fhat / Uhat / H every convolution of the plan needs (pointers null).
+SpecWs spectral_need(const lgf_plan *plan);
 std::unique_ptr<ConvOp> build_op(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool refine);
 // Refinement workspaces (per component region) for the plan's refined ops.
 void plan_alloc_refine(lgf_plan *plan, const std::vector<const ConvOp *> &ops);

@@ -19,7 +19,7 @@ _PREC = {"fp64": LGF_FP64, "fp32_refine": LGF_FP32_REFINE}
 EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "lgf_plan_create",
             "lgf_problem_check",
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
-            "lgf_solve", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
+            "lgf_solve", "lgf_solve_scratch", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
             "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
@@ -85,6 +85,8 @@ def lib():
     L.lgf_plan_field_len.restype = sz
     L.lgf_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(Report)]
     L.lgf_solve.restype = ctypes.c_int
+    L.lgf_solve_scratch.argtypes = [vp, vp, vp, vp]
+    L.lgf_solve_scratch.restype = ctypes.c_int
     L.lgf_solve_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(vp), vp, ctypes.POINTER(Report)]
     L.lgf_solve_batch.restype = ctypes.c_int
@@ -301,6 +303,23 @@ class Plan:
         _check(lib().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                _stream_handle(stream), ctypes.byref(rep) if rep is not None else None))
         return (u, rep) if report else u
+
+    def solve_scratch(self, f, u, stream=None):
+        """lgf_solve_scratch: the same solve with the spectral workspace in the
+        library's static device array (allocates nothing; u must be given)."""
+        import torch
+        n = self.field_len()
+        for t in (f, u):
+            if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+                raise ValueError("f and u must be contiguous CUDA float64 tensors of %d elements" % n)
+        _check(lib().lgf_solve_scratch(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                       _stream_handle(stream)))
+        return u
+
+
+def scratch_max_bytes():
+    """LGF_SCRATCH_MAX_BYTES of include/lgf.h: the static scratch of lgf_solve_scratch."""
+    return 64 << 20
 
 
 class Graph:
