@@ -91,8 +91,10 @@ typedef struct lgf_report {
 
 /*
  * Create a context on HIP device `device`.  The context owns the device-
- * resident LGF table (built here, in float64) and the cache of LGF block
- * spectra shared by every plan made from it.  `hbm_budget_bytes` caps what
+ * resident LGF table (built here, in float64: the exact near field and the
+ * asymptotic far field that Sec. 5 of the paper tabulates once and shares
+ * between levels, since the 7-point LGF is the same on every level) and the
+ * cache of LGF block spectra shared by every plan made from it.  `hbm_budget_bytes` caps what
  * plans and spectra may allocate (0 = no cap).  Errors: LGF_E_INVALID
  * (bad device or null out), LGF_E_DEVICE.
  */
@@ -163,12 +165,23 @@ lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream,
 lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *stream);
 
 /*
- * Solve n independent requests with one launch per pipeline stage: the block
- * FFTs, spectral products and inverse FFTs of all requests that share block
- * size and precision run in common grids.  Each u[i] equals what
- * lgf_solve(plans[i], f[i], u[i], ...) writes, bit for bit (every request's
- * reduction order is fixed by its own plan).  The plans must be distinct
- * and come from `ctx`.  `reps` (optional) has n entries.
+ * Solve n independent requests (each the problem of lgf_solve: Sec. 2.2 on
+ * one level, the Sec. 3.4 recursion on a composite mesh) together.  Per block
+ * size, the single-level requests run component by component, and the
+ * composite ones level by level in the paper's order (every request's
+ * restriction and coarsening; then for k = 0, 1, ...: every request's
+ * correction source of level k, the phi_k convolutions of all requests,
+ * their psi_k convolutions, the restriction).  Within one such step the
+ * forward block FFTs of all requests run as one launch per precision, the
+ * block-pair spectral products as one launch per (phase, precision, tile
+ * shape, sparsity), the inverse block FFTs as one launch per precision;
+ * lattice-FFT products and the stencil steps run per request.  These are
+ * ordinary grids over a job table, not a persistent kernel, and the batch is
+ * not captured into a graph (lgf_graph_create captures one plan's solve).
+ * Each u[i] equals what lgf_solve(plans[i], f[i], u[i], ...) writes, bit for
+ * bit (every request's reduction order is fixed by its own plan).  The
+ * plans must be distinct and come from `ctx`.  `reps` (optional) has n
+ * entries; each gets the device time of the whole batch.
  */
 lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans,
                            const double *const *f, double *const *u, void *stream,

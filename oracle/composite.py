@@ -11,7 +11,10 @@ AMR-LGF-2, partial_LGF, Scorrection, combine_S, FLGF-AMR), in its order:
    (phi_0 = L_0^-1 F_0);
 3. restriction Gamma: phi_k is kept on Omega_k only.
 
-Every L_k^-1 is the plain direct sum dx_k^2 * G * (.) of ``direct.py``.
+Every L_k^-1 is the plain direct sum dx_k^2 * G * (.) of ``direct.py``; with
+``fft_min_targets`` set, evaluations at that many target cells or more (the
+full psi_k fields of large meshes) use the same convolution by a zero-padded
+library FFT over the bounding box (``box.py``).
 
 Readings where the paper is silent (each is listed in the design notes):
 
@@ -32,7 +35,7 @@ Readings where the paper is silent (each is listed in the design notes):
 """
 import numpy as np
 
-from . import direct
+from . import box as fftbox, direct
 
 
 # ---------------------------------------------------------------- helpers --
@@ -142,8 +145,9 @@ def coarsen_mean8(fine_box, fine, coarse_cells):
 class CompositeOracle:
     """Composite-grid LGF solve of one scalar component (all steps in FP64)."""
 
-    def __init__(self, nb, dx0, level_blocks, ext_layers=1):
+    def __init__(self, nb, dx0, level_blocks, ext_layers=1, fft_min_targets=None):
         self.nb = nb
+        self.fft_min_targets = fft_min_targets
         self.dx0 = dx0
         self.K = len(level_blocks)
         self.blocks = [np.asarray(b, dtype=np.int64).reshape(-1, 3) for b in level_blocks]
@@ -203,6 +207,8 @@ class CompositeOracle:
     def conv(self, k, src_cells, src_vals, tgt_cells):
         """L_k^-1 applied to a source on cells, evaluated at target cells."""
         keep = src_vals != 0.0
+        if self.fft_min_targets is not None and len(tgt_cells) >= self.fft_min_targets and keep.any():
+            return fftbox.convolve_cells(src_cells[keep], src_vals[keep], tgt_cells, self.dx[k])
         return direct.direct_sum(src_cells[keep], src_vals[keep], tgt_cells, self.dx[k])
 
     # ---- stage: correction source S_k on R_k (step 2) ----

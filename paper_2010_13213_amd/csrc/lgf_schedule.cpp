@@ -518,6 +518,147 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
 
 }  // namespace
 
+// One L^-1 application of a batch, for one component: plan, op, source ->
+// destination (accumulate: add into it).  The plans of one batch call are
+// distinct, so each call owns its plan's spectral and refinement workspaces.
+struct OpCall {
+    lgf_plan *p;
+    const ConvOp *op;
+    const double *src;
+    double *dst;
+    double dx;
+    int accumulate;
+};
+
+// The ops of one batch step: plain ones and the float32 pass of refined ones
+// in common launches, then the refined ones' residual step, cut passes (rows
+// along x, then along y) and float32 residual pass, each in common launches.
+void run_ops_batch(lgf_context *ctx, const std::vector<OpCall> &calls, hipStream_t s) {
+    std::vector<ConvCall> a, b1, b1y, b2;
+    for (const OpCall &k : calls) {
+        const ConvOp &op = *k.op;
+        if (!op.refined) {
+            a.push_back(ConvCall{k.p, op.c64.get(), k.src, k.dst, k.dx, k.accumulate});
+            continue;
+        }
+        a.push_back(ConvCall{k.p, op.c32.get(), k.src, (double *)k.p->ws_ut.ptr, k.dx, 0});
+        if (op.c64) b1.push_back(ConvCall{k.p, op.c64.get(), (const double *)k.p->ws_ush.ptr, k.dst, k.dx, 1});
+        if (op.c64y) b1y.push_back(ConvCall{k.p, op.c64y.get(), (const double *)k.p->ws_ush.ptr, k.dst, k.dx, 1});
+        b2.push_back(ConvCall{k.p, op.ccorr.get(), (const double *)k.p->ws_rho.ptr, k.dst, k.dx, 1});
+    }
+    run_conv_batch(ctx, a, s);
+    for (const OpCall &k : calls)
+        if (k.op->refined)
+            refine_middle(k.p, *k.op, k.src, k.dst, (const double *)k.p->ws_ut.ptr, (double *)k.p->ws_rho.ptr,
+                          (double *)k.p->ws_ush.ptr, k.dx, k.accumulate, s);
+    run_conv_batch(ctx, b1, s);
+    run_conv_batch(ctx, b1y, s);
+    run_conv_batch(ctx, b2, s);
+}
+
+// Composite plans of one block size, level by level (the order of the
+// paper's Sec. 3.4 within each plan): per component group, every plan's
+// source restriction and coarsening, then for k = 0, 1, ...: every plan's
+// correction source at level k, the phi_k convolutions of all plans in
+// common launches, then their psi_k convolutions, then the restriction.
+void run_composite_batch(lgf_context *ctx, const std::vector<lgf_plan *> &ps, const std::vector<const double *> &fs,
+                         const std::vector<double *> &us, hipStream_t s) {
+    int n_groups = 0, k_max = 0;
+    for (lgf_plan *p : ps) {
+        n_groups = std::max(n_groups, (p->nc + kMacComponents - 1) / kMacComponents);
+        k_max = std::max(k_max, p->K);
+    }
+    const size_t n = ps.size();
+    for (int g = 0; g < n_groups; ++g) {
+        const int c0 = g * kMacComponents;
+        std::vector<int> ng(n, 0), cur(n, 0);
+        for (size_t i = 0; i < n; ++i) {
+            lgf_plan *p = ps[i];
+            if (c0 >= p->nc) continue;
+            ng[i] = std::min(kMacComponents, p->nc - c0);
+            const int64_t CL = p->comp_len;
+            const double *fg = fs[i] + (size_t)c0 * CL;
+            double *FH = (double *)p->ws_fhat.ptr, *FC = (double *)p->ws_F.ptr;
+            StageTimer tm(ctx, 3, s);
+            for (int c = 0; c < ng[i]; ++c)
+                for (int k = 0; k < p->K; ++k) {
+                    const LevelSched &L = *p->lv[k];
+                    hip_check(mask_blocks(p->nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                          (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
+                                          L.n_own, s),
+                              "mask sources");
+                    hip_check(copy_blocks(p->nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                          (const int64_t *)L.d_own_off.ptr, L.n_own, s),
+                              "copy sources");
+                }
+            for (int c = 0; c < ng[i]; ++c)
+                for (int k = p->K - 2; k >= 0; --k) {
+                    const LevelSched &L = *p->lv[k];
+                    hip_check(coarsen_mean8(p->nb, FC + c * CL, FC + c * CL, (const int64_t *)L.d_cf_fine.ptr,
+                                            (const int64_t *)L.d_cf_coarse.ptr, (const unsigned char *)L.d_cf_oct.ptr,
+                                            L.n_cf, s),
+                              "coarsen");
+                }
+        }
+        for (int k = 0; k < k_max; ++k) {
+            std::vector<OpCall> opF[kMacComponents], opPsi[kMacComponents];
+            for (size_t i = 0; i < n; ++i) {
+                lgf_plan *p = ps[i];
+                if (ng[i] == 0 || k >= p->K) continue;
+                const LevelSched &L = *p->lv[k];
+                const int nb = p->nb;
+                const int64_t CL = p->comp_len, DL = p->dom_len, EL = p->ext_len;
+                double *FH = (double *)p->ws_fhat.ptr, *FC = (double *)p->ws_F.ptr;
+                double *PP = (double *)p->ws_ppsi.ptr, *SF = (double *)p->ws_srcF.ptr, *Sf = (double *)p->ws_srcf.ptr;
+                double *ug = us[i] + (size_t)c0 * CL;
+                const double dxk = p->dx0 / (double)(1 << k);
+                double *psi_prev = (double *)p->ws_psi[cur[i]].ptr;
+                double *psi_next = (double *)p->ws_psi[cur[i] ^ 1].ptr;
+                if (k > 0) {
+                    StageTimer tm(ctx, 3, s);
+                    for (int c = 0; c < ng[i]; ++c) {
+                        hip_check(correction_source(nb, L.corr, psi_prev + c * DL, (const int *)L.d_cmap.ptr,
+                                                    (const int *)L.d_fblk.ptr, (const int64_t *)L.d_ext_own.ptr,
+                                                    FC + c * CL, FH + c * CL, PP + c * EL, SF + c * EL, Sf + c * EL,
+                                                    L.n_ext, s),
+                                  "correction source");
+                        hip_check(copy_blocks(nb, PP + c * EL, ug + c * CL, (const int64_t *)L.d_cu_src.ptr,
+                                              (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
+                                  "P psi -> phi");
+                        if (L.convPsi)
+                            hip_check(copy_blocks(nb, PP + c * EL, psi_next + c * DL, (const int64_t *)L.d_cp_src.ptr,
+                                                  (const int64_t *)L.d_cp_dst.ptr, L.n_dom, s),
+                                      "P psi -> psi");
+                    }
+                }
+                for (int c = 0; c < ng[i]; ++c) {
+                    const double *srcF = k == 0 ? FC + c * CL : SF + c * EL;
+                    opF[c].push_back(OpCall{p, L.convF.get(), srcF, ug + c * CL, dxk, k > 0});
+                    if (L.convPsi) {
+                        const double *srcf = k == 0 ? FH + c * CL : Sf + c * EL;
+                        opPsi[c].push_back(OpCall{p, L.convPsi.get(), srcf, psi_next + c * DL, dxk, k > 0});
+                    }
+                }
+            }
+            for (int c = 0; c < kMacComponents; ++c) run_ops_batch(ctx, opF[c], s);
+            for (int c = 0; c < kMacComponents; ++c) run_ops_batch(ctx, opPsi[c], s);
+            for (size_t i = 0; i < n; ++i) {
+                lgf_plan *p = ps[i];
+                if (ng[i] == 0 || k >= p->K) continue;
+                const LevelSched &L = *p->lv[k];
+                double *ug = us[i] + (size_t)c0 * p->comp_len;
+                if (L.any_cover)
+                    for (int c = 0; c < ng[i]; ++c)
+                        hip_check(mask_blocks(p->nb, ug + c * p->comp_len, ug + c * p->comp_len,
+                                              (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
+                                              (const unsigned char *)L.d_cover.ptr, L.n_own, s),
+                                  "restrict phi");
+                cur[i] ^= 1;
+            }
+        }
+    }
+}
+
 void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
                hipStream_t s, lgf_report *reps) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -526,52 +667,37 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         hip_check(hipEventCreate(&e1), "event");
         hip_check(hipEventRecord(e0, s), "event record");
     }
-    // composite plans run one after another; single-level plans are batched
+    // per block size: single-level plans component by component, then the
+    // composite plans level by level
     std::map<int, std::vector<int>> by_nb;
-    for (int i = 0; i < n; ++i) {
-        if (plans[i]->K > 1) {
-            enqueue(plans[i], f[i], u[i], s);
-            continue;
-        }
-        by_nb[plans[i]->nb].push_back(i);
-    }
+    for (int i = 0; i < n; ++i) by_nb[plans[i]->nb].push_back(i);
     for (auto &kv : by_nb) {
-        const std::vector<int> &ids = kv.second;
+        std::vector<int> single;
+        std::vector<lgf_plan *> cps;
+        std::vector<const double *> cfs;
+        std::vector<double *> cus;
+        for (int i : kv.second) {
+            if (plans[i]->K == 1) {
+                single.push_back(i);
+            } else {
+                cps.push_back(plans[i]);
+                cfs.push_back(f[i]);
+                cus.push_back(u[i]);
+            }
+        }
         int max_nc = 0;
-        for (int i : ids) max_nc = std::max(max_nc, plans[i]->nc);
+        for (int i : single) max_nc = std::max(max_nc, plans[i]->nc);
         for (int comp = 0; comp < max_nc; ++comp) {
-            // a: plain solves and the float32 pass of refined ones; then the
-            // refined ones' residual, cut (b1: rows along x, b1y: rows along
-            // y) and float32 residual (b2) passes
-            std::vector<ConvCall> a, b1, b1y, b2;
-            for (int i : ids) {
+            std::vector<OpCall> calls;
+            for (int i : single) {
                 lgf_plan *p = plans[i];
                 if (comp >= p->nc) continue;
-                const double *src = f[i] + (size_t)comp * p->comp_len;
-                double *dst = u[i] + (size_t)comp * p->comp_len;
-                const ConvOp &op = *p->op0;
-                if (!op.refined) {
-                    a.push_back(ConvCall{p, op.c64.get(), src, dst, p->dx0, 0});
-                } else {
-                    a.push_back(ConvCall{p, op.c32.get(), src, (double *)p->ws_ut.ptr, p->dx0, 0});
-                    if (op.c64) b1.push_back(ConvCall{p, op.c64.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
-                    if (op.c64y)
-                        b1y.push_back(ConvCall{p, op.c64y.get(), (const double *)p->ws_ush.ptr, dst, p->dx0, 1});
-                    b2.push_back(ConvCall{p, op.ccorr.get(), (const double *)p->ws_rho.ptr, dst, p->dx0, 1});
-                }
+                calls.push_back(OpCall{p, p->op0.get(), f[i] + (size_t)comp * p->comp_len,
+                                       u[i] + (size_t)comp * p->comp_len, p->dx0, 0});
             }
-            run_conv_batch(ctx, a, s);
-            for (int i : ids) {
-                lgf_plan *p = plans[i];
-                if (comp >= p->nc || !p->op0->refined) continue;
-                refine_middle(p, *p->op0, f[i] + (size_t)comp * p->comp_len, u[i] + (size_t)comp * p->comp_len,
-                              (const double *)p->ws_ut.ptr, (double *)p->ws_rho.ptr, (double *)p->ws_ush.ptr, p->dx0,
-                              0, s);
-            }
-            run_conv_batch(ctx, b1, s);
-            run_conv_batch(ctx, b1y, s);
-            run_conv_batch(ctx, b2, s);
+            run_ops_batch(ctx, calls, s);
         }
+        if (!cps.empty()) run_composite_batch(ctx, cps, cfs, cus, s);
     }
     if (reps) {
         hip_check(hipEventRecord(e1, s), "event record");

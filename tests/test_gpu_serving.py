@@ -73,3 +73,46 @@ def test_hbm_budget_refuses_an_oversized_plan():
     small.close()
     ctx.close()
     torch.cuda.synchronize()
+
+
+def _two_level_small(nc, seed):
+    rng = np.random.default_rng(seed)
+    b0 = np.array([(x, y, z) for z in range(3) for y in range(3) for x in range(3)], dtype=np.int32)
+    b1 = np.array([(2, 2, 2), (3, 2, 2), (2, 3, 3)], dtype=np.int32)
+    return inputs.Problem(nb=8, dx0=0.5, levels=[
+        inputs.Level(blocks=b0, values=rng.standard_normal((nc, len(b0), 8, 8, 8))),
+        inputs.Level(blocks=b1, values=rng.standard_normal((nc, len(b1), 8, 8, 8)))])
+
+
+def test_composite_batch_equals_alone_bitwise(gpu_ctx):
+    """Composite plans of 2 and 3 levels (FP64 and FP32+refine, 2 and 4
+    components) batched level by level with a single-level plan: each result
+    equals its lgf_solve, bit for bit, and the three-level ones meet the
+    stored oracle samples."""
+    import os
+    import torch
+    from paper_2010_13213_amd import lgf
+    rings = inputs.colliding_rings(nb=8, dx0=1.0 / 8, components=(0, 2))
+    cases = [(rings, "fp64"), (_two_level_small(4, 3), "fp32_refine"), (rings, "fp32_refine"),
+             (inputs.gaussian_box(), "fp64"), (_two_level_small(1, 4), "fp64")]
+    plans = [lgf.Plan.for_problem(gpu_ctx, p, prec) for p, prec in cases]
+    fs = [torch.from_numpy(p.flat_source()).cuda() for p, _ in cases]
+    alone = [pl.solve(f).cpu().numpy() for pl, f in zip(plans, fs)]
+    us = [torch.full_like(f, float("nan")) for f in fs]
+    print("batch: 3-level rings fp64/fp32_refine, 2-level 4 comps, single level", flush=True)
+    lgf.solve_batch(gpu_ctx, plans, fs, us)
+    torch.cuda.synchronize()
+    for (p, prec), a, u in zip(cases, alone, us):
+        assert np.array_equal(a, u.cpu().numpy()), (p.name, prec)
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "colliding_rings_quarter_samples.npz"))
+    for i, tol in ((0, 1e-12), (2, 1e-10)):
+        got = us[i].cpu().numpy().reshape(2, -1)
+        base = 0
+        for k, lv in enumerate(rings.levels):
+            n = len(lv.blocks) * rings.nb ** 3
+            for c in range(2):
+                idx = gold["sample%d" % k]
+                assert rel_l2(got[c][base:base + n][idx], gold["phi%d_c%d" % (k, c)]) < tol, (i, k, c)
+            base += n
+    for pl in plans:
+        pl.close()

@@ -20,6 +20,7 @@
   phi_2 = Psi_2 + L_2^-1 P f^_1 and phi_1 = Psi_1 + L_1^-1 (mean-8 of f^_2).
 """
 import numpy as np
+import pytest
 
 from oracle import composite as C, direct, lgf_table as T
 
@@ -110,11 +111,16 @@ def _lap_on_cells(box_lo, box_hi, fn, cells, dx):
     return L[i, j, k]
 
 
-def _two_level(ext_layers):
+# Each composite pin runs with every convolution a direct sum (None) and with
+# every convolution a zero-padded FFT over the bounding box (1 target).
+FFT_MODES = pytest.mark.parametrize("fft", [None, 1], ids=["direct", "fft"])
+
+
+def _two_level(ext_layers, fft=None):
     nb = 8
     coarse = _cube_blocks(0, 4)                   # coarse cells [0, 32)^3, dx0 = 1
     fine = _cube_blocks(2, 2)                     # refines coarse cells [8, 16)^3
-    orc = C.CompositeOracle(nb, 1.0, [coarse, fine], ext_layers=ext_layers)
+    orc = C.CompositeOracle(nb, 1.0, [coarse, fine], ext_layers=ext_layers, fft_min_targets=fft)
     ctr, rad = np.array([22.0, 22.0, 22.0]), 4.5  # compact Psi in the coarse-only zone
     psi = lambda c: _bump(c, ctr, rad)
     f0 = _lap_on_cells((-2, -2, -2), (34, 34, 34), psi, orc.cells[0], 1.0)
@@ -122,10 +128,11 @@ def _two_level(ext_layers):
     return orc, psi, f0, f1
 
 
-def test_two_level_exact_when_extension_covers_correction_support():
+@FFT_MODES
+def test_two_level_exact_when_extension_covers_correction_support(fft):
     """f^_0 = L_0 Psi with compact Psi: phi_0 = Psi on Omega_0 and
     phi_1 = L_1^-1 P f^_0 exactly once Omega_1^E covers supp S."""
-    orc, psi, f0, f1 = _two_level(ext_layers=3)
+    orc, psi, f0, f1 = _two_level(ext_layers=3, fft=fft)
     assert np.all(orc.mask[0][f0 != 0])           # the source lives on Omega_0
     phi = orc.solve([f0, f1])
     m0 = orc.mask[0]
@@ -235,7 +242,8 @@ def _smooth_step(t):
     return out
 
 
-def test_three_level_coarse_source_reaches_finest_level_through_psi_recursion():
+@FFT_MODES
+def test_three_level_coarse_source_reaches_finest_level_through_psi_recursion(fft):
     """f^_0 = L_0 Psi_0 on Omega_0, nothing finer.  Psi_0 is linear (so
     discrete-harmonic: L_0 Psi_0 = 0) on a coarse box around the refined
     region and falls smoothly to 0 outside it, so f^_0 is compact, lives on
@@ -248,7 +256,8 @@ def test_three_level_coarse_source_reaches_finest_level_through_psi_recursion():
     a wrong sign or a wrong level spacing in it is an O(1) error."""
     nb, lo, hi, w = 4, 7.0, 11.0, 4.0
     lv0 = _box_blocks((0, 0, 0), (5, 5, 5))                   # coarse cells [0, 20)^3
-    orc = C.CompositeOracle(nb, 1.0, [lv0, np.array([[4, 4, 4]]), np.array([[8, 8, 8]])], ext_layers=7)
+    orc = C.CompositeOracle(nb, 1.0, [lv0, np.array([[4, 4, 4]]), np.array([[8, 8, 8]])], ext_layers=7,
+                            fft_min_targets=fft)
     a, b = np.array([0.3, -0.5, 0.8]), 2.0
 
     def psi0(c):                # linear on centres in [lo, hi)^3, 0 beyond distance w
@@ -286,14 +295,15 @@ def test_three_level_coarse_source_reaches_finest_level_through_psi_recursion():
     assert e2 < 1e-3, e2
 
 
-def test_three_level_middle_and_fine_sources():
+@FFT_MODES
+def test_three_level_middle_and_fine_sources(fft):
     """f^_1 = L_1 Psi_1 on Omega_1 and f^_2 = L_2 Psi_2 on Omega_2 (compact),
     f^_0 = 0.  Then psi_0 = 0, psi_1 = Psi_1 (the recursion takes f^_1, not
     the cumulative F_1), S_2 = (P L_1 - L_2 P) Psi_1 is compact and covered,
     so exactly phi_2 = Psi_2 + L_2^-1 P f^_1 and phi_1 = Psi_1 + L_1^-1 F
     with F the mean of the 8 children of f^_2 (eq. combine_S)."""
     nb, blocks = _k3_geometry()
-    orc = C.CompositeOracle(nb, 1.0, blocks, ext_layers=2)
+    orc = C.CompositeOracle(nb, 1.0, blocks, ext_layers=2, fft_min_targets=fft)
     psi1 = lambda c: _bump(c, np.array([27.0, 32.0, 32.0]), 2.2)   # level-1 x in (24.8, 29.2): Omega_1
     psi2 = lambda c: _bump(c, np.array([40.0, 64.0, 64.0]), 5.5)   # level-2 cells inside Omega_2
     box1 = C.Box(np.array([14, 22, 22]), np.array([50, 42, 42]))

@@ -10,7 +10,9 @@
 import numpy as np
 import scipy.fft as sfft
 
-from oracle import direct, lgf_table as T
+import pytest
+
+from oracle import box, direct, lgf_table as T
 
 
 def _grid(n0, n1, lo=(0, 0, 0)):
@@ -79,3 +81,21 @@ def test_translation_invariance():
     a = direct.direct_sum(src, f, tgt, 1.0)
     b = direct.direct_sum(src + sh, f, tgt + sh, 1.0)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (140, 3, 4), (3, 131, 2)])
+def test_fft_box_convolution_equals_direct_sum(shape):
+    """The oracle's zero-padded FFT over a box (used for full psi fields of
+    large composite meshes) against the direct sum, across the near/far
+    switch of the table (extents past 129 cells)."""
+    rng = np.random.default_rng(sum(shape))
+    f = rng.standard_normal(shape)
+    ax = [np.arange(n) for n in shape]
+    cells = np.stack([a.ravel() for a in np.meshgrid(*ax, indexing="ij")], axis=1)
+    u = box.convolve_box(f, 0.3)
+    ref = direct.direct_sum(cells, f.ravel(), cells, 0.3)
+    assert np.max(np.abs(u.ravel() - ref)) / np.abs(ref).max() < 1e-13
+    sub = rng.choice(len(cells), 40, replace=False)
+    got = box.convolve_cells(cells[sub] + 11, f.ravel()[sub], cells - 7, 0.3)
+    ref2 = direct.direct_sum(cells[sub] + 11, f.ravel()[sub], cells - 7, 0.3)
+    assert np.max(np.abs(got - ref2)) / np.abs(ref2).max() < 1e-13
