@@ -145,8 +145,35 @@ def _pct(xs, q):
     return xs[k]
 
 
-def cpu_baseline(problem, budget_s=12.0, seed=0):
-    """Time the oracle direct sum on a sample of targets (all sources)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _time_direct(c, f, dx, rng, budget_s):
+    """Direct sums of all sources at a random target sample sized to take
+    about budget_s: returns (targets, seconds)."""
+    from oracle import direct
+    probe = c[rng.choice(len(c), 2 * direct.num_threads(), replace=False)]   # every thread busy
+    t0 = time.perf_counter()
+    direct.direct_sum(c, f, probe, dx)
+    per = max(time.perf_counter() - t0, 1e-4) / len(probe)
+    n = int(max(8, min(len(c), budget_s / per)))
+    tg = c[rng.choice(len(c), n, replace=False)]
+    t0 = time.perf_counter()
+    direct.direct_sum(c, f, tg, dx)
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(problem, budget_s=10.0, seed=0):
+    """Time the oracle direct sum on samples of targets (all sources), on all
+    host cores and on one, plus the full 32^3 Gaussian box."""
     import numpy as np
     from oracle import direct
     from paper_2010_13213_amd import inputs
@@ -155,20 +182,30 @@ def cpu_baseline(problem, budget_s=12.0, seed=0):
     rng = np.random.default_rng(seed)
     direct.build(force=False)
     direct.direct_sum(c[:1], f[:1], c[:1], problem.dx0)      # loads the library and its table
-    probe = c[rng.choice(len(c), 8, replace=False)]
+    threads = direct.num_threads()
+    n, dt = _time_direct(c, f, problem.dx0, rng, budget_s)
+    direct.set_num_threads(1)
+    try:
+        n1, dt1 = _time_direct(c, f, problem.dx0, rng, budget_s / 2)
+    finally:
+        direct.set_num_threads(threads)
+    gb = inputs.gaussian_box()
+    cg = inputs.cell_coords(gb.levels[0].blocks, gb.nb)
     t0 = time.perf_counter()
-    direct.direct_sum(c, f, probe, problem.dx0)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    n = int(max(16, min(len(c), 8 * budget_s / dt)))
-    tg = c[rng.choice(len(c), n, replace=False)]
-    t0 = time.perf_counter()
-    direct.direct_sum(c, f, tg, problem.dx0)
-    dt = time.perf_counter() - t0
-    u_tg = direct.direct_sum(c, f, tg[:64], problem.dx0)
-    return {"value": n / dt, "unit": "cells/s", "cores": direct.num_threads(), "kind": "oracle",
+    direct.direct_sum(cg, gb.flat_source(), cg, gb.dx0)
+    t_gb = time.perf_counter() - t0
+    tg = c[rng.choice(len(c), 64, replace=False)]
+    u_tg = direct.direct_sum(c, f, tg, problem.dx0)
+    return {"value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "%d random target cells of the 256^3 box, each summed over all %d source "
-                      "cells (C/OpenMP direct sum), %.1f s" % (n, len(c), dt),
-            "fft_comparator": cpu_fft_comparator(problem, c, f, tg[:64], u_tg)}
+                      "cells (C/OpenMP direct sum, %d threads), %.1f s" % (n, len(c), threads, dt),
+            "single_thread": {"value": n1 / dt1, "unit": "cells/s", "cores": 1,
+                              "sample": "%d random target cells of the same box, %.1f s" % (n1, dt1)},
+            "gaussian_box_32_full": {"value": len(cg) / t_gb, "unit": "cells/s", "cores": threads,
+                                     "sample": "all %d cells against all %d sources, %.2f s"
+                                               % (len(cg), len(cg), t_gb)},
+            "fft_comparator": cpu_fft_comparator(problem, c, f, tg, u_tg)}
 
 
 def cpu_fft_comparator(problem, c, f, check_tgt, check_ref):
@@ -223,7 +260,8 @@ def main():
     ap.add_argument("--only", choices=["both", "fp64", "fp32_refine"], default="both",
                     help="which precision paths to time (profiling runs use one)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="HBM budget of the serving context")
     ap.add_argument("--configs", action="store_true",
                     help="also time every workload (FP64 and FP32+refine) into a 'configs' entry")
     ap.add_argument("--print-hash", choices=sorted(KERNELS),
@@ -384,22 +422,34 @@ def main():
     if not args.no_serving:
         from paper_2010_13213_amd import serve
         reqs = inputs.served_stream(args.serve_requests)
-        pool = serve.PlanPool(ctx)
+        budget = int(args.serve_budget_gb * (1 << 30))
+        sctx = lgf.Context(0, hbm_budget_bytes=budget)
+        pool = serve.PlanPool(sctx)
         # plans are resident state: one untimed pass at full concurrency
         # creates every plan the timed passes hold at once
-        serve.serve(ctx, reqs, None, pool=pool)
-        cap = serve.serve(ctx, reqs, None, pool=pool)
-        run = serve.serve(ctx, reqs, 0.9 * cap["requests_per_s"], pool=pool)
+        serve.serve(sctx, reqs, None, pool=pool)
+        cap = serve.serve(sctx, reqs, None, pool=pool)
+        sweep = []
+        for frac in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+            r = serve.serve(sctx, reqs, frac * cap["requests_per_s"], pool=pool)
+            sweep.append({"rate_x_capacity": frac, "rate_requests_per_s": r["rate_req_per_s"],
+                          "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                          "throughput_cells_per_s": r["throughput_cells_per_s"], "mean_batch": r["mean_batch"],
+                          "deferred": r["deferred"], "peak_context_bytes": r["peak_context_bytes"]})
+            print("serving %.2f x capacity: p50 %.2f ms, p99 %.2f ms" % (frac, r["p50_ms"], r["p99_ms"]),
+                  file=sys.stderr, flush=True)
         pool.close()
+        sctx.close()
+        at09 = [r for r in sweep if r["rate_x_capacity"] == 0.9][0]
         out["serving"] = {
             "workload": "%d independent dense-cube solves, side 16..128 cells (8^3 blocks), 1-4 Gaussian "
-                        "blobs, half FP64 / half FP32+refine, Poisson arrivals at 0.9 x capacity"
-                        % len(reqs),
+                        "blobs, half FP64 / half FP32+refine, Poisson arrivals; context HBM budget %.0f GiB"
+                        % (len(reqs), args.serve_budget_gb),
             "capacity_requests_per_s": cap["requests_per_s"],
-            "rate_requests_per_s": run["rate_req_per_s"],
-            "p50_ms": run["p50_ms"], "p99_ms": run["p99_ms"],
-            "throughput_cells_per_s": run["throughput_cells_per_s"],
-            "mean_batch": run["mean_batch"]}
+            "rate_requests_per_s": at09["rate_requests_per_s"],
+            "p50_ms": at09["p50_ms"], "p99_ms": at09["p99_ms"],
+            "throughput_cells_per_s": at09["throughput_cells_per_s"],
+            "mean_batch": at09["mean_batch"], "budget_bytes": budget, "rate_sweep": sweep}
     if args.configs:
         out["configs"] = config_table(ctx)
     if not args.no_cpu_baseline:

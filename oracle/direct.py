@@ -45,6 +45,8 @@ def _load():
         lib.oracle_far_field.argtypes = [ctypes.c_double] * 3
         lib.oracle_far_field.restype = ctypes.c_double
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -59,6 +61,11 @@ def _ip(a):
 
 def num_threads():
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of later direct sums (timing the oracle on fewer cores)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def G_points(ijk):

@@ -156,6 +156,7 @@ class Context:
         _check(lib().lgf_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self._h = h
         self.device = int(device)
+        self.hbm_budget_bytes = int(hbm_budget_bytes)
 
     @property
     def handle(self):

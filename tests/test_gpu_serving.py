@@ -116,3 +116,58 @@ def test_composite_batch_equals_alone_bitwise(gpu_ctx):
             base += n
     for pl in plans:
         pl.close()
+
+
+def _cube_req(L, seed, precision="fp64", rid=0):
+    p = inputs.blob_cube(L, 8, np.random.default_rng(seed))
+    return inputs.Request(rid=rid, problem=p, precision=precision, arrival=0.0)
+
+
+def test_plans_of_equal_block_count_and_other_shape_are_not_shared(gpu_ctx):
+    """2x4x1 and 8x1x1 blocks (8 each) in one served stream: each result
+    meets the oracle (a pool keyed by block count would hand one the
+    other's plan)."""
+    from paper_2010_13213_amd import serve
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i, blocks in enumerate([[(x, y, 0) for y in range(4) for x in range(2)], [(x, 0, 0) for x in range(8)]] * 2):
+        b = np.array(blocks, dtype=np.int32)
+        p = inputs.Problem(nb=8, dx0=1.0, levels=[inputs.Level(blocks=b, values=rng.standard_normal((1, 8, 8, 8, 8)))])
+        reqs.append(inputs.Request(rid=i, problem=p, precision="fp64", arrival=0.0))
+    res = serve.serve(gpu_ctx, reqs, None, keep_results=True, max_batch=1, n_streams=1)
+    assert res["plans_created"] == 2
+    for r, u in zip(reqs, res["u"]):
+        c = inputs.cell_coords(r.problem.levels[0].blocks, 8)
+        ref = direct.direct_sum(c, r.problem.flat_source(), c, 1.0)
+        assert rel_l2(u, ref) < 1e-12
+
+
+def test_request_waits_for_memory_and_the_budget_holds():
+    """A context budget that holds the table, the spectra and one large plan
+    but not two: the second shape waits until the first completes and its
+    idle plan is freed; the context never exceeds the budget, and every
+    result equals the request solved alone."""
+    import torch
+    from paper_2010_13213_amd import lgf, serve
+    big, other = _cube_req(104, 1), _cube_req(96, 2)
+    probe = lgf.Context(0)
+    alone = {}
+    ws = []
+    for r in (big, other):
+        pl = lgf.Plan.for_problem(probe, r.problem, r.precision)
+        ws.append(pl.workspace_bytes())
+        alone[r.problem.name] = pl.solve(torch.from_numpy(r.problem.flat_source()).cuda()).cpu().numpy()
+        pl.close()
+    base = probe.bytes()                       # table and spectra, no plan
+    probe.close()
+    budget = base + max(ws) + min(ws) // 2
+    ctx = lgf.Context(0, hbm_budget_bytes=budget)
+    reqs = [_cube_req(104, 1, rid=0), _cube_req(96, 2, rid=1), _cube_req(104, 1, rid=2), _cube_req(96, 2, rid=3)]
+    print("serving 4 requests under a budget of %d bytes (base %d, plans %s)" % (budget, base, ws), flush=True)
+    res = serve.serve(ctx, reqs, None, keep_results=True)
+    assert res["deferred"] > 0 and res["plans_evicted"] > 0
+    assert res["peak_context_bytes"] <= budget
+    for r, u in zip(reqs, res["u"]):
+        assert np.array_equal(u, alone[r.problem.name])
+    ctx.close()
+    torch.cuda.synchronize()
