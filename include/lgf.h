@@ -165,6 +165,26 @@ lgf_status lgf_solve(lgf_plan *plan, const double *f, double *u, void *stream,
 lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *stream);
 
 /*
+ * Velocity refresh (Sec. 4.1, eq. vel_update): u = -C^dagger L_E^-1 omega on
+ * one level, the velocity recovered from the vorticity on the base level.
+ * plan: a single-level plan with n_components = 3.  Staggering (Sec. 2.1:
+ * vectors on the positive faces and edges of each cell): component c of a
+ * field at cell n is the value on the c-edge (omega, psi) or c-face (u)
+ * that cell owns, n + (e - e_c)/2 resp. n + e_c/2 with e = (1, 1, 1).
+ * omega: device float64 edge vorticity in the plan's field layout
+ * ([component][block][z][y][x]).  psi: caller-owned device array of the same
+ * size that receives the streamfunction L_E^-1 omega (the LGF solve of every
+ * component, as lgf_solve).  u: caller-owned device array of the same size
+ * that receives -C^dagger psi, the curl from edges to faces with backward
+ * differences scaled by 1/dx0 (the adjoint of the forward-difference curl C
+ * of eq. mimetic).  A u component whose stencil needs psi one cell back in a
+ * block outside the support is written as NaN.  omega, psi and u must be
+ * distinct.  Asynchronous on `stream`.  Errors: LGF_E_INVALID (plan shape,
+ * null, misaligned or aliased pointers), LGF_E_DEVICE.
+ */
+lgf_status lgf_velocity_refresh(lgf_plan *plan, const double *omega, double *psi, double *u, void *stream);
+
+/*
  * Solve n independent requests (each the problem of lgf_solve: Sec. 2.2 on
  * one level, the Sec. 3.4 recursion on a composite mesh) together.  Per block
  * size, the single-level requests run component by component, and the

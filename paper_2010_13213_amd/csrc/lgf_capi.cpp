@@ -282,6 +282,25 @@ lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *s
     });
 }
 
+lgf_status lgf_velocity_refresh(lgf_plan *plan, const double *omega, double *psi, double *u, void *stream) {
+    return guard([&] {
+        require(plan != nullptr, "null plan");
+        require(plan->K == 1 && plan->nc == 3, "the velocity refresh needs a single-level plan of 3 components");
+        require(omega && psi && u, "null field pointer");
+        require(((uintptr_t)omega % 8) == 0 && ((uintptr_t)psi % 8) == 0 && ((uintptr_t)u % 8) == 0,
+                "misaligned field pointer");
+        require(psi != omega && psi != u && u != omega, "omega, psi and u must be distinct arrays");
+        DeviceScope ds(plan->ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        run_plan(plan, omega, psi, s, nullptr);
+        StageTimer t(plan->ctx, kStageOther, s);
+        hip_check(curl_backward_blocks(plan->nb, psi, u, plan->comp_len, (const int64_t *)plan->d_blk_off.ptr,
+                                       (const int64_t *)plan->d_blk_back.ptr, (int)plan->levels[0].size(),
+                                       1.0 / plan->dx0, s),
+                  "curl");
+    });
+}
+
 struct lgf_graph {
     lgf_plan *plan = nullptr;
     hipGraph_t graph = nullptr;

@@ -184,6 +184,13 @@ hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *sr
 // p[0, bytes) = 0 by a kernel (bytes and p 16-byte aligned); a memset node
 // is avoided in code that a caller may capture into a graph.
 hipError_t zero_fill(void *p, size_t bytes, hipStream_t s);
+
+// Velocity refresh: u = -C^dagger psi (backward-difference curl, 1/dx) on
+// the blocks of one level, 3 components comp_len apart; nbr_off[3b + a] is
+// the field offset of block b's neighbour one block back along axis a, or -1
+// (lgf_refresh.hip).
+hipError_t curl_backward_blocks(int nb, const double *psi, double *u, int64_t comp_len, const int64_t *blk_off,
+                                const int64_t *nbr_off, int n_blocks, double inv_dx, hipStream_t s);
 struct CorrGeom {
     double dxc, dxf;        // cell widths of levels k-1 and k
     int mlo[3], mdim[3];    // dense map of psi_{k-1} blocks: index or -1

@@ -236,6 +236,8 @@ struct lgf_plan {
     lgf::DeviceBuffer ws_lat;                      // lattice-DFT workspace H, mac_nc regions
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     const lgf::SpecWs *ws_scratch = nullptr;       // set only during a static-scratch solve
+    lgf::DeviceBuffer d_blk_off, d_blk_back;       // single level, 3 components: block offsets and the
+                                                   // offsets of the blocks one back along x, y, z (or -1)
     size_t workspace_bytes() const;
 };
 

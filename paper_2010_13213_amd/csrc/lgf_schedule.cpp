@@ -66,6 +66,22 @@ void build_schedule(lgf_plan *p) {
         p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
         plan_alloc_refine(p, {p->op0.get()});
         plan_alloc_spectral(p);
+        if (p->nc == 3) {      // the velocity refresh's curl reads backward neighbours
+            std::map<Key, int64_t> at;
+            for (const auto &b : p->levels[0]) at[Key(b.ijk[0], b.ijk[1], b.ijk[2])] = b.off;
+            std::vector<int64_t> off, back;
+            for (const auto &b : p->levels[0]) {
+                off.push_back(b.off);
+                for (int a = 0; a < 3; ++a) {
+                    int q[3] = {b.ijk[0], b.ijk[1], b.ijk[2]};
+                    --q[a];
+                    auto it = at.find(Key(q[0], q[1], q[2]));
+                    back.push_back(it == at.end() ? -1 : it->second);
+                }
+            }
+            upload(ctx, p->d_blk_off, off, "block offsets");
+            upload(ctx, p->d_blk_back, back, "backward neighbours");
+        }
         return;
     }
     for (int k = 0; k < K; ++k) p->lv.push_back(std::make_unique<LevelSched>());

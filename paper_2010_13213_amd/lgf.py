@@ -19,7 +19,7 @@ _PREC = {"fp64": LGF_FP64, "fp32_refine": LGF_FP32_REFINE}
 EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "lgf_plan_create",
             "lgf_problem_check",
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
-            "lgf_solve", "lgf_solve_scratch", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
+            "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
             "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
@@ -87,6 +87,8 @@ def lib():
     L.lgf_solve.restype = ctypes.c_int
     L.lgf_solve_scratch.argtypes = [vp, vp, vp, vp]
     L.lgf_solve_scratch.restype = ctypes.c_int
+    L.lgf_velocity_refresh.argtypes = [vp, vp, vp, vp, vp]
+    L.lgf_velocity_refresh.restype = ctypes.c_int
     L.lgf_solve_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(vp), vp, ctypes.POINTER(Report)]
     L.lgf_solve_batch.restype = ctypes.c_int
@@ -316,6 +318,27 @@ class Plan:
         _check(lib().lgf_solve_scratch(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                        _stream_handle(stream)))
         return u
+
+
+def _check_field(t, n, name):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous CUDA float64 tensor of %d elements" % (name, n))
+
+
+def velocity_refresh(plan, omega, psi=None, u=None, stream=None):
+    """lgf_velocity_refresh: u = -C^dagger L_E^-1 omega on a single-level
+    3-component plan; returns (psi, u)."""
+    import torch
+    n = plan.field_len()
+    _check_field(omega, n, "omega")
+    psi = torch.empty_like(omega) if psi is None else psi
+    u = torch.empty_like(omega) if u is None else u
+    _check_field(psi, n, "psi")
+    _check_field(u, n, "u")
+    _check(lib().lgf_velocity_refresh(plan.handle, ctypes.c_void_p(omega.data_ptr()), ctypes.c_void_p(psi.data_ptr()),
+                                      ctypes.c_void_p(u.data_ptr()), _stream_handle(stream)))
+    return psi, u
 
 
 def scratch_max_bytes():
