@@ -185,6 +185,30 @@ lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *s
 lgf_status lgf_velocity_refresh(lgf_plan *plan, const double *omega, double *psi, double *u, void *stream);
 
 /*
+ * Refinement indicator (Sec. 4.2, eqs. refine1, maximumS, refine2): the
+ * criterion is evaluated on the combined source S_k of eq. combined_source,
+ * the right-hand side of level k's phi convolution (k = 0: the cumulative
+ * source F_0; k >= 1: S_k + F_k on the level's source blocks R_k, its blocks
+ * and the extended correction region).
+ *
+ * lgf_plan_source_blocks: the blocks of R_k ([n][3] block coordinates of
+ * level k, the level's blocks for k = 0, the level's blocks dilated by
+ * ne_blocks layers for k >= 1, in the plan's order) into ijk (if non-null);
+ * returns n, or -1 for a bad plan or level.
+ *
+ * lgf_solve_indicator: lgf_solve(plan, f, u, stream, NULL), and on the way,
+ * per component, level and R_k block (host arrays of n_components *
+ * sum_k n_k entries, [component][level][block]), the root mean square of
+ * the combined source over the block's cells into block_rms and its largest
+ * magnitude into block_max.  On one level S is the source f itself.  The
+ * call waits for its stream.  Errors: LGF_E_INVALID (null or misaligned
+ * pointers), LGF_E_DEVICE.
+ */
+int64_t lgf_plan_source_blocks(const lgf_plan *plan, int level, int32_t *ijk);
+lgf_status lgf_solve_indicator(lgf_plan *plan, const double *f, double *u, void *stream, double *block_rms,
+                               double *block_max);
+
+/*
  * Solve n independent requests (each the problem of lgf_solve: Sec. 2.2 on
  * one level, the Sec. 3.4 recursion on a composite mesh) together.  Per block
  * size, the single-level requests run component by component, and the

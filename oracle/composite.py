@@ -239,6 +239,9 @@ class CompositeOracle:
         """
         fhat = [np.where(self.mask[k], f_levels[k], 0.0) for k in range(self.K)]
         F = self.cumulative_sources(fhat)
+        # the combined source of each level's phi convolution (eq.
+        # combined_source; the refinement indicator of Sec. 4.2): cells, values
+        self.combined = [(self.cells[0], F[0].copy())]
         out = []
         psi_cells, psi = None, None
         for k in range(self.K):
@@ -265,6 +268,7 @@ class CompositeOracle:
                 srcf[i2, j2, k2] += fhat[k]
                 vF = srcF[i, j, kk]
                 vf = srcf[i, j, kk]
+                self.combined.append((R, vF.copy()))
                 pr = Box.around(R, 0)
                 Pp = pr.zeros()
                 Pp[i, j, kk] = Ppsi_R

@@ -301,6 +301,42 @@ lgf_status lgf_velocity_refresh(lgf_plan *plan, const double *omega, double *psi
     });
 }
 
+int64_t lgf_plan_source_blocks(const lgf_plan *plan, int level, int32_t *ijk) {
+    if (!plan || level < 0 || level >= (int)plan->src_ijk.size()) return -1;
+    const auto &v = plan->src_ijk[level];
+    if (ijk) std::copy(v.begin(), v.end(), ijk);
+    return (int64_t)v.size() / 3;
+}
+
+lgf_status lgf_solve_indicator(lgf_plan *plan, const double *f, double *u, void *stream, double *block_rms,
+                               double *block_max) {
+    return guard([&] {
+        require(plan != nullptr, "null plan");
+        require(f != nullptr && u != nullptr, "null field pointer");
+        require(((uintptr_t)f % 8) == 0 && ((uintptr_t)u % 8) == 0, "misaligned field pointer");
+        require(block_rms != nullptr && block_max != nullptr, "null statistics arrays");
+        DeviceScope ds(plan->ctx->device);
+        hipStream_t s = (hipStream_t)stream;
+        hip_check(zero_fill(plan->d_ind.ptr, plan->d_ind.bytes, s), "clear indicator");
+        struct Restore {
+            lgf_plan *p;
+            ~Restore() { p->collect = false; }
+        } restore{plan};
+        plan->collect = true;
+        run_plan(plan, f, u, s, nullptr);
+        const size_t n = (size_t)plan->ind_total * plan->nc;
+        std::vector<double> h(2 * n);
+        hip_check(hipMemcpyAsync(h.data(), plan->d_ind.ptr, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s),
+                  "indicator copy");
+        hip_check(hipStreamSynchronize(s), "indicator sync");
+        const double nb3 = (double)plan->nb * plan->nb * plan->nb;
+        for (size_t i = 0; i < n; ++i) {
+            block_rms[i] = std::sqrt(h[2 * i] / nb3);
+            block_max[i] = h[2 * i + 1];
+        }
+    });
+}
+
 struct lgf_graph {
     lgf_plan *plan = nullptr;
     hipGraph_t graph = nullptr;

@@ -236,4 +236,46 @@ hipError_t correction_source(int nb, const CorrGeom &g, const double *psi, const
     return hipGetLastError();
 }
 
+namespace {
+
+// Per block: sum of squares and max |v| of the block's nb^3 values.
+template <int NB>
+__global__ void __launch_bounds__(256) stats_kernel(const double *__restrict__ v, const int64_t *__restrict__ off,
+                                                    double *__restrict__ out) {
+    const int b = blockIdx.x;
+    const double *p = v + (off ? off[b] : (int64_t)b * NB * NB * NB);
+    double ss = 0.0, mx = 0.0;
+    for (int i = threadIdx.x; i < NB * NB * NB; i += 256) {
+        const double a = p[i];
+        ss += a * a;
+        mx = fmax(mx, fabs(a));
+    }
+    __shared__ double s_ss[256], s_mx[256];
+    s_ss[threadIdx.x] = ss;
+    s_mx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_ss[threadIdx.x] += s_ss[threadIdx.x + w];
+            s_mx[threadIdx.x] = fmax(s_mx[threadIdx.x], s_mx[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * b] = s_ss[0];
+        out[2 * b + 1] = s_mx[0];
+    }
+}
+
+}  // namespace
+
+hipError_t block_stats(int nb, const double *v, const int64_t *off, int n_blocks, double *out, hipStream_t s) {
+    if (n_blocks <= 0) return hipSuccess;
+    if (nb == 8)
+        stats_kernel<8><<<n_blocks, 256, 0, s>>>(v, off, out);
+    else
+        stats_kernel<16><<<n_blocks, 256, 0, s>>>(v, off, out);
+    return hipGetLastError();
+}
+
 }  // namespace lgf

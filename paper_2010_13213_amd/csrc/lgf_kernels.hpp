@@ -185,6 +185,10 @@ hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *sr
 // is avoided in code that a caller may capture into a graph.
 hipError_t zero_fill(void *p, size_t bytes, hipStream_t s);
 
+// Per block of nb^3 values at v + off[b] (off null: v + b * nb^3): the sum
+// of squares into out[2b] and the largest magnitude into out[2b + 1].
+hipError_t block_stats(int nb, const double *v, const int64_t *off, int n_blocks, double *out, hipStream_t s);
+
 // Velocity refresh: u = -C^dagger psi (backward-difference curl, 1/dx) on
 // the blocks of one level, 3 components comp_len apart; nbr_off[3b + a] is
 // the field offset of block b's neighbour one block back along axis a, or -1

@@ -236,8 +236,17 @@ struct lgf_plan {
     lgf::DeviceBuffer ws_lat;                      // lattice-DFT workspace H, mac_nc regions
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     const lgf::SpecWs *ws_scratch = nullptr;       // set only during a static-scratch solve
-    lgf::DeviceBuffer d_blk_off, d_blk_back;       // single level, 3 components: block offsets and the
+    lgf::DeviceBuffer d_blk_off, d_blk_back;       // single level: block offsets; with 3 components also the
                                                    // offsets of the blocks one back along x, y, z (or -1)
+    // refinement indicator: the source blocks R_k of every level (level 0:
+    // its blocks; k >= 1: its blocks dilated by ne layers) and, while
+    // `collect` is set, per (component, level, R_k block) the sum of squares
+    // and max |.| of the combined source of the level's phi convolution
+    std::vector<std::vector<int32_t>> src_ijk;
+    std::vector<int64_t> ind_base;
+    int64_t ind_total = 0;
+    lgf::DeviceBuffer d_ind;
+    bool collect = false;
     size_t workspace_bytes() const;
 };
 

@@ -66,22 +66,28 @@ void build_schedule(lgf_plan *p) {
         p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
         plan_alloc_refine(p, {p->op0.get()});
         plan_alloc_spectral(p);
+        std::map<Key, int64_t> at;
+        std::vector<int64_t> off, back;
+        p->src_ijk.assign(1, {});
+        for (const auto &b : p->levels[0]) {
+            at[Key(b.ijk[0], b.ijk[1], b.ijk[2])] = b.off;
+            off.push_back(b.off);
+            p->src_ijk[0].insert(p->src_ijk[0].end(), b.ijk, b.ijk + 3);
+        }
+        upload(ctx, p->d_blk_off, off, "block offsets");
         if (p->nc == 3) {      // the velocity refresh's curl reads backward neighbours
-            std::map<Key, int64_t> at;
-            for (const auto &b : p->levels[0]) at[Key(b.ijk[0], b.ijk[1], b.ijk[2])] = b.off;
-            std::vector<int64_t> off, back;
-            for (const auto &b : p->levels[0]) {
-                off.push_back(b.off);
+            for (const auto &b : p->levels[0])
                 for (int a = 0; a < 3; ++a) {
                     int q[3] = {b.ijk[0], b.ijk[1], b.ijk[2]};
                     --q[a];
                     auto it = at.find(Key(q[0], q[1], q[2]));
                     back.push_back(it == at.end() ? -1 : it->second);
                 }
-            }
-            upload(ctx, p->d_blk_off, off, "block offsets");
             upload(ctx, p->d_blk_back, back, "backward neighbours");
         }
+        p->ind_base = {0};
+        p->ind_total = (int64_t)p->levels[0].size();
+        p->d_ind.alloc(ctx, sizeof(double) * 2 * p->ind_total * p->nc, "indicator statistics");
         return;
     }
     for (int k = 0; k < K; ++k) p->lv.push_back(std::make_unique<LevelSched>());
@@ -224,6 +230,22 @@ void build_schedule(lgf_plan *p) {
             upload(ctx, L.d_cp_dst, cp_d, "copy offsets");
         }
     }
+    // refinement-indicator bookkeeping: R_0 = level 0's blocks, R_k = ext[k]
+    p->src_ijk.assign(K, {});
+    for (const auto &b : p->levels[0]) p->src_ijk[0].insert(p->src_ijk[0].end(), b.ijk, b.ijk + 3);
+    for (int k = 1; k < K; ++k)
+        for (const Key &q : ext[k]) {
+            p->src_ijk[k].push_back(std::get<0>(q));
+            p->src_ijk[k].push_back(std::get<1>(q));
+            p->src_ijk[k].push_back(std::get<2>(q));
+        }
+    p->ind_base.clear();
+    p->ind_total = 0;
+    for (int k = 0; k < K; ++k) {
+        p->ind_base.push_back(p->ind_total);
+        p->ind_total += (int64_t)p->src_ijk[k].size() / 3;
+    }
+    p->d_ind.alloc(ctx, sizeof(double) * 2 * p->ind_total * p->nc, "indicator statistics");
     // workspaces: mac_nc component regions each (the components of one MAC group)
     const int64_t m = p->mac_nc;
     p->dom_len = std::max<int64_t>(1, max_dom) * nb3;
@@ -283,7 +305,13 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
             const double dxk = p->dx0 / (double)(1 << k);
             double *psi_prev = (double *)p->ws_psi[cur].ptr;
             double *psi_next = (double *)p->ws_psi[cur ^ 1].ptr;
+            double *ind = (double *)p->d_ind.ptr;
             if (k == 0) {
+                if (p->collect)
+                    for (int c = 0; c < ng; ++c)
+                        hip_check(block_stats(nb, FC + c * CL, (const int64_t *)L.d_own_off.ptr, L.n_own,
+                                              ind + 2 * ((c0 + c) * p->ind_total + p->ind_base[0]), s),
+                                  "indicator");
                 run_op(p, *L.convF, FC, CL, ug, CL, ng, dxk, 0, s);
                 if (L.convPsi) run_op(p, *L.convPsi, FH, CL, psi_next, DL, ng, dxk, 0, s);
             } else {
@@ -296,6 +324,10 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
                     hip_check(copy_blocks(nb, PP + c * EL, ug + c * CL, (const int64_t *)L.d_cu_src.ptr,
                                           (const int64_t *)L.d_cu_dst.ptr, L.n_own, s),
                               "P psi -> phi");
+                    if (p->collect)
+                        hip_check(block_stats(nb, SF + c * EL, nullptr, L.n_ext,
+                                              ind + 2 * ((c0 + c) * p->ind_total + p->ind_base[k]), s),
+                                  "indicator");
                 }
                 run_op(p, *L.convF, SF, EL, ug, CL, ng, dxk, 1, s);
                 if (L.convPsi) {
@@ -322,6 +354,11 @@ static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
         enqueue_composite(p, f, u, s);
         return;
     }
+    if (p->collect)      // one level: the combined source is the source itself
+        for (int c = 0; c < p->nc; ++c)
+            hip_check(block_stats(p->nb, f + (size_t)c * p->comp_len, (const int64_t *)p->d_blk_off.ptr,
+                                  (int)p->levels[0].size(), (double *)p->d_ind.ptr + 2 * c * p->ind_total, s),
+                      "indicator");
     run_op(p, *p->op0, f, p->comp_len, u, p->comp_len, p->nc, p->dx0, 0, s);
 }
 

@@ -19,7 +19,8 @@ _PREC = {"fp64": LGF_FP64, "fp32_refine": LGF_FP32_REFINE}
 EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "lgf_plan_create",
             "lgf_problem_check",
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
-            "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
+            "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_indicator",
+            "lgf_plan_source_blocks", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
             "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
@@ -89,6 +90,10 @@ def lib():
     L.lgf_solve_scratch.restype = ctypes.c_int
     L.lgf_velocity_refresh.argtypes = [vp, vp, vp, vp, vp]
     L.lgf_velocity_refresh.restype = ctypes.c_int
+    L.lgf_solve_indicator.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.lgf_solve_indicator.restype = ctypes.c_int
+    L.lgf_plan_source_blocks.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+    L.lgf_plan_source_blocks.restype = ctypes.c_int64
     L.lgf_solve_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(vp), vp, ctypes.POINTER(Report)]
     L.lgf_solve_batch.restype = ctypes.c_int
@@ -258,6 +263,7 @@ class Plan:
     def __init__(self, ctx, level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0):
         self.ctx = ctx
         self.nb = int(nb)
+        self.n_levels = len(level_blocks)
         self.n_components = int(n_components)
         self.precision = precision
         prob, self._keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks)
@@ -306,6 +312,34 @@ class Plan:
         _check(lib().lgf_solve(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                _stream_handle(stream), ctypes.byref(rep) if rep is not None else None))
         return (u, rep) if report else u
+
+    def source_blocks(self, level):
+        """Blocks of the level's combined source R_k ((n, 3) int32)."""
+        n = int(lib().lgf_plan_source_blocks(self._h, int(level), None))
+        if n < 0:
+            raise ValueError("no level %d" % level)
+        out = np.empty((n, 3), dtype=np.int32)
+        lib().lgf_plan_source_blocks(self._h, int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return out
+
+    def solve_indicator(self, f, u=None, stream=None):
+        """lgf_solve_indicator: returns (u, rms, max), rms / max as lists per
+        component of lists per level of per-block arrays."""
+        import torch
+        n = self.field_len()
+        _check_field(f, n, "f")
+        u = torch.empty_like(f) if u is None else u
+        _check_field(u, n, "u")
+        counts = [len(self.source_blocks(k)) for k in range(self.n_levels)]
+        tot = sum(counts) * self.n_components
+        rms = np.empty(tot)
+        mx = np.empty(tot)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().lgf_solve_indicator(self._h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                         _stream_handle(stream), rms.ctypes.data_as(dp), mx.ctypes.data_as(dp)))
+        split = np.cumsum(counts)[:-1]
+        per = lambda a: [np.split(r, split) for r in a.reshape(self.n_components, -1)]
+        return u, per(rms), per(mx)
 
     def solve_scratch(self, f, u, stream=None):
         """lgf_solve_scratch: the same solve with the spectral workspace in the
