@@ -114,6 +114,26 @@ size_t lgf_context_bytes(const lgf_context *ctx);
 lgf_status lgf_plan_create(lgf_context *ctx, const lgf_problem *desc, lgf_plan **out);
 
 /*
+ * Integrating factor (Sec. 2.3, eqs. heat, IF-single; Sec. 3.5, eq.
+ * FIF-AMR).  A plan whose solves apply H(a) = exp(a L), the solution
+ * operator of the discrete heat equation over a time kappa (t - tau), with
+ * a = kappa (t - tau) / dx^2 for the unscaled 7-point L, instead of L^-1:
+ * u = E * f with the kernel E(n) = prod_i e^{-2a} I_{n_i}(2a) (tabulated in
+ * float64 on the device for |n_i| <= lgf_table_radius(), 0 beyond, where it
+ * is below 1e-300 for any a of interest).  a0 is a on level 0; level k uses
+ * a_k = 4^k a0 (dx_k = dx0 / 2^k).  On a composite mesh the solve returns
+ * Gamma H P f^: per level k the composite source on the level's blocks and
+ * the extended region (the cumulative F_k plus the interpolation of the
+ * coarser levels' sources, q_0 = f^_0, q_k = P q_{k-1} + f^_k), convolved
+ * with E(a_k) and restricted to Omega_k.  The plan is used with lgf_solve,
+ * lgf_solve_scratch, lgf_solve_batch (composite integrating-factor plans run
+ * one after another inside a batch) and the graph calls.  precision must be
+ * LGF_FP64 (else LGF_E_UNSUPPORTED); other errors as lgf_plan_create, and
+ * LGF_E_INVALID for a0 not in (0, 1e6].
+ */
+lgf_status lgf_plan_create_if(lgf_context *ctx, const lgf_problem *desc, double a0, lgf_plan **out);
+
+/*
  * Validate a problem description on the host only (no device work): the
  * same checks lgf_plan_create applies before it builds anything.  Returns
  * LGF_OK or LGF_E_INVALID with the reason in lgf_last_error().

@@ -186,7 +186,9 @@ void lgf_context_destroy(lgf_context *ctx) {
     }
     ctx->pending.clear();
     ring_free(ctx);
+    ctx->lat_tables.clear();
     ctx->tables.clear();
+    ctx->if_cubes.clear();
     ctx->gcube.release();
     if (ctx->stream) hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -206,6 +208,31 @@ lgf_status lgf_plan_create(lgf_context *ctx, const lgf_problem *desc, lgf_plan *
     lgf_status st = guard([&] {
         DeviceScope ds(ctx->device);
         validate_and_copy(p, desc);
+        build_schedule(p);
+    });
+    if (st != LGF_OK) {
+        lgf_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return LGF_OK;
+}
+
+lgf_status lgf_plan_create_if(lgf_context *ctx, const lgf_problem *desc, double a0, lgf_plan **out) {
+    if (!ctx || !out) {
+        set_error("null context or out pointer");
+        return LGF_E_INVALID;
+    }
+    *out = nullptr;
+    lgf_plan *p = new lgf_plan();
+    p->ctx = ctx;
+    lgf_status st = guard([&] {
+        require(a0 > 0.0 && std::isfinite(a0) && a0 <= 1.0e6, "a0 must be positive and at most 1e6");
+        DeviceScope ds(ctx->device);
+        validate_and_copy(p, desc);
+        if (p->prec != LGF_FP64)
+            throw Failure(LGF_E_UNSUPPORTED, "the integrating factor is applied in float64 only");
+        p->if_a0 = a0;
         build_schedule(p);
     });
     if (st != LGF_OK) {
@@ -285,7 +312,8 @@ lgf_status lgf_solve_scratch(lgf_plan *plan, const double *f, double *u, void *s
 lgf_status lgf_velocity_refresh(lgf_plan *plan, const double *omega, double *psi, double *u, void *stream) {
     return guard([&] {
         require(plan != nullptr, "null plan");
-        require(plan->K == 1 && plan->nc == 3, "the velocity refresh needs a single-level plan of 3 components");
+        require(plan->K == 1 && plan->nc == 3 && plan->if_a0 == 0.0,
+                "the velocity refresh needs a single-level LGF plan of 3 components");
         require(omega && psi && u, "null field pointer");
         require(((uintptr_t)omega % 8) == 0 && ((uintptr_t)psi % 8) == 0 && ((uintptr_t)u % 8) == 0,
                 "misaligned field pointer");
@@ -434,7 +462,7 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
         t.data.alloc(ctx, 16 * n_off * n_freq, "spectrum");
         DeviceBuffer scratch;
         scratch.alloc(ctx, 16 * n_freq * std::min<size_t>(n_off, 512), "spectrum scratch");
-        hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, ax, ay, az, false, t.data.ptr, scratch.ptr,
+        hip_check(build_spectra((const double *)ctx->gcube.ptr, true, nb, ax, ay, az, false, t.data.ptr, scratch.ptr,
                                 scratch.bytes, ctx->stream),
                   "build_spectra");
         hip_check(hipStreamSynchronize(ctx->stream), "sync");

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(256) correction_kernel(CorrGeom g, const doubl
                             at(x, y, z + 1) + at(x, y, z - 1) - 6.0 * pp) *
                            ifd2;
         const double plp = trilinear<CL>(clp, q0x + 1, q0y + 1, q0z + 1, fx, fy, fz);
-        const double S = plp - lpp;
+        const double S = g.interp_only ? pp : plp - lpp;
         Ppsi[base + i] = pp;
         const double fk = oo >= 0 ? Fk[oo + i] : 0.0;
         const double hk = oo >= 0 ? fhk[oo + i] : 0.0;

@@ -192,6 +192,19 @@ __device__ __forceinline__ double lgf_G(const double *__restrict__ gc, int nx, i
     return lgf_far((double)a, (double)b, (double)c);
 }
 
+// The kernel of a convolution at lattice offset n: the LGF (far = true: the
+// near cube, then the asymptotic series), or a kernel tabulated on the same
+// cube that vanishes beyond it (far = false: the integrating factor).
+__device__ __forceinline__ double kernel_at(const double *__restrict__ gc, bool far, int nx, int ny, int nz) {
+    if (far) return lgf_G(gc, nx, ny, nz);
+    const int a = abs(nx), b = abs(ny), c = abs(nz);
+    if (a <= kTableRadius && b <= kTableRadius && c <= kTableRadius) {
+        const int s = kTableRadius + 1;
+        return gc[((size_t)a * s + b) * s + c];
+    }
+    return 0.0;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (hardware id b lands
 // on XCD b mod 8); renumber them so that consecutive logical ids run on the
 // same XCD and share its L2.  A bijection on [0, n) for any n.

@@ -13,8 +13,11 @@ hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int
 // Spectra of every block offset in [0,XH] x [0,YH] x [0,ZH] into
 // table[omega][dy][dz][dx] (complex float or double); offsets with negative
 // components are served by reflection.
-hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bool fp32, void *table,
+hipError_t build_spectra(const double *gcube, bool far, int nb, int XH, int YH, int ZH, bool fp32, void *table,
                          void *scratch, size_t scratch_bytes, hipStream_t s);
+// Integrating-factor kernel E(n) = prod_i e^{-2a} I_{n_i}(2a) on the near
+// cube layout (row: kTableRadius + 1 doubles of scratch, w: one double).
+hipError_t build_if_table(double *cube, double *row, double *w, double a, hipStream_t s);
 
 // ---- block FFTs (lgf_fft.hip) ----
 // Spectral workspaces hold spectrum value omega = (kz N + ky) H + kx (of
@@ -198,10 +201,11 @@ hipError_t curl_backward_blocks(int nb, const double *psi, double *u, int64_t co
 struct CorrGeom {
     double dxc, dxf;        // cell widths of levels k-1 and k
     int mlo[3], mdim[3];    // dense map of psi_{k-1} blocks: index or -1
+    int interp_only;        // 1: no commutator -- the outputs are P psi, P psi + F_k, P psi + f^_k
 };
 // For each level-k block fblk[b] (x,y,z): P psi_{k-1}, and S + F_k, S + f^_k
 // (F_k, f^_k read at own_off[b] when >= 0, else 0) into block b of the
-// compact outputs.
+// compact outputs; with interp_only, P psi in place of S.
 hipError_t correction_source(int nb, const CorrGeom &g, const double *psi, const int *cmap, const int *fblk,
                              const int64_t *own_off, const double *Fk, const double *fhk, double *Ppsi,
                              double *SrcF, double *Srcf, int n_blocks, hipStream_t s);

@@ -139,13 +139,33 @@ void build_context_table(lgf_context *ctx) {
     hip_check(hipStreamSynchronize(ctx->stream), "table sync");
 }
 
-SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH) {
+// The integrating-factor kernel cube for a (caller holds ctx->mu).
+static const double *if_cube(lgf_context *ctx, double a) {
+    auto it = ctx->if_cubes.find(a);
+    if (it != ctx->if_cubes.end()) return (const double *)it->second->ptr;
+    const int S = kTableRadius + 1;
+    auto cube = std::make_unique<DeviceBuffer>();
+    cube->alloc(ctx, sizeof(double) * (size_t)S * S * S, "integrating-factor table");
+    DeviceBuffer row, w;
+    row.alloc(ctx, sizeof(double) * S, "Bessel row");
+    w.alloc(ctx, sizeof(double), "quadrature weight");
+    hip_check(build_if_table((double *)cube->ptr, (double *)row.ptr, (double *)w.ptr, a, ctx->stream),
+              "build_if_table");
+    hip_check(hipStreamSynchronize(ctx->stream), "if table sync");
+    const double *p = (const double *)cube->ptr;
+    ctx->if_cubes[a] = std::move(cube);
+    return p;
+}
+
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, double ka) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &t : ctx->tables)
-        if (t->nb == nb && t->fp32 == fp32 && t->XH >= XH && t->YH >= YH && t->ZH >= ZH) return t.get();
+        if (t->nb == nb && t->fp32 == fp32 && t->ka == ka && t->XH >= XH && t->YH >= YH && t->ZH >= ZH)
+            return t.get();
     auto t = std::make_unique<SpecTable>();
     t->nb = nb;
     t->fp32 = fp32;
+    t->ka = ka;
     t->XH = XH;
     t->YH = YH;
     t->ZH = ZH;
@@ -158,8 +178,9 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     const size_t per_off = (size_t)t->n_freq * 16;
     const size_t want = std::min<size_t>(n_off, 2048) * per_off;
     scratch.alloc(ctx, want, "spectra scratch");
-    hip_check(build_spectra((const double *)ctx->gcube.ptr, nb, XH, YH, ZH, fp32, t->data.ptr, scratch.ptr,
-                            scratch.bytes, ctx->stream),
+    const double *kern = ka > 0.0 ? if_cube(ctx, ka) : (const double *)ctx->gcube.ptr;
+    hip_check(build_spectra(kern, ka <= 0.0, nb, XH, YH, ZH, fp32, t->data.ptr, scratch.ptr, scratch.bytes,
+                            ctx->stream),
               "build_spectra");
     hip_check(hipStreamSynchronize(ctx->stream), "spectra sync");
     {
@@ -189,10 +210,11 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     return ctx->tables.back().get();
 }
 
-LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz) {
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, double ka) {
     auto find = [&]() -> LatSpec * {
         for (auto &t : ctx->lat_tables)
-            if (t->nb == nb && t->fp32 == fp32 && t->lx == lx && t->ly == ly && t->lz == lz) return t.get();
+            if (t->nb == nb && t->fp32 == fp32 && t->ka == ka && t->lx == lx && t->ly == ly && t->lz == lz)
+                return t.get();
         return nullptr;
     };
     {
@@ -200,10 +222,11 @@ LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, in
         if (LatSpec *t = find()) return t;
     }
     // offsets up to L/2 - 1 per axis
-    SpecTable *oct = get_spectra(ctx, nb, fp32, lx / 2 - 1, ly / 2 - 1, lz / 2 - 1);
+    SpecTable *oct = get_spectra(ctx, nb, fp32, lx / 2 - 1, ly / 2 - 1, lz / 2 - 1, ka);
     auto t = std::make_unique<LatSpec>();
     t->nb = nb;
     t->fp32 = fp32;
+    t->ka = ka;
     t->lx = lx;
     t->ly = ly;
     t->lz = lz;
@@ -303,8 +326,8 @@ static void build_conv_lattice(lgf_plan *plan, Conv &c, const std::vector<Blk> &
     c.fp32 = fp32;
     c.n_src = (int)src.size();
     c.n_tgt = (int)tgt.size();
-    c.lspec = get_lat_spectra(ctx, plan->nb, fp32, c.lx, c.ly, c.lz);
-    c.spec = get_spectra(ctx, plan->nb, fp32, c.lx / 2 - 1, c.ly / 2 - 1, c.lz / 2 - 1);
+    c.lspec = get_lat_spectra(ctx, plan->nb, fp32, c.lx, c.ly, c.lz, plan->build_ka);
+    c.spec = get_spectra(ctx, plan->nb, fp32, c.lx / 2 - 1, c.ly / 2 - 1, c.lz / 2 - 1, plan->build_ka);
     std::vector<int> s_slot, t_slot;
     std::vector<int64_t> s_off, t_off;
     auto slot_of = [&](const Blk &b) {
@@ -519,8 +542,8 @@ static void build_conv_tile(lgf_plan *plan, Conv &c, const std::vector<Blk> &src
     c.n_src = (int)src.size();
     c.n_tgt = (int)tgt.size();
     // the spectra table is indexed by lattice offsets
-    c.spec = axis == 1 ? get_spectra(ctx, nb, fp32, c.ey - 1, rs - 1, c.ez - 1)
-                       : get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1);
+    c.spec = axis == 1 ? get_spectra(ctx, nb, fp32, c.ey - 1, rs - 1, c.ez - 1, plan->build_ka)
+                       : get_spectra(ctx, nb, fp32, rs - 1, c.ey - 1, c.ez - 1, plan->build_ka);
     upload_slots(ctx, c, s_slot, t_slot, s_off, t_off);
 }
 
@@ -1005,7 +1028,7 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
         StageTimer t(plan->ctx, 2, s);
         hip_check(block_fft_inverse(nb, c.fp32, (char *)ws.uhat + k * fs * elem, c.n_slots,
                                     c.method == kMethodLattice, (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
-                                    dst + (size_t)k * dstride, dx * dx / N3, accumulate, s),
+                                    dst + (size_t)k * dstride, conv_scale(plan, dx) / N3, accumulate, s),
                   "inverse block FFT");
     }
 }

@@ -53,6 +53,7 @@ struct DeviceBuffer {
 struct SpecTable {
     int nb = 0;
     bool fp32 = false;
+    double ka = 0.0;        // kernel: 0 the LGF, > 0 the integrating factor E(a = ka)
     int XH = 0, YH = 0, ZH = 0;
     int n_freq = 0;
     DeviceBuffer data;
@@ -82,6 +83,7 @@ struct JobRing {
 struct LatSpec {
     int nb = 0;
     bool fp32 = false;
+    double ka = 0.0;              // kernel, as SpecTable::ka
     int lx = 0, ly = 0, lz = 0;
     int n_freq = 0;
     DeviceBuffer data;
@@ -118,6 +120,7 @@ struct lgf_context_impl {
     DeviceBuffer gcube;
     std::vector<std::unique_ptr<SpecTable>> tables;
     std::vector<std::unique_ptr<LatSpec>> lat_tables;
+    std::map<double, std::unique_ptr<DeviceBuffer>> if_cubes;   // integrating-factor kernels by a
     std::mutex mu;
     lgf_context_impl(int dev, size_t budget_);
 };
@@ -203,13 +206,16 @@ struct LevelSched {
     std::unique_ptr<ConvOp> convF, convPsi;
 };
 
-SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH);
-LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz);
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, double ka);
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, double ka);
 LatGeom lat_geom(const Conv &c, int nc);
 // every slot of the convolution holds a source block: its forward FFTs
 // write the whole spectral region it reads
 inline bool fhat_full(const Conv &c) { return (int64_t)c.n_src == c.n_slots; }
 SmacGeom conv_geom(const Conv &c, const SubConv &p);
+// Factor of the spectral convolution's result: dx^2 for L_dx^-1 = dx^2 G *,
+// 1 for the integrating factor (its kernel already carries dx through a).
+inline double conv_scale(const lgf_plan *p, double dx);
 
 }  // namespace lgf
 
@@ -236,6 +242,10 @@ struct lgf_plan {
     lgf::DeviceBuffer ws_lat;                      // lattice-DFT workspace H, mac_nc regions
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     const lgf::SpecWs *ws_scratch = nullptr;       // set only during a static-scratch solve
+    double if_a0 = 0.0;                            // > 0: integrating-factor plan, a on level 0 (a_k = 4^k a0)
+    double build_ka = 0.0;                         // kernel of the convolutions being built (0: the LGF)
+    int n_q0 = 0;                                  // integrating factor, composite: level-0 blocks in dom(psi_0)
+    lgf::DeviceBuffer d_q0_src, d_q0_dst;
     lgf::DeviceBuffer d_blk_off, d_blk_back;       // single level: block offsets; with 3 components also the
                                                    // offsets of the blocks one back along x, y, z (or -1)
     // refinement indicator: the source blocks R_k of every level (level 0:
@@ -251,6 +261,7 @@ struct lgf_plan {
 };
 
 namespace lgf {
+inline double conv_scale(const lgf_plan *p, double dx) { return p->if_a0 > 0.0 ? 1.0 : dx * dx; }
 // Timed stages: block FFT forward, block-pair MAC, block FFT inverse, other,
 // lattice x DFTs, lattice y/z slabs (DFTs, product, inverse DFTs), lattice
 // inverse x DFTs.

@@ -62,6 +62,8 @@ void build_schedule(lgf_plan *p) {
     const int nb = p->nb, K = p->K;
     const int64_t nb3 = (int64_t)nb * nb * nb;
     p->mac_nc = std::min(p->nc, kMacComponents);
+    const bool fif = p->if_a0 > 0.0;
+    p->build_ka = fif ? p->if_a0 : 0.0;
     if (K == 1) {
         p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
         plan_alloc_refine(p, {p->op0.get()});
@@ -162,11 +164,13 @@ void build_schedule(lgf_plan *p) {
     for (int k = 0; k < K; ++k) {
         LevelSched &L = *p->lv[k];
         // convolution of the phi right-hand side: sources -> Omega_k targets
+        // (the integrating factor of level k has a_k = 4^k a_0)
         std::vector<Blk> src = (k == 0) ? p->levels[0] : as_blk(ext[k]);
+        if (fif) p->build_ka = p->if_a0 * (double)(1 << (2 * k));
         L.convF = build_op(p, src, p->levels[k], refine);
         if (k + 1 < K) {
             std::vector<Blk> tgt = as_blk(dom[k]);
-            L.convPsi = build_op(p, src, tgt, refine);
+            if (!fif) L.convPsi = build_op(p, src, tgt, refine);
             L.n_dom = (int)dom[k].size();
             max_dom = std::max<int64_t>(max_dom, L.n_dom);
             // dense map of dom(psi_k) for the level-(k+1) correction
@@ -229,6 +233,21 @@ void build_schedule(lgf_plan *p) {
             upload(ctx, L.d_cp_src, cp_s, "copy offsets");
             upload(ctx, L.d_cp_dst, cp_d, "copy offsets");
         }
+    }
+    if (fif) {      // q_0 = f^_0 on dom(psi_0): the level-0 blocks inside it, the rest 0
+        std::map<Key, int> didx;
+        for (size_t i = 0; i < dom[0].size(); ++i) didx[dom[0][i]] = (int)i;
+        std::vector<int64_t> qs, qd;
+        for (const auto &b : p->levels[0]) {
+            auto it = didx.find(Key(b.ijk[0], b.ijk[1], b.ijk[2]));
+            if (it == didx.end()) continue;
+            qs.push_back(b.off);
+            qd.push_back((int64_t)it->second * nb3);
+        }
+        p->n_q0 = (int)qs.size();
+        upload(ctx, p->d_q0_src, qs, "q0 offsets");
+        upload(ctx, p->d_q0_dst, qd, "q0 offsets");
+        for (int k = 1; k < K; ++k) p->lv[k]->corr.interp_only = 1;
     }
     // refinement-indicator bookkeeping: R_0 = level 0's blocks, R_k = ext[k]
     p->src_ijk.assign(K, {});
@@ -349,9 +368,84 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
     }
 }
 
+// Integrating factor on the composite mesh (paper Sec. 3.5, eq. FIF-AMR):
+// phi = Gamma H P f^.  Per level k the composite source P f^ on R_k is the
+// cumulative F_k (f^_k plus the coarsening of finer levels) plus the
+// interpolation P q_{k-1} of the coarser-level sources, q_0 = f^_0,
+// q_k = P q_{k-1} + f^_k; then phi_k = H(a_k) of it on Omega_k.
+static void enqueue_fif(lgf_plan *p, const double *f, double *u, hipStream_t s) {
+    const int K = p->K, nb = p->nb;
+    const int64_t CL = p->comp_len, DL = p->dom_len, EL = p->ext_len;
+    double *FH = (double *)p->ws_fhat.ptr, *FC = (double *)p->ws_F.ptr;
+    double *PP = (double *)p->ws_ppsi.ptr, *SF = (double *)p->ws_srcF.ptr, *Sf = (double *)p->ws_srcf.ptr;
+    for (int c0 = 0; c0 < p->nc; c0 += kMacComponents) {
+        const int ng = std::min(kMacComponents, p->nc - c0);
+        const double *fg = f + (size_t)c0 * CL;
+        double *ug = u + (size_t)c0 * CL;
+        StageTimer tm(p->ctx, 3, s);
+        for (int c = 0; c < ng; ++c)
+            for (int k = 0; k < K; ++k) {
+                const LevelSched &L = *p->lv[k];
+                hip_check(mask_blocks(nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                      (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr, L.n_own,
+                                      s),
+                          "mask sources");
+                hip_check(copy_blocks(nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                      (const int64_t *)L.d_own_off.ptr, L.n_own, s),
+                          "copy sources");
+            }
+        for (int c = 0; c < ng; ++c)
+            for (int k = K - 2; k >= 0; --k) {
+                const LevelSched &L = *p->lv[k];
+                hip_check(coarsen_mean8(nb, FC + c * CL, FC + c * CL, (const int64_t *)L.d_cf_fine.ptr,
+                                        (const int64_t *)L.d_cf_coarse.ptr, (const unsigned char *)L.d_cf_oct.ptr,
+                                        L.n_cf, s),
+                          "coarsen");
+            }
+        int cur = 0;
+        for (int k = 0; k < K; ++k) {
+            const LevelSched &L = *p->lv[k];
+            const double dxk = p->dx0 / (double)(1 << k);
+            double *q_prev = (double *)p->ws_psi[cur].ptr;
+            double *q_next = (double *)p->ws_psi[cur ^ 1].ptr;
+            if (k == 0) {
+                run_op(p, *L.convF, FC, CL, ug, CL, ng, dxk, 0, s);
+                hip_check(zero_fill(q_next, sizeof(double) * (size_t)DL * ng, s), "clear q");
+                for (int c = 0; c < ng; ++c)
+                    hip_check(copy_blocks(nb, FH + c * CL, q_next + c * DL, (const int64_t *)p->d_q0_src.ptr,
+                                          (const int64_t *)p->d_q0_dst.ptr, p->n_q0, s),
+                              "q0");
+            } else {
+                for (int c = 0; c < ng; ++c)
+                    hip_check(correction_source(nb, L.corr, q_prev + c * DL, (const int *)L.d_cmap.ptr,
+                                                (const int *)L.d_fblk.ptr, (const int64_t *)L.d_ext_own.ptr,
+                                                FC + c * CL, FH + c * CL, PP + c * EL, SF + c * EL, Sf + c * EL,
+                                                L.n_ext, s),
+                              "interpolate q");
+                run_op(p, *L.convF, SF, EL, ug, CL, ng, dxk, 0, s);
+                if (k + 1 < K)
+                    for (int c = 0; c < ng; ++c)
+                        hip_check(copy_blocks(nb, Sf + c * EL, q_next + c * DL, (const int64_t *)L.d_cp_src.ptr,
+                                              (const int64_t *)L.d_cp_dst.ptr, L.n_dom, s),
+                                  "q");
+            }
+            if (L.any_cover)
+                for (int c = 0; c < ng; ++c)
+                    hip_check(mask_blocks(nb, ug + c * CL, ug + c * CL, (const int64_t *)L.d_own_off.ptr,
+                                          (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
+                                          L.n_own, s),
+                              "restrict phi");
+            cur ^= 1;
+        }
+    }
+}
+
 static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
     if (p->K > 1) {
-        enqueue_composite(p, f, u, s);
+        if (p->if_a0 > 0.0)
+            enqueue_fif(p, f, u, s);
+        else
+            enqueue_composite(p, f, u, s);
         return;
     }
     if (p->collect)      // one level: the combined source is the source itself
@@ -554,7 +648,7 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
             j.spec = k.p->Uhat.ptr;
             j.n_slots = k.c->n_slots;
             j.block_major = k.c->method == kMethodLattice;
-            j.scale = k.dx * k.dx / N3;
+            j.scale = conv_scale(k.p, k.dx) / N3;
             j.accumulate = k.accumulate;
             j.blk_begin = total;
             total += k.c->n_tgt;
@@ -732,6 +826,8 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         for (int i : kv.second) {
             if (plans[i]->K == 1) {
                 single.push_back(i);
+            } else if (plans[i]->if_a0 > 0.0) {   // integrating factor on a composite mesh: its own schedule
+                enqueue(plans[i], f[i], u[i], s);
             } else {
                 cps.push_back(plans[i]);
                 cfs.push_back(f[i]);

@@ -124,6 +124,7 @@ __global__ void eval_points_kernel(const double *__restrict__ gc, const int *__r
 struct SpecGeom {
     int nb, XH, YH, ZH, XD, YD, ZD;
     int o_begin, o_count;   // linear offset range [o_begin, o_begin + o_count)
+    int far;                // 1: the LGF (cube + asymptotic series); 0: a cube kernel, 0 beyond it
 };
 
 __device__ __forceinline__ void offset_of(const SpecGeom &g, int o, int &dx, int &dy, int &dz) {
@@ -153,7 +154,7 @@ __global__ void spec_pass_x(const double *__restrict__ gc, SpecGeom g, cplx<doub
     for (int x = 0; x < N; ++x) {
         double v = 0.0;
         if (!zero_row && x != N / 2)
-            v = lgf_G(gc, dx * g.nb + circ<N>(x), dy * g.nb + circ<N>(y), dz * g.nb + circ<N>(z));
+            v = kernel_at(gc, g.far != 0, dx * g.nb + circ<N>(x), dy * g.nb + circ<N>(y), dz * g.nb + circ<N>(z));
         a[x] = cmake(v, 0.0);
     }
     fft_reg<double, N, false>(a);
@@ -202,10 +203,11 @@ __global__ void spec_pass_z(SpecGeom g, const cplx<double> *__restrict__ S, cplx
 }
 
 template <int N, typename T>
-hipError_t build_spectra_n(const double *gc, int nb, int XH, int YH, int ZH, void *table, void *scratch,
+hipError_t build_spectra_n(const double *gc, bool far, int nb, int XH, int YH, int ZH, void *table, void *scratch,
                            size_t scratch_bytes, hipStream_t s) {
     constexpr int H = N / 2 + 1;
     SpecGeom g;
+    g.far = far ? 1 : 0;
     g.nb = nb;
     g.XH = XH;
     g.YH = YH;
@@ -256,15 +258,40 @@ hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int
     return hipGetLastError();
 }
 
-hipError_t build_spectra(const double *gcube, int nb, int XH, int YH, int ZH, bool fp32, void *table,
+hipError_t build_spectra(const double *gcube, bool far, int nb, int XH, int YH, int ZH, bool fp32, void *table,
                          void *scratch, size_t scratch_bytes, hipStream_t s) {
     if (nb == 16)
-        return fp32 ? build_spectra_n<32, float>(gcube, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
-                    : build_spectra_n<32, double>(gcube, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
+        return fp32 ? build_spectra_n<32, float>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
+                    : build_spectra_n<32, double>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
     if (nb == 8)
-        return fp32 ? build_spectra_n<16, float>(gcube, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
-                    : build_spectra_n<16, double>(gcube, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
+        return fp32 ? build_spectra_n<16, float>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
+                    : build_spectra_n<16, double>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
     return hipErrorInvalidValue;
+}
+
+// Integrating factor of the discrete heat equation (paper Sec. 2.3, eqs.
+// heat, IF-single): H(a) = exp(a L) for the unscaled 7-point L, a =
+// kappa (t - tau) / dx^2.  exp(a (S + S^-1 - 2)) along one axis has the
+// kernel e^{-2a} I_n(2a) (the generating function of I_n), so the 3-D kernel
+// is E(n) = prod_i e^{-2a} I_{n_i}(2a): the integrand of the LGF's Bessel
+// form at t = a.  One Bessel row at x = 2a (bessel_rows_kernel with the
+// single node t = a), then the cube of its products.
+namespace {
+__global__ void if_cube_kernel(const double *__restrict__ B, double *__restrict__ cube) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kS * kS * kS) return;
+    const int c = idx % kS, b = (idx / kS) % kS, a = idx / (kS * kS);
+    const int hi = max(a, max(b, c)), lo = min(a, min(b, c)), mid = a + b + c - hi - lo;
+    cube[idx] = B[hi] * B[mid] * B[lo];
+}
+}  // namespace
+
+hipError_t build_if_table(double *cube, double *row, double *w, double a, hipStream_t s) {
+    if (!(a > 0.0)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bessel_rows_kernel, dim3(1), dim3(64), 0, s, row, w, 1, log(a), 0.0);
+    const int total = kS * kS * kS;
+    hipLaunchKernelGGL(if_cube_kernel, dim3((total + 255) / 256), dim3(256), 0, s, row, cube);
+    return hipGetLastError();
 }
 
 }  // namespace lgf
