@@ -196,3 +196,27 @@ def test_dense_256_box_sampled_parity(gpu_ctx):
     nz = f != 0
     ref = direct.direct_sum(c[nz], f[nz], c[idx], p.dx0)
     assert rel_l2(u[idx], ref) < TOL64
+
+
+def _fft_oracle(p, comp):
+    """The oracle's whole-box convolution (zero-padded library FFT of the
+    definition, pinned against the direct sum) at every cell of the support."""
+    from oracle import box
+    c = level_cells(p)
+    return box.convolve_cells(c, p.levels[0].values[comp].reshape(-1), c, p.dx0)
+
+
+def test_dense_256_box_full_parity(gpu_ctx):
+    """Every one of the 16.8M cells of the 256^3 box against the oracle."""
+    p = inputs.mstar()
+    u = gpu_solve(gpu_ctx, p)[0]
+    print("256^3 box solved; oracle FFT convolution of the whole box", flush=True)
+    assert rel_l2(u, _fft_oracle(p, 0)) < TOL64
+
+
+def test_vortex_ring_full_parity(gpu_ctx):
+    """All 852k cells of each component of the 128^3 ring support."""
+    p = inputs.single_ring(components=(0, 1))
+    u = gpu_solve(gpu_ctx, p)
+    for comp in range(2):
+        assert rel_l2(u[comp], _fft_oracle(p, comp)) < TOL64, comp

@@ -112,3 +112,35 @@ def test_full_size_colliding_rings_finest_manufactured_source(gpu_ctx, precision
         scale = -direct.direct_sum(cc[nz], np.abs(F_c[nz]), cells_k[tgt_idx], dx[kk])
         assert np.abs(got[kk][0][tgt_idx] - ref).max() < tol * scale.max(), kk
         Fb, F_fine = cb, F_c.reshape(cb.shape)
+
+
+@pytest.fixture(scope="module")
+def full_rings():
+    """The full-size colliding rings (992 / 2137 / 4776 blocks of 16^3),
+    omega_x and omega_z, with the stored oracle samples."""
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "colliding_rings_full_samples.npz"))
+    comps = tuple(int(c) for c in gold["components"])
+    print("building the full-size colliding rings (components %s)" % (comps,), flush=True)
+    p = inputs.colliding_rings(components=comps)
+    assert [len(lv.blocks) for lv in p.levels] == list(gold["n_blocks"])
+    return p, gold
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_refine", 1e-10)])
+def test_full_size_colliding_rings_ring_source_against_stored_oracle(gpu_ctx, full_rings, precision, tol):
+    """The two-ring vorticity on all three levels (R/32, R/64, R/128),
+    through the whole Sec. 3.4 recursion, against 2000 oracle samples per
+    level and component (written by tests/golden/make_colliding_rings_full.py:
+    the oracle's psi fields by its FFT box convolution, the samples by
+    direct sums)."""
+    p, gold = full_rings
+    nc = p.n_components
+    fields = [lv.values.reshape(nc, -1) for lv in p.levels]
+    print("solving the full-size colliding rings, %s" % precision, flush=True)
+    got = _solve(gpu_ctx, p, precision, fields)
+    for c in range(nc):
+        for k in range(3):
+            idx = gold["sample%d" % k]
+            e = rel_l2(got[k][c][idx], gold["phi%d_c%d" % (k, c)])
+            print("level %d component %d: rel L2 %.3e" % (k, c, e), flush=True)
+            assert e < tol, (c, k)
