@@ -266,6 +266,19 @@ lgf_status lgf_solve_batch(lgf_context *ctx, int n, lgf_plan *const *plans,
  */
 typedef struct lgf_graph lgf_graph;
 lgf_status lgf_graph_create(lgf_plan *plan, const double *f, double *u, lgf_graph **out);
+/*
+ * Graph form of lgf_solve_batch: records one lgf_solve_batch(ctx, n, plans,
+ * f, u, ...) on fixed buffers (the launches of every level and stage of
+ * every request, in the batch's order) into one HIP graph; each
+ * lgf_graph_launch replays the whole batch with one call.  The job tables of
+ * the batched launches are copied at capture into device buffers owned by
+ * the graph, so replays need no host staging.  Results equal
+ * lgf_solve_batch bit for bit.  The plans and the context must outlive the
+ * graph; replays must not overlap in time with each other or with other
+ * uses of the same plans.  Errors as lgf_solve_batch and lgf_graph_create.
+ */
+lgf_status lgf_graph_create_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f,
+                                  double *const *u, lgf_graph **out);
 lgf_status lgf_graph_launch(lgf_graph *graph, void *stream);
 void lgf_graph_destroy(lgf_graph *graph);
 

@@ -366,7 +366,10 @@ lgf_status lgf_solve_indicator(lgf_plan *plan, const double *f, double *u, void 
 }
 
 struct lgf_graph {
-    lgf_plan *plan = nullptr;
+    lgf_plan *plan = nullptr;                                  // single-plan graphs
+    std::vector<lgf_plan *> plans;                             // batch graphs
+    std::vector<std::unique_ptr<lgf::DeviceBuffer>> tables;    // job tables of a batch graph
+    int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -381,7 +384,36 @@ lgf_status lgf_graph_create(lgf_plan *plan, const double *f, double *u, lgf_grap
         DeviceScope ds(plan->ctx->device);
         auto g = std::make_unique<lgf_graph>();
         g->plan = plan;
+        g->device = plan->ctx->device;
         g->graph = capture_solve(plan, f, u);
+        const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g->graph);
+            hip_check(e, "graph instantiate");
+        }
+        *out = g.release();
+    });
+}
+
+lgf_status lgf_graph_create_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f,
+                                  double *const *u, lgf_graph **out) {
+    return guard([&] {
+        require(out != nullptr, "null output");
+        *out = nullptr;
+        require(ctx != nullptr && n >= 1, "bad batch arguments");
+        require(plans && f && u, "null batch arrays");
+        std::set<const lgf_plan *> seen;
+        for (int i = 0; i < n; ++i) {
+            require(plans[i] && plans[i]->ctx == ctx, "plan from another context");
+            require(seen.insert(plans[i]).second, "a plan appears twice in one batch");
+            require(f[i] && u[i], "null field pointer");
+            require(((uintptr_t)f[i] % 8) == 0 && ((uintptr_t)u[i] % 8) == 0, "misaligned field pointer");
+        }
+        DeviceScope ds(ctx->device);
+        auto g = std::make_unique<lgf_graph>();
+        g->plans.assign(plans, plans + n);
+        g->device = ctx->device;
+        g->graph = capture_batch(ctx, n, plans, f, u, g->tables);
         const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(g->graph);
@@ -394,17 +426,19 @@ lgf_status lgf_graph_create(lgf_plan *plan, const double *f, double *u, lgf_grap
 lgf_status lgf_graph_launch(lgf_graph *g, void *stream) {
     return guard([&] {
         require(g != nullptr && g->exec != nullptr, "null graph");
-        DeviceScope ds(g->plan->ctx->device);
+        DeviceScope ds(g->device);
         // the graph clears the spectral workspace itself; the next eager
         // solve must not assume any slot map either
-        g->plan->fhat_conv = nullptr;
+        if (g->plan) g->plan->fhat_conv = nullptr;
+        for (lgf_plan *p : g->plans) p->fhat_conv = nullptr;
         hip_check(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
     });
 }
 
 void lgf_graph_destroy(lgf_graph *g) {
     if (!g) return;
-    DeviceScope ds(g->plan->ctx->device);
+    DeviceScope ds(g->device);
+    if (!g->tables.empty()) (void)hipDeviceSynchronize();   // no replay may still read the job tables
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;

@@ -284,6 +284,11 @@ void build_context_table(lgf_context *ctx);
 void build_schedule(lgf_plan *plan);
 void run_plan(lgf_plan *plan, const double *f, double *u, hipStream_t s, lgf_report *rep);
 hipGraph_t capture_solve(lgf_plan *plan, const double *f, double *u);
+// While set on a thread (batch capture), batched launches stage their job
+// tables into new device buffers appended here instead of the ring.
+extern thread_local std::vector<std::unique_ptr<DeviceBuffer>> *g_job_sink;
+hipGraph_t capture_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
+                         std::vector<std::unique_ptr<DeviceBuffer>> &tables);
 void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
                hipStream_t s, lgf_report *reps);
 void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt, bool fp32,

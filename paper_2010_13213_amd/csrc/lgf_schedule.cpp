@@ -507,6 +507,8 @@ hipGraph_t capture_solve(lgf_plan *p, const double *f, double *u) {
     return g;
 }
 
+thread_local std::vector<std::unique_ptr<DeviceBuffer>> *g_job_sink = nullptr;
+
 namespace {
 
 // One convolution of a batch: plan workspace, sources -> destination.
@@ -523,6 +525,19 @@ struct ConvCall {
 template <typename T> const T *stage_jobs(lgf_context *ctx, const std::vector<T> &jobs, hipStream_t s, int &slot) {
     JobRing &r = ctx->ring;
     const size_t bytes = sizeof(T) * jobs.size();
+    if (g_job_sink) {   // graph capture: a table of its own, filled now, read by every replay
+        auto b = std::make_unique<DeviceBuffer>();
+        b->alloc(ctx, std::max<size_t>(bytes, 16), "captured job table");
+        // on the context's own stream, which is not being captured (a copy
+        // on the legacy stream would join the capture)
+        hip_check(hipMemcpyAsync(b->ptr, jobs.data(), bytes, hipMemcpyHostToDevice, ctx->stream),
+                  "captured job table copy");
+        hip_check(hipStreamSynchronize(ctx->stream), "captured job table sync");
+        const T *d = (const T *)b->ptr;
+        g_job_sink->push_back(std::move(b));
+        slot = -1;
+        return d;
+    }
     if (bytes > JobRing::kSlotBytes) throw Failure(LGF_E_UNSUPPORTED, "batch job table larger than 256 KiB");
     std::lock_guard<std::mutex> lk(r.mu);
     const int k = r.next;
@@ -538,6 +553,7 @@ template <typename T> const T *stage_jobs(lgf_context *ctx, const std::vector<T>
 
 // The slot may be reused once the launch that reads it has completed.
 void ring_mark(lgf_context *ctx, int slot, hipStream_t s) {
+    if (slot < 0) return;   // a captured table, not a ring slot
     JobRing &r = ctx->ring;
     std::lock_guard<std::mutex> lk(r.mu);
     hip_check(hipEventRecord(r.done[slot], s), "ring event record");
@@ -861,6 +877,43 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+}
+
+}  // namespace lgf
+
+namespace lgf {
+
+// Record one lgf_solve_batch of these plans on fixed buffers into a graph,
+// as capture_solve does for one plan; the job tables of the batched
+// launches go to buffers of their own (kept in `tables`) instead of the ring.
+hipGraph_t capture_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *const *f, double *const *u,
+                         std::vector<std::unique_ptr<DeviceBuffer>> &tables) {
+    hipStream_t cs = nullptr;
+    hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+    for (int i = 0; i < n; ++i) plans[i]->fhat_conv = nullptr;
+    g_no_timing = true;
+    g_job_sink = &tables;
+    hipGraph_t g = nullptr;
+    auto reset = [&]() {
+        g_no_timing = false;
+        g_job_sink = nullptr;
+        for (int i = 0; i < n; ++i) plans[i]->fhat_conv = nullptr;
+        (void)hipStreamDestroy(cs);
+    };
+    try {
+        hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+        run_batch(ctx, n, plans, f, u, cs, nullptr);
+        hip_check(hipStreamEndCapture(cs, &g), "end capture");
+    } catch (...) {
+        hipGraph_t partial = nullptr;
+        (void)hipStreamEndCapture(cs, &partial);
+        if (partial) (void)hipGraphDestroy(partial);
+        (void)hipGetLastError();
+        reset();
+        throw;
+    }
+    reset();
+    return g;
 }
 
 }  // namespace lgf

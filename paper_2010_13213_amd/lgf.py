@@ -23,7 +23,8 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_indicator",
             "lgf_plan_source_blocks", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
-            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_launch", "lgf_graph_destroy",
+            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_create_batch", "lgf_graph_launch",
+            "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
             "lgf_context_set_mac_method",
             "lgf_context_tuning_size"]
@@ -129,6 +130,9 @@ def lib():
     L.lgf_status_string.restype = ctypes.c_char_p
     L.lgf_graph_create.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
     L.lgf_graph_create.restype = ctypes.c_int
+    L.lgf_graph_create_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.lgf_graph_create_batch.restype = ctypes.c_int
     L.lgf_graph_launch.argtypes = [vp, vp]
     L.lgf_graph_launch.restype = ctypes.c_int
     L.lgf_graph_destroy.argtypes = [vp]
@@ -407,6 +411,39 @@ class Graph:
     def launch(self, stream=None):
         _check(lib().lgf_graph_launch(self._h, _stream_handle(stream)))
         return self.u
+
+    def close(self):
+        if self._h:
+            lib().lgf_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraph:
+    """One lgf_solve_batch of `plans` on the fixed tensors fs, us, captured
+    as a HIP graph (lgf_graph_create_batch); launch() replays it.  Keep the
+    plans, tensors and context alive while the graph exists."""
+
+    def __init__(self, ctx, plans, fs, us):
+        n = len(plans)
+        for p, f, u in zip(plans, fs, us):
+            _check_field(f, p.field_len(), "f")
+            _check_field(u, p.field_len(), "u")
+        self.ctx, self.plans, self.fs, self.us = ctx, list(plans), list(fs), list(us)
+        P = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+        F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        U = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        self._h = ctypes.c_void_p()
+        _check(lib().lgf_graph_create_batch(ctx.handle, n, P, F, U, ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(lib().lgf_graph_launch(self._h, _stream_handle(stream)))
+        return self.us
 
     def close(self):
         if self._h:

@@ -59,3 +59,47 @@ def test_graph_replays_equal_eager_solves(gpu_ctx, case, precision):
     # eager solves after the graph is gone still agree
     assert torch.equal(plan.solve(f0), ref0)
     plan.close()
+
+
+def test_batch_graph_replays_equal_eager_batches(gpu_ctx):
+    """lgf_graph_create_batch: one graph holds a whole batch -- single-level
+    FP64 and FP32+refine, a composite FP64 and a composite FP32+refine plan,
+    an integrating-factor plan.  Each replay (inputs refreshed in place,
+    eager batches of the same plans between replays) equals the eager
+    lgf_solve_batch bit for bit."""
+    import torch
+    from paper_2010_13213_amd import lgf
+    reqs = inputs.served_stream(4, seed=31, sizes=[16, 24, 40])
+    cases = [(r.problem, r.precision, None) for r in reqs] + \
+            [(_two_level(), "fp64", None), (_two_level(), "fp32_refine", None), (_two_level(), "fp64", 0.7)]
+    plans = [lgf.Plan.for_problem(gpu_ctx, p, prec, if_a0=a) for p, prec, a in cases]
+    f0 = [torch.from_numpy(p.flat_source()).cuda() for p, _, _ in cases]
+    f1 = [torch.flip(f, dims=[0]).contiguous() * -0.25 for f in f0]
+    refs = []
+    for src in (f0, f1):
+        us = [torch.empty_like(f) for f in src]
+        lgf.solve_batch(gpu_ctx, plans, src, us)
+        torch.cuda.synchronize()
+        refs.append([u.clone() for u in us])
+    fb = [f.clone() for f in f0]
+    ub = [torch.empty_like(f) for f in f0]
+    print("capturing a batch of %d plans" % len(plans), flush=True)
+    g = lgf.BatchGraph(gpu_ctx, plans, fb, ub)
+    scratch = [torch.empty_like(f) for f in f0]
+    for rep in range(4):
+        src, ref = (f0, refs[0]) if rep % 2 == 0 else (f1, refs[1])
+        for a, b in zip(fb, src):
+            a.copy_(b)
+        for u in ub:
+            u.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (u, r) in enumerate(zip(ub, ref)):
+            assert torch.equal(u, r), (rep, i)
+        lgf.solve_batch(gpu_ctx, plans, f1 if rep % 2 == 0 else f0, scratch)
+        torch.cuda.synchronize()
+        for u, r in zip(scratch, refs[1] if rep % 2 == 0 else refs[0]):
+            assert torch.equal(u, r)
+    g.close()
+    for p in plans:
+        p.close()
