@@ -63,10 +63,22 @@ typedef enum lgf_precision {
 typedef struct lgf_context lgf_context;
 typedef struct lgf_plan lgf_plan;
 
-/* One refinement level: n_blocks block coordinates, [n_blocks][3] (x, y, z). */
+/*
+ * One refinement level: n_blocks block coordinates, [n_blocks][3] (x, y, z),
+ * and an optional cell mask that states the level's part Omega_k of the
+ * partition of Sec. 3.1 (eq. partition) cell by cell: [n_blocks][nb^3] bytes
+ * in the field's [z][y][x] order, 1 = the cell belongs to Omega_k (its
+ * source is used, its solution written), 0 = it does not (its source is
+ * ignored and 0 is written).  NULL: Omega_k = every cell of the level's
+ * blocks that no level-(k+1) block covers.  A mask may drop further cells
+ * but may not keep a covered one: a 1 on a cell under a level-(k+1) block
+ * makes the levels overlap and is refused (LGF_E_INVALID), as are values
+ * other than 0 and 1.
+ */
 typedef struct lgf_level {
     int32_t n_blocks;
     const int32_t *block_ijk;
+    const uint8_t *cell_mask;
 } lgf_level;
 
 /* Problem description (Sec. 3.1 composite grid, Sec. 5 block structure). */

@@ -145,7 +145,7 @@ def coarsen_mean8(fine_box, fine, coarse_cells):
 class CompositeOracle:
     """Composite-grid LGF solve of one scalar component (all steps in FP64)."""
 
-    def __init__(self, nb, dx0, level_blocks, ext_layers=1, fft_min_targets=None):
+    def __init__(self, nb, dx0, level_blocks, ext_layers=1, fft_min_targets=None, cell_masks=None):
         self.nb = nb
         self.fft_min_targets = fft_min_targets
         self.dx0 = dx0
@@ -153,16 +153,26 @@ class CompositeOracle:
         self.blocks = [np.asarray(b, dtype=np.int64).reshape(-1, 3) for b in level_blocks]
         self.dx = [dx0 / 2 ** k for k in range(self.K)]
         self.cells = [block_cells(b, nb) for b in self.blocks]
-        # Omega_k mask over the cells of level-k blocks (True = kept).
-        self.mask = []
+        # Omega_k mask over the cells of level-k blocks (True = kept): cells
+        # no level-(k+1) block covers, further restricted by the caller's cell
+        # mask (the partition of Sec. 3.1 given cell by cell; a kept covered
+        # cell would make the levels overlap)
+        self.covered, self.mask = [], []
         for k in range(self.K):
             if k + 1 < self.K:
                 fine = {tuple(b) for b in self.blocks[k + 1].tolist()}
                 child_blk = np.floor_divide(2 * self.cells[k], nb)
                 covered = np.array([tuple(c) in fine for c in child_blk.tolist()])
-                self.mask.append(~covered)
             else:
-                self.mask.append(np.ones(len(self.cells[k]), dtype=bool))
+                covered = np.zeros(len(self.cells[k]), dtype=bool)
+            keep = ~covered
+            if cell_masks is not None and cell_masks[k] is not None:
+                cm = np.asarray(cell_masks[k]).reshape(-1).astype(bool)
+                if np.any(cm & covered):
+                    raise ValueError("levels overlap after masking (level %d)" % k)
+                keep = keep & cm
+            self.covered.append(covered)
+            self.mask.append(keep)
         # R_k = Omega_k u Omega_k^E as cells of the dilated block set (k >= 1).
         self.ext_blocks = [None] + [dilate_blocks(self.blocks[k], ext_layers)
                                     for k in range(1, self.K)]
@@ -199,7 +209,7 @@ class CompositeOracle:
             i, j, kk = fb.idx(self.cells[k + 1])
             arr[i, j, kk] = F[k + 1]
             Fk = fhat[k].copy()
-            cov = ~self.mask[k]
+            cov = self.covered[k]
             Fk[cov] = coarsen_mean8(fb, arr, self.cells[k][cov])
             F[k] = Fk
         return F

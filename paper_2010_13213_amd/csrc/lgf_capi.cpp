@@ -126,6 +126,35 @@ void validate_and_copy(lgf_plan *p, const lgf_problem *d) {
         for (const auto &b : p->levels[k])
             require(sets[k - 1].count(Key(fdiv(b.ijk[0], 2), fdiv(b.ijk[1], 2), fdiv(b.ijk[2], 2))) > 0,
                     "level " + std::to_string(k) + " block outside level " + std::to_string(k - 1));
+    // cell masks: 0 / 1 only, and no 1 under a finer block (levels overlap)
+    p->cell_mask.assign(p->K, {});
+    for (int k = 0; k < p->K; ++k) {
+        const lgf_level &L = d->levels[k];
+        if (!L.cell_mask) continue;
+        const size_t n = (size_t)L.n_blocks * nb3;
+        p->cell_mask[k].assign(L.cell_mask, L.cell_mask + n);
+        for (size_t i = 0; i < n; ++i)
+            require(p->cell_mask[k][i] <= 1, "cell mask values must be 0 or 1 (level " + std::to_string(k) + ")");
+        if (k + 1 < p->K) {
+            std::map<Key, int> idx;
+            for (int i = 0; i < (int)p->levels[k].size(); ++i) {
+                const auto &b = p->levels[k][i];
+                idx[Key(b.ijk[0], b.ijk[1], b.ijk[2])] = i;
+            }
+            const int nb = p->nb, H = nb / 2;
+            for (const auto &fb : p->levels[k + 1]) {
+                const int px = fdiv(fb.ijk[0], 2), py = fdiv(fb.ijk[1], 2), pz = fdiv(fb.ijk[2], 2);
+                const int bi = idx.at(Key(px, py, pz));
+                const int ox = (fb.ijk[0] - 2 * px) * H, oy = (fb.ijk[1] - 2 * py) * H, oz = (fb.ijk[2] - 2 * pz) * H;
+                for (int z = 0; z < H; ++z)
+                    for (int y = 0; y < H; ++y)
+                        for (int x = 0; x < H; ++x)
+                            require(p->cell_mask[k][(size_t)bi * nb3 + ((oz + z) * nb + (oy + y)) * nb + (ox + x)] == 0,
+                                    "levels overlap after masking: a level-" + std::to_string(k) +
+                                        " cell under a level-" + std::to_string(k + 1) + " block is kept");
+            }
+        }
+    }
 }
 
 }  // namespace

@@ -3,8 +3,9 @@
 // Paper Sec. 3.2-3.4.  Level k+1 halves the cell width of level k; a
 // level-(k+1) cell c' is a child of level-k cell floor(c'/2).
 //  * mask_blocks: restriction to Omega_k -- cells of a level-k block whose
-//    octant is covered by a level-(k+1) block are zeroed (f^_k = Gamma_k f_k,
-//    and the returned phi_k is 0 there).
+//    octant is covered by a level-(k+1) block, and cells the caller's cell
+//    mask drops, are zeroed (f^_k = Gamma_k f_k, and the returned phi_k is 0
+//    there).
 //  * coarsen_mean8: P_{k+1->k}, the mean of the 8 children, written into the
 //    covered octant of the parent block (step 1 of the algorithm,
 //    F_k = f^_k + P_{k+1->k} F_{k+1}).
@@ -32,16 +33,19 @@ template <int NB>
 __global__ void __launch_bounds__(256) mask_kernel(const double *__restrict__ src, double *__restrict__ dst,
                                                    const int64_t *__restrict__ src_off,
                                                    const int64_t *__restrict__ dst_off,
-                                                   const unsigned char *__restrict__ cover) {
+                                                   const unsigned char *__restrict__ cover,
+                                                   const unsigned char *__restrict__ cmask) {
     constexpr int H = NB / 2;
     const int b = blockIdx.x;
     const double *s = src + src_off[b];
     double *d = dst + dst_off[b];
-    const unsigned m = cover[b];
+    const unsigned m = cover ? cover[b] : 0u;
+    const unsigned char *cm = cmask ? cmask + (size_t)b * NB * NB * NB : nullptr;
     for (int i = threadIdx.x; i < NB * NB * NB; i += 256) {
         const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
         const int oct = (x >= H) | ((y >= H) << 1) | ((z >= H) << 2);
-        d[i] = ((m >> oct) & 1u) ? 0.0 : s[i];
+        const bool keep = !((m >> oct) & 1u) && (!cm || cm[i]);
+        d[i] = keep ? s[i] : 0.0;
     }
 }
 
@@ -180,12 +184,14 @@ __global__ void __launch_bounds__(256) correction_kernel(CorrGeom g, const doubl
 }  // namespace
 
 hipError_t mask_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,
-                       const unsigned char *cover, int n_blocks, hipStream_t s) {
+                       const unsigned char *cover, int n_blocks, hipStream_t s, const unsigned char *cmask) {
     if (n_blocks <= 0) return hipSuccess;
     if (nb == 16)
-        hipLaunchKernelGGL(mask_kernel<16>, dim3(n_blocks), dim3(256), 0, s, src, dst, src_off, dst_off, cover);
+        hipLaunchKernelGGL(mask_kernel<16>, dim3(n_blocks), dim3(256), 0, s, src, dst, src_off, dst_off, cover,
+                           cmask);
     else if (nb == 8)
-        hipLaunchKernelGGL(mask_kernel<8>, dim3(n_blocks), dim3(256), 0, s, src, dst, src_off, dst_off, cover);
+        hipLaunchKernelGGL(mask_kernel<8>, dim3(n_blocks), dim3(256), 0, s, src, dst, src_off, dst_off, cover,
+                           cmask);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

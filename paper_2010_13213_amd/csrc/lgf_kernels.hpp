@@ -175,9 +175,12 @@ hipError_t lattice_spectra(const LatSpecGeom &sg, bool fp32, const void *octant,
                            size_t scratch_bytes, hipStream_t s);
 
 // ---- composite-grid kernels (lgf_composite.hip) ----
-// dst block b = src block b with the octants flagged in cover[b] zeroed.
+// dst block b = src block b with the octants flagged in cover[b] (cover may
+// be null) zeroed, and the cells whose byte in cmask + b nb^3 is 0 (cmask may
+// be null).
 hipError_t mask_blocks(int nb, const double *src, double *dst, const int64_t *src_off, const int64_t *dst_off,
-                       const unsigned char *cover, int n_blocks, hipStream_t s);
+                       const unsigned char *cover, int n_blocks, hipStream_t s,
+                       const unsigned char *cmask = nullptr);
 // coarse octant (octant[i]) of the block at coarse_off[i] = mean of 8 children
 // of the fine block at fine_off[i].
 hipError_t coarsen_mean8(int nb, const double *fine, double *coarse, const int64_t *fine_off,

@@ -194,6 +194,7 @@ struct SpecWs {
 struct LevelSched {
     int n_own = 0;
     bool any_cover = false;
+    DeviceBuffer d_cmask;                            // the level's cell mask ([block][nb^3]), if given
     DeviceBuffer d_cover, d_own_off;                 // level blocks: octant cover bits, field offsets
     int n_cf = 0;
     DeviceBuffer d_cf_fine, d_cf_coarse, d_cf_oct;   // coarsening pairs from level k+1
@@ -228,6 +229,8 @@ struct lgf_plan {
     int K = 1, nb = 16, nc = 1, prec = 0, ne = 1;
     double dx0 = 1.0;
     std::vector<std::vector<lgf::Blk>> levels;     // per level, offsets within one component
+    std::vector<std::vector<uint8_t>> cell_mask;   // per level: the caller's cell mask, or empty
+    lgf::DeviceBuffer d_cmask0, ws_masked;         // single level with a mask: the mask, the masked source
     std::vector<int64_t> level_base;               // element offset of each level in a component
     int64_t comp_len = 0;                          // elements per component
     std::unique_ptr<lgf::ConvOp> op0;                       // single-level plans

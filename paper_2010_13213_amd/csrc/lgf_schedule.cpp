@@ -87,6 +87,10 @@ void build_schedule(lgf_plan *p) {
                 }
             upload(ctx, p->d_blk_back, back, "backward neighbours");
         }
+        if (!p->cell_mask[0].empty()) {
+            upload(ctx, p->d_cmask0, p->cell_mask[0], "cell mask");
+            p->ws_masked.alloc(ctx, sizeof(double) * p->comp_len * p->nc, "masked source");
+        }
         p->ind_base = {0};
         p->ind_total = (int64_t)p->levels[0].size();
         p->d_ind.alloc(ctx, sizeof(double) * 2 * p->ind_total * p->nc, "indicator statistics");
@@ -122,6 +126,7 @@ void build_schedule(lgf_plan *p) {
         L.n_own = (int)B.size();
         L.any_cover = std::any_of(cover.begin(), cover.end(), [](unsigned char c) { return c != 0; });
         upload(ctx, L.d_cover, cover, "cover bits");
+        if (!p->cell_mask[k].empty()) upload(ctx, L.d_cmask, p->cell_mask[k], "cell mask");
         upload(ctx, L.d_own_off, own, "offsets");
         L.n_cf = (int)cf_f.size();
         upload(ctx, L.d_cf_fine, cf_f, "coarsen pairs");
@@ -304,7 +309,7 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
                 const LevelSched &L = *p->lv[k];
                 hip_check(mask_blocks(nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
                                       (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr, L.n_own,
-                                      s),
+                                      s, (const unsigned char *)L.d_cmask.ptr),
                           "mask sources");
                 hip_check(copy_blocks(nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
                                       (const int64_t *)L.d_own_off.ptr, L.n_own, s),
@@ -357,11 +362,11 @@ static void enqueue_composite(lgf_plan *p, const double *f, double *u, hipStream
                     run_op(p, *L.convPsi, Sf, EL, psi_next, DL, ng, dxk, 1, s);
                 }
             }
-            if (L.any_cover)
+            if (L.any_cover || L.d_cmask.ptr)
                 for (int c = 0; c < ng; ++c)
                     hip_check(mask_blocks(nb, ug + c * CL, ug + c * CL, (const int64_t *)L.d_own_off.ptr,
                                           (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
-                                          L.n_own, s),
+                                          L.n_own, s, (const unsigned char *)L.d_cmask.ptr),
                               "restrict phi");
             cur ^= 1;
         }
@@ -388,7 +393,7 @@ static void enqueue_fif(lgf_plan *p, const double *f, double *u, hipStream_t s) 
                 const LevelSched &L = *p->lv[k];
                 hip_check(mask_blocks(nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
                                       (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr, L.n_own,
-                                      s),
+                                      s, (const unsigned char *)L.d_cmask.ptr),
                           "mask sources");
                 hip_check(copy_blocks(nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
                                       (const int64_t *)L.d_own_off.ptr, L.n_own, s),
@@ -429,11 +434,11 @@ static void enqueue_fif(lgf_plan *p, const double *f, double *u, hipStream_t s) 
                                               (const int64_t *)L.d_cp_dst.ptr, L.n_dom, s),
                                   "q");
             }
-            if (L.any_cover)
+            if (L.any_cover || L.d_cmask.ptr)
                 for (int c = 0; c < ng; ++c)
                     hip_check(mask_blocks(nb, ug + c * CL, ug + c * CL, (const int64_t *)L.d_own_off.ptr,
                                           (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
-                                          L.n_own, s),
+                                          L.n_own, s, (const unsigned char *)L.d_cmask.ptr),
                               "restrict phi");
             cur ^= 1;
         }
@@ -448,12 +453,28 @@ static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
             enqueue_composite(p, f, u, s);
         return;
     }
+    const int nblk = (int)p->levels[0].size();
+    const int64_t *boff = (const int64_t *)p->d_blk_off.ptr;
+    const unsigned char *cm = (const unsigned char *)p->d_cmask0.ptr;
+    if (cm) {            // the caller's cell mask: Omega_0 only
+        double *fm = (double *)p->ws_masked.ptr;
+        for (int c = 0; c < p->nc; ++c)
+            hip_check(mask_blocks(p->nb, f + (size_t)c * p->comp_len, fm + (size_t)c * p->comp_len, boff, boff,
+                                  nullptr, nblk, s, cm),
+                      "mask sources");
+        f = fm;
+    }
     if (p->collect)      // one level: the combined source is the source itself
         for (int c = 0; c < p->nc; ++c)
-            hip_check(block_stats(p->nb, f + (size_t)c * p->comp_len, (const int64_t *)p->d_blk_off.ptr,
-                                  (int)p->levels[0].size(), (double *)p->d_ind.ptr + 2 * c * p->ind_total, s),
+            hip_check(block_stats(p->nb, f + (size_t)c * p->comp_len, boff, nblk,
+                                  (double *)p->d_ind.ptr + 2 * c * p->ind_total, s),
                       "indicator");
     run_op(p, *p->op0, f, p->comp_len, u, p->comp_len, p->nc, p->dx0, 0, s);
+    if (cm)
+        for (int c = 0; c < p->nc; ++c)
+            hip_check(mask_blocks(p->nb, u + (size_t)c * p->comp_len, u + (size_t)c * p->comp_len, boff, boff, nullptr,
+                                  nblk, s, cm),
+                      "restrict u");
 }
 
 void run_plan(lgf_plan *p, const double *f, double *u, hipStream_t s, lgf_report *rep) {
@@ -748,7 +769,7 @@ void run_composite_batch(lgf_context *ctx, const std::vector<lgf_plan *> &ps, co
                     const LevelSched &L = *p->lv[k];
                     hip_check(mask_blocks(p->nb, fg + c * CL, FH + c * CL, (const int64_t *)L.d_own_off.ptr,
                                           (const int64_t *)L.d_own_off.ptr, (const unsigned char *)L.d_cover.ptr,
-                                          L.n_own, s),
+                                          L.n_own, s, (const unsigned char *)L.d_cmask.ptr),
                               "mask sources");
                     hip_check(copy_blocks(p->nb, FH + c * CL, FC + c * CL, (const int64_t *)L.d_own_off.ptr,
                                           (const int64_t *)L.d_own_off.ptr, L.n_own, s),
@@ -810,11 +831,11 @@ void run_composite_batch(lgf_context *ctx, const std::vector<lgf_plan *> &ps, co
                 if (ng[i] == 0 || k >= p->K) continue;
                 const LevelSched &L = *p->lv[k];
                 double *ug = us[i] + (size_t)c0 * p->comp_len;
-                if (L.any_cover)
+                if (L.any_cover || L.d_cmask.ptr)
                     for (int c = 0; c < ng[i]; ++c)
                         hip_check(mask_blocks(p->nb, ug + c * p->comp_len, ug + c * p->comp_len,
                                               (const int64_t *)L.d_own_off.ptr, (const int64_t *)L.d_own_off.ptr,
-                                              (const unsigned char *)L.d_cover.ptr, L.n_own, s),
+                                              (const unsigned char *)L.d_cover.ptr, L.n_own, s, (const unsigned char *)L.d_cmask.ptr),
                                   "restrict phi");
                 cur[i] ^= 1;
             }
@@ -840,7 +861,9 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         std::vector<const double *> cfs;
         std::vector<double *> cus;
         for (int i : kv.second) {
-            if (plans[i]->K == 1) {
+            if (plans[i]->K == 1 && plans[i]->d_cmask0.ptr) {   // a cell mask: the plan's own masking steps
+                enqueue(plans[i], f[i], u[i], s);
+            } else if (plans[i]->K == 1) {
                 single.push_back(i);
             } else if (plans[i]->if_a0 > 0.0) {   // integrating factor on a composite mesh: its own schedule
                 enqueue(plans[i], f[i], u[i], s);

@@ -31,6 +31,7 @@ import numpy as np
 class Level:
     blocks: np.ndarray            # (n, 3) int32 block coordinates
     values: np.ndarray            # (n_comp, n, nb, nb, nb) float64, [b][z][y][x]
+    cell_mask: Optional[np.ndarray] = None   # (n, nb, nb, nb) 0/1: the cells of Omega_k (None: not covered)
 
 
 @dataclass

@@ -37,7 +37,8 @@ class LgfError(RuntimeError):
 
 
 class _Level(ctypes.Structure):
-    _fields_ = [("n_blocks", ctypes.c_int32), ("block_ijk", ctypes.POINTER(ctypes.c_int32))]
+    _fields_ = [("n_blocks", ctypes.c_int32), ("block_ijk", ctypes.POINTER(ctypes.c_int32)),
+                ("cell_mask", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class _Problem(ctypes.Structure):
@@ -245,21 +246,27 @@ def table_radius():
     return int(lib().lgf_table_radius())
 
 
-def _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks):
+def _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks, cell_masks=None):
     blocks = [np.ascontiguousarray(b, dtype=np.int32).reshape(-1, 3) for b in level_blocks]
+    masks = [None if m is None else np.ascontiguousarray(m, dtype=np.uint8).reshape(-1)
+             for m in (cell_masks or [None] * len(blocks))]
     levels = (_Level * max(1, len(blocks)))()
     for i, b in enumerate(blocks):
         levels[i].n_blocks = len(b)
         levels[i].block_ijk = b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if masks[i] is not None:
+            if masks[i].size != len(b) * int(nb) ** 3:
+                raise ValueError("cell mask of level %d needs %d bytes" % (i, len(b) * int(nb) ** 3))
+            levels[i].cell_mask = masks[i].ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     prob = _Problem(len(blocks), int(nb), float(dx0), int(n_components),
                     _PREC[precision] if isinstance(precision, str) else int(precision),
                     int(ne_blocks), levels)
-    return prob, (blocks, levels)
+    return prob, (blocks, masks, levels)
 
 
-def problem_check(level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0):
+def problem_check(level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0, cell_masks=None):
     """Host-only validation of a problem; returns (status, message)."""
-    prob, keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks)
+    prob, keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks, cell_masks)
     st = lib().lgf_problem_check(ctypes.byref(prob))
     return st, (lib().lgf_last_error().decode() if st != LGF_OK else "")
 
@@ -267,15 +274,18 @@ def problem_check(level_blocks, nb, dx0, n_components=1, precision="fp64", ne_bl
 class Plan:
     """An immutable solve plan for one block support (all levels)."""
 
-    def __init__(self, ctx, level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0, if_a0=None):
+    def __init__(self, ctx, level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0, if_a0=None,
+                 cell_masks=None):
         """if_a0: None for the LGF solve (L^-1); a > 0 for the integrating
-        factor H(a) = exp(a L) on level 0 (a_k = 4^k a on level k)."""
+        factor H(a) = exp(a L) on level 0 (a_k = 4^k a on level k).
+        cell_masks: None or one entry per level, None or nb^3 bytes per
+        block ([block][z][y][x]; 1 keeps the cell in Omega_k)."""
         self.ctx = ctx
         self.nb = int(nb)
         self.n_levels = len(level_blocks)
         self.n_components = int(n_components)
         self.precision = precision
-        prob, self._keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks)
+        prob, self._keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks, cell_masks)
         h = ctypes.c_void_p()
         if if_a0 is None:
             _check(lib().lgf_plan_create(ctx.handle, ctypes.byref(prob), ctypes.byref(h)))
@@ -285,8 +295,10 @@ class Plan:
 
     @classmethod
     def for_problem(cls, ctx, problem, precision="fp64", ne_blocks=0, if_a0=None):
+        masks = [getattr(lv, "cell_mask", None) for lv in problem.levels]
         return cls(ctx, [lv.blocks for lv in problem.levels], problem.nb, problem.dx0,
-                   problem.n_components, precision, ne_blocks, if_a0)
+                   problem.n_components, precision, ne_blocks, if_a0,
+                   None if all(m is None for m in masks) else masks)
 
     @property
     def handle(self):

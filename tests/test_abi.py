@@ -74,3 +74,22 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.lgf_solve(None, None, None, None, None) == lgf.LGF_E_INVALID
     out = ctypes.c_void_p()
     assert L.lgf_context_create(0, 0, None) == lgf.LGF_E_INVALID
+
+
+def test_problem_check_cell_masks():
+    coarse, fine = _cube(2), _cube(2, lo=2)           # fine blocks 2,3 refine coarse block (1,1,1)
+    nb = 8
+    m0 = np.ones((len(coarse), nb, nb, nb), dtype=np.uint8)
+    i = [tuple(b) for b in coarse.tolist()].index((1, 1, 1))
+    m0[i] = 0                                          # the refined block dropped entirely: valid
+    m0[0, :2] = 0                                      # and some uncovered cells: valid
+    st, msg = lgf.problem_check([coarse, fine], nb, 1.0, cell_masks=[m0, None])
+    assert st == lgf.LGF_OK, msg
+    bad = m0.copy()
+    bad[i, 7, 7, 7] = 1                                # a covered cell kept: the levels overlap
+    st, msg = lgf.problem_check([coarse, fine], nb, 1.0, cell_masks=[bad, None])
+    assert st == lgf.LGF_E_INVALID and "overlap" in msg
+    two = m0.copy()
+    two[0, 5, 5, 5] = 2
+    st, msg = lgf.problem_check([coarse, fine], nb, 1.0, cell_masks=[two, None])
+    assert st == lgf.LGF_E_INVALID and "0 or 1" in msg

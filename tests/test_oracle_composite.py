@@ -334,3 +334,35 @@ def test_three_level_middle_and_fine_sources(fft):
     t1 = orc.cells[1][samp[1]]
     ref1 = psi1(t1) + direct.direct_sum(cc[F != 0], F[F != 0], t1, 0.5)
     assert np.linalg.norm(phi[1][samp[1]] - ref1) / np.linalg.norm(ref1) < 1e-11
+
+
+def test_cell_masks_state_the_partition():
+    """Reading c8 (Sec. 3.1, eq. partition): a cell mask equal to the cover
+    reproduces the unmasked recursion bit for bit; dropping uncovered cells
+    equals zeroing their sources and discarding their targets; a kept
+    covered cell is refused."""
+    orc = _three_level_nested()
+    blocks = orc.blocks
+    rng = np.random.default_rng(11)
+    f = [rng.standard_normal(len(orc.cells[k])) for k in range(3)]
+    base = orc.solve(f, sample=[np.arange(0, len(orc.cells[k]), 37) for k in range(3)])
+    same = C.CompositeOracle(orc.nb, 1.0, blocks, cell_masks=[m.astype(np.uint8) for m in orc.mask])
+    got = same.solve(f, sample=[np.arange(0, len(orc.cells[k]), 37) for k in range(3)])
+    for a, b in zip(base, got):
+        assert np.array_equal(a, b)
+    drop = [m.copy() for m in orc.mask]
+    drop[0][:700] = False                             # uncovered coarse cells leave Omega_0
+    masked = C.CompositeOracle(orc.nb, 1.0, blocks, cell_masks=drop)
+    f2 = [np.where(drop[k], f[k], 0.0) for k in range(3)]
+    samp = [np.arange(0, len(orc.cells[k]), 23) for k in range(3)]
+    ref = orc.solve(f2, sample=samp)
+    out = masked.solve(f, sample=samp)
+    for k in range(3):
+        keep = samp[k][drop[k][samp[k]]]
+        assert np.array_equal(out[k][keep], ref[k][keep])
+        gone = samp[k][~drop[k][samp[k]]]
+        assert np.all(out[k][gone] == 0.0)
+    bad = [m.copy() for m in orc.mask]
+    bad[1][np.nonzero(~orc.mask[1])[0][0]] = True
+    with pytest.raises(ValueError):
+        C.CompositeOracle(orc.nb, 1.0, blocks, cell_masks=bad)
