@@ -96,7 +96,7 @@ typedef struct lgf_problem {
 /* Optional per-solve report, filled after the solve's stream work is done. */
 typedef struct lgf_report {
     double device_ms;       /* stream time of the solve (HIP events)        */
-    double refine_rel_l2;   /* mixed path: ||correction|| / ||u||, else 0   */
+    double refine_rel_l2;   /* reserved: written as 0                      */
     int32_t passes;         /* LGF convolutions run per component           */
     int32_t reserved;
 } lgf_report;

@@ -61,41 +61,41 @@ template <typename R> __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<
     return acc;
 }
 
-// exp(-2 pi i k / 64), k = 0..31, as (cos, -sin) pairs (the even entries are
-// the 32nds of a turn).
+// exp(-2 pi i k / 64), k = 0..31, as (cos, -sin) pairs, each correctly
+// rounded to float64 (the even entries are the 32nds of a turn).
 constexpr double kTw64[32][2] = {
     {1.0, 0.0},
-    {9.95184726672196928732e-01, -9.80171403295606036288e-02},
-    {9.80785280403230449126e-1, -1.95090322016128267848e-1},
-    {9.56940335732208824382e-01, -2.90284677254462331053e-01},
-    {9.23879532511286756128e-1, -3.82683432365089771728e-1},
-    {8.81921264348355049556e-01, -4.71396736825997642040e-01},
-    {8.31469612302545237079e-1, -5.55570233019602224743e-1},
-    {7.73010453362736993377e-01, -6.34393284163645487794e-01},
-    {7.07106781186547524401e-1, -7.07106781186547524401e-1},
-    {6.34393284163645487794e-01, -7.73010453362736993377e-01},
-    {5.55570233019602224743e-1, -8.31469612302545237079e-1},
-    {4.71396736825997808573e-01, -8.81921264348354938534e-01},
-    {3.82683432365089771728e-1, -9.23879532511286756128e-1},
-    {2.90284677254462331053e-01, -9.56940335732208935404e-01},
-    {1.95090322016128267848e-1, -9.80785280403230449126e-1},
-    {9.80171403295607701622e-02, -9.95184726672196817709e-01},
+    {0.9951847266721969, -0.0980171403295606},
+    {0.9807852804032304, -0.19509032201612828},
+    {0.9569403357322088, -0.2902846772544624},
+    {0.9238795325112867, -0.3826834323650898},
+    {0.881921264348355, -0.47139673682599764},
+    {0.8314696123025452, -0.5555702330196022},
+    {0.773010453362737, -0.6343932841636455},
+    {0.7071067811865476, -0.7071067811865476},
+    {0.6343932841636455, -0.773010453362737},
+    {0.5555702330196022, -0.8314696123025452},
+    {0.47139673682599764, -0.881921264348355},
+    {0.3826834323650898, -0.9238795325112867},
+    {0.2902846772544624, -0.9569403357322088},
+    {0.19509032201612828, -0.9807852804032304},
+    {0.0980171403295606, -0.9951847266721969},
     {0.0, -1.0},
-    {-9.80171403295606452621e-02, -9.95184726672196928732e-01},
-    {-1.95090322016128267848e-1, -9.80785280403230449126e-1},
-    {-2.90284677254462164520e-01, -9.56940335732208935404e-01},
-    {-3.82683432365089771728e-1, -9.23879532511286756128e-1},
-    {-4.71396736825997697551e-01, -8.81921264348355049556e-01},
-    {-5.55570233019602224743e-1, -8.31469612302545237079e-1},
-    {-6.34393284163645376772e-01, -7.73010453362737104399e-01},
-    {-7.07106781186547524401e-1, -7.07106781186547524401e-1},
-    {-7.73010453362736993377e-01, -6.34393284163645487794e-01},
-    {-8.31469612302545237079e-1, -5.55570233019602224743e-1},
-    {-8.81921264348354938534e-01, -4.71396736825997864084e-01},
-    {-9.23879532511286756128e-1, -3.82683432365089771728e-1},
-    {-9.56940335732208824382e-01, -2.90284677254462386564e-01},
-    {-9.80785280403230449126e-1, -1.95090322016128267848e-1},
-    {-9.95184726672196817709e-01, -9.80171403295608256734e-02},
+    {-0.0980171403295606, -0.9951847266721969},
+    {-0.19509032201612828, -0.9807852804032304},
+    {-0.2902846772544624, -0.9569403357322088},
+    {-0.3826834323650898, -0.9238795325112867},
+    {-0.47139673682599764, -0.881921264348355},
+    {-0.5555702330196022, -0.8314696123025452},
+    {-0.6343932841636455, -0.773010453362737},
+    {-0.7071067811865476, -0.7071067811865476},
+    {-0.773010453362737, -0.6343932841636455},
+    {-0.8314696123025452, -0.5555702330196022},
+    {-0.881921264348355, -0.47139673682599764},
+    {-0.9238795325112867, -0.3826834323650898},
+    {-0.9569403357322088, -0.2902846772544624},
+    {-0.9807852804032304, -0.19509032201612828},
+    {-0.9951847266721969, -0.0980171403295606},
 };
 
 template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle(int k) {

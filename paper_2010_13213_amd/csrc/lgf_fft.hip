@@ -135,19 +135,17 @@ __device__ __forceinline__ void fwd_body(const double *__restrict__ src, const i
 }
 
 // workgroup -> (block, chunk); the chunks of a block are consecutive and run
-// on one XCD (they read the same input block)
-template <int NB, typename R>
+// on one XCD (they read the same input block).  One instantiation per
+// spectrum layout, so each gets its own register allocation.
+template <int NB, typename R, bool BM>
 __global__ void __launch_bounds__(fft_threads<NB>) __attribute__((amdgpu_waves_per_eu(4))) fwd_kernel(const double *__restrict__ src, const int64_t *__restrict__ blk_off,
                                                   const int *__restrict__ slot, cplx<R> *__restrict__ Fhat,
-                                                  int64_t n_slots, int block_major, double scale) {
+                                                  int64_t n_slots, double scale) {
     using S = FftShape<NB, R>;
     __shared__ cplx<R> A[S::FA_ELEMS];
     __shared__ cplx<R> B[S::FB_ELEMS];
     const int wg = (int)xcd_order(blockIdx.x, gridDim.x);
-    if (block_major)
-        fwd_body<NB, R, true>(src, blk_off, slot, Fhat, n_slots, scale, wg / kSpecChunks, wg % kSpecChunks, A, B);
-    else
-        fwd_body<NB, R, false>(src, blk_off, slot, Fhat, n_slots, scale, wg / kSpecChunks, wg % kSpecChunks, A, B);
+    fwd_body<NB, R, BM>(src, blk_off, slot, Fhat, n_slots, scale, wg / kSpecChunks, wg % kSpecChunks, A, B);
 }
 
 __device__ __forceinline__ int find_job(const FftJob *__restrict__ jobs, int n_jobs, int b) {
@@ -310,8 +308,12 @@ template <int NB, typename R>
 hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot, int n_blocks, void *Fhat,
                       int64_t n_slots, bool block_major, double scale, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fwd_kernel<NB, R>), dim3(n_blocks * kSpecChunks), dim3(FftShape<NB, R>::NT), 0, s, src, blk_off, slot, (cplx<R> *)Fhat,
-                       n_slots, (int)block_major, scale);
+    if (block_major)
+        hipLaunchKernelGGL((fwd_kernel<NB, R, true>), dim3(n_blocks * kSpecChunks), dim3(FftShape<NB, R>::NT), 0, s,
+                           src, blk_off, slot, (cplx<R> *)Fhat, n_slots, scale);
+    else
+        hipLaunchKernelGGL((fwd_kernel<NB, R, false>), dim3(n_blocks * kSpecChunks), dim3(FftShape<NB, R>::NT), 0, s,
+                           src, blk_off, slot, (cplx<R> *)Fhat, n_slots, scale);
     return hipGetLastError();
 }
 

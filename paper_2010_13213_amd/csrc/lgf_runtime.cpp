@@ -305,6 +305,29 @@ static bool lattice_feasible(const std::vector<Blk> &src, const std::vector<Blk>
            lattice_zlen_ok(lattice_len(ext[2]));
 }
 
+// Under an HBM budget the lattice is a candidate only if the spectra it
+// would build still fit (the block-pair spectra of the same box are far
+// smaller); spectra already in the context cost nothing.
+static bool lattice_fits_budget(lgf_plan *plan, const std::vector<Blk> &src, const std::vector<Blk> &tgt,
+                                bool fp32) {
+    lgf_context *ctx = plan->ctx;
+    if (!ctx->budget) return true;
+    int lo[3], ext[3];
+    box_extent(src, tgt, lo, ext);
+    const int lx = lattice_len(ext[0]), ly = lattice_len(ext[1]), lz = lattice_len(ext[2]);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &t : ctx->lat_tables)
+        if (t->nb == plan->nb && t->fp32 == fp32 && t->ka == plan->build_ka && t->lx == lx && t->ly == ly &&
+            t->lz == lz)
+            return true;
+    const size_t n_freq = (size_t)(2 * plan->nb) * (2 * plan->nb) * (plan->nb + 1);
+    const size_t per_w = (size_t)lx * ly * lz;
+    size_t need = (fp32 ? 4 : 8) * per_w * (size_t)lattice_stored_freqs(2 * plan->nb) +
+                  std::min<size_t>(size_t(256) << 20, (fp32 ? 8 : 16) * per_w * n_freq);
+    need += (fp32 ? 8 : 16) * (size_t)(lx / 2) * (ly / 2) * (lz / 2) * n_freq + 2048 * n_freq * 16;
+    return ctx->used + need <= ctx->budget;
+}
+
 // A convolution whose MAC is the lattice FFT: slots over the tight bounding
 // box, spectra for its DFT lengths.
 static void build_conv_lattice(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std::vector<Blk> &tgt,
@@ -659,7 +682,7 @@ void build_conv(lgf_plan *plan, Conv &c, const std::vector<Blk> &src, const std:
     const int n_tiles = smac_tiles(bx, tiles, 4);
     std::vector<std::string> cand;
     for (int i = 0; i < n_tiles; ++i) cand.push_back("pairs " + std::to_string(tiles[i][0]) + "x" + std::to_string(tiles[i][1]));
-    const bool lattice_ok = lattice_feasible(src, tgt);
+    const bool lattice_ok = lattice_feasible(src, tgt) && lattice_fits_budget(plan, src, tgt, fp32);
     if (lattice_ok && ctx->mac_method != LGF_MAC_PAIRS) cand.push_back("lattice");
     if (lattice_ok && ctx->mac_method == LGF_MAC_LATTICE) cand.assign(1, "lattice");
     auto build = [&](Conv &into, const std::string &choice) {
