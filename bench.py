@@ -156,15 +156,9 @@ def cpu_model():
     return None
 
 
-def _time_direct(c, f, dx, rng, budget_s):
-    """Direct sums of all sources at a random target sample sized to take
-    about budget_s: returns (targets, seconds)."""
+def _time_direct(c, f, dx, rng, n):
+    """Direct sums of all sources at n random targets: (targets, seconds)."""
     from oracle import direct
-    probe = c[rng.choice(len(c), 2 * direct.num_threads(), replace=False)]   # every thread busy
-    t0 = time.perf_counter()
-    direct.direct_sum(c, f, probe, dx)
-    per = max(time.perf_counter() - t0, 1e-4) / len(probe)
-    n = int(max(8, min(len(c), budget_s / per)))
     tg = c[rng.choice(len(c), n, replace=False)]
     t0 = time.perf_counter()
     direct.direct_sum(c, f, tg, dx)
@@ -183,12 +177,17 @@ def cpu_baseline(problem, budget_s=10.0, seed=0):
     direct.build(force=False)
     direct.direct_sum(c[:1], f[:1], c[:1], problem.dx0)      # loads the library and its table
     threads = direct.num_threads()
-    n, dt = _time_direct(c, f, problem.dx0, rng, budget_s)
+    # one thread first: its rate sizes both samples (the OpenMP loop hands
+    # out targets 16 at a time, so a small all-core probe would idle cores)
     direct.set_num_threads(1)
     try:
-        n1, dt1 = _time_direct(c, f, problem.dx0, rng, budget_s / 2)
+        _, t_probe = _time_direct(c, f, problem.dx0, rng, 2)
+        n1, dt1 = _time_direct(c, f, problem.dx0, rng, max(4, int(0.4 * budget_s / (t_probe / 2))))
     finally:
         direct.set_num_threads(threads)
+    per1 = dt1 / n1
+    n = int(max(16 * threads, min(len(c), (budget_s * threads / per1) // (16 * threads) * 16 * threads)))
+    n, dt = _time_direct(c, f, problem.dx0, rng, n)
     gb = inputs.gaussian_box()
     cg = inputs.cell_coords(gb.levels[0].blocks, gb.nb)
     t0 = time.perf_counter()
