@@ -146,6 +146,27 @@ lgf_status lgf_plan_create(lgf_context *ctx, const lgf_problem *desc, lgf_plan *
 lgf_status lgf_plan_create_if(lgf_context *ctx, const lgf_problem *desc, double a0, lgf_plan **out);
 
 /*
+ * Fast-LGF far-field approximation (Sec. 2.2 and Sec. 5: the paper sums the
+ * LGF convolution with a fast multipole-type method on the block octree;
+ * this is a two-grid reading of it).  Block pairs within near_blocks blocks
+ * (max_i |t_i - s_i| <= near_blocks) are summed exactly; for the other pairs
+ * the kernel is replaced by its cubic interpolation from a lattice of nodes
+ * twice as coarse, (nb/2)^3 nodes per block at fine positions 2k + 1, every
+ * block interpolating from its own nodes (the 4 nearest per axis, the window
+ * kept inside the block):  u = u_near + I (G2_far * (A f)) with A = I^T
+ * (anterpolation) and G2_far the LGF at the even lattice vectors between
+ * nodes of far blocks, convolved over the node lattice by the same block
+ * engine (blocks of nb/2).  Not exact: the error falls roughly with the
+ * fourth power of the near radius; lgf_solve of a plan made by
+ * lgf_plan_create gives the exact sum.  Single-level problems of 16^3
+ * blocks in float64 without cell masks only (else LGF_E_UNSUPPORTED or
+ * LGF_E_INVALID); near_blocks in [0, 8].  The plan is used with lgf_solve,
+ * lgf_solve_scratch, lgf_solve_batch (it runs its own steps inside a batch)
+ * and the graph calls.
+ */
+lgf_status lgf_plan_create_flgf(lgf_context *ctx, const lgf_problem *desc, int near_blocks, lgf_plan **out);
+
+/*
  * Validate a problem description on the host only (no device work): the
  * same checks lgf_plan_create applies before it builds anything.  Returns
  * LGF_OK or LGF_E_INVALID with the reason in lgf_last_error().

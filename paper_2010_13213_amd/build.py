@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblgf.so")
-SOURCES = ["lgf_table.hip", "lgf_fft.hip", "lgf_smac.hip", "lgf_lattice.hip", "lgf_composite.hip", "lgf_refine.hip", "lgf_refresh.hip", "lgf_runtime.cpp", "lgf_schedule.cpp",
+SOURCES = ["lgf_table.hip", "lgf_fft.hip", "lgf_smac.hip", "lgf_lattice.hip", "lgf_composite.hip", "lgf_refine.hip", "lgf_refresh.hip", "lgf_flgf.hip", "lgf_runtime.cpp", "lgf_schedule.cpp",
            "lgf_tuning.cpp", "lgf_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",

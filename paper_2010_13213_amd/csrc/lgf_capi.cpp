@@ -272,6 +272,34 @@ lgf_status lgf_plan_create_if(lgf_context *ctx, const lgf_problem *desc, double 
     return LGF_OK;
 }
 
+lgf_status lgf_plan_create_flgf(lgf_context *ctx, const lgf_problem *desc, int near_blocks, lgf_plan **out) {
+    if (!ctx || !out) {
+        set_error("null context or out pointer");
+        return LGF_E_INVALID;
+    }
+    *out = nullptr;
+    lgf_plan *p = new lgf_plan();
+    p->ctx = ctx;
+    lgf_status st = guard([&] {
+        require(near_blocks >= 0 && near_blocks <= 8, "near_blocks must be in [0, 8]");
+        DeviceScope ds(ctx->device);
+        validate_and_copy(p, desc);
+        if (p->K != 1 || p->nb != 16 || p->prec != LGF_FP64)
+            throw Failure(LGF_E_UNSUPPORTED, "the fast-LGF approximation serves single-level float64 plans of 16^3 blocks");
+        require(p->cell_mask[0].empty(), "the fast-LGF approximation takes no cell mask");
+        p->flgf_D = near_blocks;
+        p->kernel0.band = 1;
+        p->kernel0.D = near_blocks;
+        build_schedule(p);
+    });
+    if (st != LGF_OK) {
+        lgf_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return LGF_OK;
+}
+
 lgf_status lgf_problem_check(const lgf_problem *desc) {
     return guard([&] {
         lgf_plan tmp;
@@ -525,7 +553,7 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
         t.data.alloc(ctx, 16 * n_off * n_freq, "spectrum");
         DeviceBuffer scratch;
         scratch.alloc(ctx, 16 * n_freq * std::min<size_t>(n_off, 512), "spectrum scratch");
-        hip_check(build_spectra((const double *)ctx->gcube.ptr, true, nb, ax, ay, az, false, t.data.ptr, scratch.ptr,
+        hip_check(build_spectra((const double *)ctx->gcube.ptr, true, 1, 0, 0, nb, ax, ay, az, false, t.data.ptr, scratch.ptr,
                                 scratch.bytes, ctx->stream),
                   "build_spectra");
         hip_check(hipStreamSynchronize(ctx->stream), "sync");

@@ -13,8 +13,11 @@ hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int
 // Spectra of every block offset in [0,XH] x [0,YH] x [0,ZH] into
 // table[omega][dy][dz][dx] (complex float or double); offsets with negative
 // components are served by reflection.
-hipError_t build_spectra(const double *gcube, bool far, int nb, int XH, int YH, int ZH, bool fp32, void *table,
-                         void *scratch, size_t scratch_bytes, hipStream_t s);
+// far: the LGF (cube, then the asymptotic series) or a cube kernel that is 0
+// beyond the cube; the kernel is sampled at stride * n; band 1 keeps only
+// block offsets with max |d_i| <= D, band 2 only those beyond (0: all).
+hipError_t build_spectra(const double *gcube, bool far, int stride, int band, int D, int nb, int XH, int YH, int ZH,
+                         bool fp32, void *table, void *scratch, size_t scratch_bytes, hipStream_t s);
 // Integrating-factor kernel E(n) = prod_i e^{-2a} I_{n_i}(2a) on the near
 // cube layout (row: kTableRadius + 1 doubles of scratch, w: one double).
 hipError_t build_if_table(double *cube, double *row, double *w, double a, hipStream_t s);
@@ -190,6 +193,12 @@ hipError_t copy_blocks(int nb, const double *src, double *dst, const int64_t *sr
 // p[0, bytes) = 0 by a kernel (bytes and p 16-byte aligned); a memset node
 // is avoided in code that a caller may capture into a graph.
 hipError_t zero_fill(void *p, size_t bytes, hipStream_t s);
+
+// Two-grid fast-LGF far field (lgf_flgf.hip), nb = 16 only: per block, the
+// cells at f + off[b] anterpolated to the block's (nb/2)^3 nodes at
+// Fc + b (nb/2)^3, and node values Uc interpolated and added to u + off[b].
+hipError_t flgf_anterpolate(int nb, const double *f, const int64_t *off, int n_blocks, double *Fc, hipStream_t s);
+hipError_t flgf_interpolate_add(int nb, const double *Uc, const int64_t *off, int n_blocks, double *u, hipStream_t s);
 
 // Per block of nb^3 values at v + off[b] (off null: v + b * nb^3): the sum
 // of squares into out[2b] and the largest magnitude into out[2b + 1].

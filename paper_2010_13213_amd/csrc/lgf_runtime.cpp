@@ -157,7 +157,7 @@ static const double *if_cube(lgf_context *ctx, double a) {
     return p;
 }
 
-SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, double ka) {
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, const KernelId &ka) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &t : ctx->tables)
         if (t->nb == nb && t->fp32 == fp32 && t->ka == ka && t->XH >= XH && t->YH >= YH && t->ZH >= ZH)
@@ -178,9 +178,9 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     const size_t per_off = (size_t)t->n_freq * 16;
     const size_t want = std::min<size_t>(n_off, 2048) * per_off;
     scratch.alloc(ctx, want, "spectra scratch");
-    const double *kern = ka > 0.0 ? if_cube(ctx, ka) : (const double *)ctx->gcube.ptr;
-    hip_check(build_spectra(kern, ka <= 0.0, nb, XH, YH, ZH, fp32, t->data.ptr, scratch.ptr, scratch.bytes,
-                            ctx->stream),
+    const double *kern = ka.a > 0.0 ? if_cube(ctx, ka.a) : (const double *)ctx->gcube.ptr;
+    hip_check(build_spectra(kern, ka.a <= 0.0, ka.stride, ka.band, ka.D, nb, XH, YH, ZH, fp32, t->data.ptr,
+                            scratch.ptr, scratch.bytes, ctx->stream),
               "build_spectra");
     hip_check(hipStreamSynchronize(ctx->stream), "spectra sync");
     {
@@ -210,7 +210,7 @@ SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int 
     return ctx->tables.back().get();
 }
 
-LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, double ka) {
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, const KernelId &ka) {
     auto find = [&]() -> LatSpec * {
         for (auto &t : ctx->lat_tables)
             if (t->nb == nb && t->fp32 == fp32 && t->ka == ka && t->lx == lx && t->ly == ly && t->lz == lz)

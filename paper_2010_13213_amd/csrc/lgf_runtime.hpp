@@ -50,10 +50,23 @@ struct DeviceBuffer {
     void release();
 };
 
+// The kernel of a convolution: the LGF (a = 0) or the integrating factor
+// E(a) (a > 0), sampled at stride * n, and all block offsets (band 0), only
+// those with max |d_i| <= D (band 1, near) or only those beyond (band 2, far).
+struct KernelId {
+    double a = 0.0;
+    int stride = 1;
+    int band = 0;
+    int D = 0;
+    bool operator==(const KernelId &o) const {
+        return a == o.a && stride == o.stride && band == o.band && (band == 0 || D == o.D);
+    }
+};
+
 struct SpecTable {
     int nb = 0;
     bool fp32 = false;
-    double ka = 0.0;        // kernel: 0 the LGF, > 0 the integrating factor E(a = ka)
+    KernelId ka;            // the kernel whose windows the table holds
     int XH = 0, YH = 0, ZH = 0;
     int n_freq = 0;
     DeviceBuffer data;
@@ -83,7 +96,7 @@ struct JobRing {
 struct LatSpec {
     int nb = 0;
     bool fp32 = false;
-    double ka = 0.0;              // kernel, as SpecTable::ka
+    KernelId ka;                  // kernel, as SpecTable::ka
     int lx = 0, ly = 0, lz = 0;
     int n_freq = 0;
     DeviceBuffer data;
@@ -207,8 +220,8 @@ struct LevelSched {
     std::unique_ptr<ConvOp> convF, convPsi;
 };
 
-SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, double ka);
-LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, double ka);
+SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, const KernelId &ka);
+LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, const KernelId &ka);
 LatGeom lat_geom(const Conv &c, int nc);
 // every slot of the convolution holds a source block: its forward FFTs
 // write the whole spectral region it reads
@@ -246,7 +259,11 @@ struct lgf_plan {
     const lgf::Conv *fhat_conv = nullptr;          // conv whose slot map Fhat currently holds
     const lgf::SpecWs *ws_scratch = nullptr;       // set only during a static-scratch solve
     double if_a0 = 0.0;                            // > 0: integrating-factor plan, a on level 0 (a_k = 4^k a0)
-    double build_ka = 0.0;                         // kernel of the convolutions being built (0: the LGF)
+    lgf::KernelId kernel0;                         // kernel of the plan's level-0 convolutions
+    lgf::KernelId build_ka;                        // kernel of the convolutions being built
+    int flgf_D = -1;                               // >= 0: two-grid fast-LGF plan with near radius D blocks
+    std::unique_ptr<lgf_plan> flgf_coarse;         // its far field on the node lattice (nb/2 per block)
+    lgf::DeviceBuffer ws_fc, ws_uc;                // node-lattice source and result
     int n_q0 = 0;                                  // integrating factor, composite: level-0 blocks in dom(psi_0)
     lgf::DeviceBuffer d_q0_src, d_q0_dst;
     lgf::DeviceBuffer d_blk_off, d_blk_back;       // single level: block offsets; with 3 components also the

@@ -63,7 +63,8 @@ void build_schedule(lgf_plan *p) {
     const int64_t nb3 = (int64_t)nb * nb * nb;
     p->mac_nc = std::min(p->nc, kMacComponents);
     const bool fif = p->if_a0 > 0.0;
-    p->build_ka = fif ? p->if_a0 : 0.0;
+    p->build_ka = p->kernel0;
+    if (fif) p->build_ka.a = p->if_a0;
     if (K == 1) {
         p->op0 = build_op(p, p->levels[0], p->levels[0], refine);
         plan_alloc_refine(p, {p->op0.get()});
@@ -77,6 +78,30 @@ void build_schedule(lgf_plan *p) {
             p->src_ijk[0].insert(p->src_ijk[0].end(), b.ijk, b.ijk + 3);
         }
         upload(ctx, p->d_blk_off, off, "block offsets");
+        if (p->flgf_D >= 0) {   // the far field: the same blocks on the node lattice (nb/2), far band, G(2n)
+            auto c = std::make_unique<lgf_plan>();
+            c->ctx = ctx;
+            c->K = 1;
+            c->nb = nb / 2;
+            c->nc = p->nc;
+            c->prec = LGF_FP64;
+            c->ne = 1;
+            c->dx0 = p->dx0;
+            const int64_t h3 = (int64_t)c->nb * c->nb * c->nb;
+            std::vector<Blk> cb = p->levels[0];
+            for (size_t i = 0; i < cb.size(); ++i) cb[i].off = (int64_t)i * h3;
+            c->levels.push_back(cb);
+            c->level_base.push_back(0);
+            c->comp_len = (int64_t)cb.size() * h3;
+            c->cell_mask.assign(1, {});
+            c->kernel0.stride = 2;
+            c->kernel0.band = 2;
+            c->kernel0.D = p->flgf_D;
+            build_schedule(c.get());
+            p->ws_fc.alloc(ctx, sizeof(double) * c->comp_len * p->nc, "node-lattice source");
+            p->ws_uc.alloc(ctx, sizeof(double) * c->comp_len * p->nc, "node-lattice field");
+            p->flgf_coarse = std::move(c);
+        }
         if (p->nc == 3) {      // the velocity refresh's curl reads backward neighbours
             for (const auto &b : p->levels[0])
                 for (int a = 0; a < 3; ++a) {
@@ -171,7 +196,7 @@ void build_schedule(lgf_plan *p) {
         // convolution of the phi right-hand side: sources -> Omega_k targets
         // (the integrating factor of level k has a_k = 4^k a_0)
         std::vector<Blk> src = (k == 0) ? p->levels[0] : as_blk(ext[k]);
-        if (fif) p->build_ka = p->if_a0 * (double)(1 << (2 * k));
+        if (fif) p->build_ka.a = p->if_a0 * (double)(1 << (2 * k));
         L.convF = build_op(p, src, p->levels[k], refine);
         if (k + 1 < K) {
             std::vector<Blk> tgt = as_blk(dom[k]);
@@ -470,6 +495,17 @@ static void enqueue(lgf_plan *p, const double *f, double *u, hipStream_t s) {
                                   (double *)p->d_ind.ptr + 2 * c * p->ind_total, s),
                       "indicator");
     run_op(p, *p->op0, f, p->comp_len, u, p->comp_len, p->nc, p->dx0, 0, s);
+    if (lgf_plan *c = p->flgf_coarse.get()) {   // + I (far convolution on the node lattice) A f
+        double *Fc = (double *)p->ws_fc.ptr, *Uc = (double *)p->ws_uc.ptr;
+        for (int k = 0; k < p->nc; ++k)
+            hip_check(flgf_anterpolate(p->nb, f + (size_t)k * p->comp_len, boff, nblk, Fc + (size_t)k * c->comp_len, s),
+                      "anterpolate");
+        run_op(c, *c->op0, Fc, c->comp_len, Uc, c->comp_len, c->nc, c->dx0, 0, s);
+        for (int k = 0; k < p->nc; ++k)
+            hip_check(flgf_interpolate_add(p->nb, Uc + (size_t)k * c->comp_len, boff, nblk, u + (size_t)k * p->comp_len,
+                                           s),
+                      "interpolate");
+    }
     if (cm)
         for (int c = 0; c < p->nc; ++c)
             hip_check(mask_blocks(p->nb, u + (size_t)c * p->comp_len, u + (size_t)c * p->comp_len, boff, boff, nullptr,
@@ -861,7 +897,7 @@ void run_batch(lgf_context *ctx, int n, lgf_plan *const *plans, const double *co
         std::vector<const double *> cfs;
         std::vector<double *> cus;
         for (int i : kv.second) {
-            if (plans[i]->K == 1 && plans[i]->d_cmask0.ptr) {   // a cell mask: the plan's own masking steps
+            if (plans[i]->K == 1 && (plans[i]->d_cmask0.ptr || plans[i]->flgf_coarse)) {   // own extra steps
                 enqueue(plans[i], f[i], u[i], s);
             } else if (plans[i]->K == 1) {
                 single.push_back(i);

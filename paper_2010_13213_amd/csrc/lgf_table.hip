@@ -125,6 +125,8 @@ struct SpecGeom {
     int nb, XH, YH, ZH, XD, YD, ZD;
     int o_begin, o_count;   // linear offset range [o_begin, o_begin + o_count)
     int far;                // 1: the LGF (cube + asymptotic series); 0: a cube kernel, 0 beyond it
+    int stride;             // the kernel sampled at stride * n
+    int band, D;            // 0: every offset; 1: only max|d_i| <= D; 2: only max|d_i| > D
 };
 
 __device__ __forceinline__ void offset_of(const SpecGeom &g, int o, int &dx, int &dy, int &dz) {
@@ -149,12 +151,14 @@ __global__ void spec_pass_x(const double *__restrict__ gc, SpecGeom g, cplx<doub
     int dx, dy, dz;
     offset_of(g, g.o_begin + ol, dx, dy, dz);
     cplx<double> a[N];
-    const bool zero_row = (y == N / 2) || (z == N / 2);
+    const int dm = max(dx, max(dy, dz));
+    const bool zero_row = (y == N / 2) || (z == N / 2) || (g.band == 1 && dm > g.D) || (g.band == 2 && dm <= g.D);
 #pragma unroll
     for (int x = 0; x < N; ++x) {
         double v = 0.0;
         if (!zero_row && x != N / 2)
-            v = kernel_at(gc, g.far != 0, dx * g.nb + circ<N>(x), dy * g.nb + circ<N>(y), dz * g.nb + circ<N>(z));
+            v = kernel_at(gc, g.far != 0, g.stride * (dx * g.nb + circ<N>(x)), g.stride * (dy * g.nb + circ<N>(y)),
+                          g.stride * (dz * g.nb + circ<N>(z)));
         a[x] = cmake(v, 0.0);
     }
     fft_reg<double, N, false>(a);
@@ -203,11 +207,14 @@ __global__ void spec_pass_z(SpecGeom g, const cplx<double> *__restrict__ S, cplx
 }
 
 template <int N, typename T>
-hipError_t build_spectra_n(const double *gc, bool far, int nb, int XH, int YH, int ZH, void *table, void *scratch,
-                           size_t scratch_bytes, hipStream_t s) {
+hipError_t build_spectra_n(const double *gc, bool far, int stride, int band, int D, int nb, int XH, int YH, int ZH,
+                           void *table, void *scratch, size_t scratch_bytes, hipStream_t s) {
     constexpr int H = N / 2 + 1;
     SpecGeom g;
     g.far = far ? 1 : 0;
+    g.stride = stride;
+    g.band = band;
+    g.D = D;
     g.nb = nb;
     g.XH = XH;
     g.YH = YH;
@@ -258,14 +265,18 @@ hipError_t eval_lgf_points(const double *gcube, const int *ijk, double *out, int
     return hipGetLastError();
 }
 
-hipError_t build_spectra(const double *gcube, bool far, int nb, int XH, int YH, int ZH, bool fp32, void *table,
-                         void *scratch, size_t scratch_bytes, hipStream_t s) {
+hipError_t build_spectra(const double *gcube, bool far, int stride, int band, int D, int nb, int XH, int YH, int ZH,
+                         bool fp32, void *table, void *scratch, size_t scratch_bytes, hipStream_t s) {
     if (nb == 16)
-        return fp32 ? build_spectra_n<32, float>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
-                    : build_spectra_n<32, double>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
+        return fp32 ? build_spectra_n<32, float>(gcube, far, stride, band, D, nb, XH, YH, ZH, table, scratch,
+                                                 scratch_bytes, s)
+                    : build_spectra_n<32, double>(gcube, far, stride, band, D, nb, XH, YH, ZH, table, scratch,
+                                                  scratch_bytes, s);
     if (nb == 8)
-        return fp32 ? build_spectra_n<16, float>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s)
-                    : build_spectra_n<16, double>(gcube, far, nb, XH, YH, ZH, table, scratch, scratch_bytes, s);
+        return fp32 ? build_spectra_n<16, float>(gcube, far, stride, band, D, nb, XH, YH, ZH, table, scratch,
+                                                 scratch_bytes, s)
+                    : build_spectra_n<16, double>(gcube, far, stride, band, D, nb, XH, YH, ZH, table, scratch,
+                                                  scratch_bytes, s);
     return hipErrorInvalidValue;
 }
 

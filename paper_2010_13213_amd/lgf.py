@@ -17,7 +17,7 @@ LGF_FP64, LGF_FP32_REFINE = 0, 1
 _PREC = {"fp64": LGF_FP64, "fp32_refine": LGF_FP32_REFINE}
 
 EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "lgf_plan_create",
-            "lgf_plan_create_if",
+            "lgf_plan_create_if", "lgf_plan_create_flgf",
             "lgf_problem_check",
             "lgf_plan_destroy", "lgf_plan_workspace_bytes", "lgf_plan_cells", "lgf_plan_field_len",
             "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_indicator",
@@ -79,6 +79,8 @@ def lib():
     L.lgf_plan_create.restype = ctypes.c_int
     L.lgf_plan_create_if.argtypes = [vp, ctypes.POINTER(_Problem), ctypes.c_double, ctypes.POINTER(vp)]
     L.lgf_plan_create_if.restype = ctypes.c_int
+    L.lgf_plan_create_flgf.argtypes = [vp, ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(vp)]
+    L.lgf_plan_create_flgf.restype = ctypes.c_int
     L.lgf_problem_check.argtypes = [ctypes.POINTER(_Problem)]
     L.lgf_problem_check.restype = ctypes.c_int
     L.lgf_plan_destroy.argtypes = [vp]
@@ -275,11 +277,13 @@ class Plan:
     """An immutable solve plan for one block support (all levels)."""
 
     def __init__(self, ctx, level_blocks, nb, dx0, n_components=1, precision="fp64", ne_blocks=0, if_a0=None,
-                 cell_masks=None):
+                 cell_masks=None, flgf_near=None):
         """if_a0: None for the LGF solve (L^-1); a > 0 for the integrating
         factor H(a) = exp(a L) on level 0 (a_k = 4^k a on level k).
         cell_masks: None or one entry per level, None or nb^3 bytes per
-        block ([block][z][y][x]; 1 keeps the cell in Omega_k)."""
+        block ([block][z][y][x]; 1 keeps the cell in Omega_k).
+        flgf_near: None for the exact sum; D >= 0 for the two-grid fast-LGF
+        approximation with block pairs within D blocks summed exactly."""
         self.ctx = ctx
         self.nb = int(nb)
         self.n_levels = len(level_blocks)
@@ -287,18 +291,20 @@ class Plan:
         self.precision = precision
         prob, self._keep = _problem(level_blocks, nb, dx0, n_components, precision, ne_blocks, cell_masks)
         h = ctypes.c_void_p()
-        if if_a0 is None:
+        if flgf_near is not None:
+            _check(lib().lgf_plan_create_flgf(ctx.handle, ctypes.byref(prob), int(flgf_near), ctypes.byref(h)))
+        elif if_a0 is None:
             _check(lib().lgf_plan_create(ctx.handle, ctypes.byref(prob), ctypes.byref(h)))
         else:
             _check(lib().lgf_plan_create_if(ctx.handle, ctypes.byref(prob), float(if_a0), ctypes.byref(h)))
         self._h = h
 
     @classmethod
-    def for_problem(cls, ctx, problem, precision="fp64", ne_blocks=0, if_a0=None):
+    def for_problem(cls, ctx, problem, precision="fp64", ne_blocks=0, if_a0=None, flgf_near=None):
         masks = [getattr(lv, "cell_mask", None) for lv in problem.levels]
         return cls(ctx, [lv.blocks for lv in problem.levels], problem.nb, problem.dx0,
                    problem.n_components, precision, ne_blocks, if_a0,
-                   None if all(m is None for m in masks) else masks)
+                   None if all(m is None for m in masks) else masks, flgf_near)
 
     @property
     def handle(self):
