@@ -417,6 +417,8 @@ def main():
             "ratio_vs_fp64": (cells * args.steps / r32["wall"]) / value},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in r64["stages"].items()},
         "roofline": roof,
+        "build": {"library": os.path.relpath(lgf.LIB_PATH, os.path.dirname(os.path.abspath(__file__))),
+                  "id": lgf.build_id()},
     }
     if not args.no_serving:
         from paper_2010_13213_amd import serve

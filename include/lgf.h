@@ -398,6 +398,13 @@ lgf_status lgf_context_tuning_size(lgf_context *ctx, int64_t *n_entries);
 const char *lgf_last_error(void);
 const char *lgf_status_string(lgf_status s);
 
+/* Build provenance (no passage of the paper: it ties a library file to the
+ * sources it was compiled from).  Returns a static NUL-terminated string
+ * "sha256=<64 hex digits> arch=gfx950": the digest is the SHA-256 of every
+ * kernel, runtime and header source and of the compiler flags, computed by
+ * the build script before compiling.  Never NULL; callable without a GPU. */
+const char *lgf_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

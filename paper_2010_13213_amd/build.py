@@ -24,9 +24,27 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-u
          "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src):
+def source_digest():
+    """SHA-256 over the library's sources (csrc/, include/) and the compiler
+    flags, in a fixed order; the build bakes it into lgf_build_id()."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(FLAGS[:-2]).encode())
+    files = []
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for name in sorted(os.listdir(d)):
+            if os.path.splitext(name)[1] in (".hip", ".cpp", ".hpp", ".h"):
+                files.append(os.path.join(d, name))
+    for path in files:
+        h.update(os.path.relpath(path, ROOT).encode() + b"\0")
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _compile(src, digest):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ['-DLGF_SOURCE_SHA256="%s"' % digest, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
@@ -35,8 +53,9 @@ def _compile(src):
 
 def build(jobs=8):
     os.makedirs(BUILD, exist_ok=True)
+    digest = source_digest()
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, digest), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

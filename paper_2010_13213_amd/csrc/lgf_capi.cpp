@@ -643,6 +643,12 @@ lgf_status lgf_context_tuning_size(lgf_context *ctx, int64_t *n_entries) {
 
 const char *lgf_last_error(void) { return g_last_error.c_str(); }
 
+#ifndef LGF_SOURCE_SHA256
+#define LGF_SOURCE_SHA256 "unknown"
+#endif
+
+const char *lgf_build_id(void) { return "sha256=" LGF_SOURCE_SHA256 " arch=gfx950"; }
+
 const char *lgf_status_string(lgf_status s) {
     switch (s) {
     case LGF_OK: return "LGF_OK";

@@ -23,7 +23,7 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_solve", "lgf_solve_scratch", "lgf_velocity_refresh", "lgf_solve_indicator",
             "lgf_plan_source_blocks", "lgf_solve_batch", "lgf_table_values", "lgf_table_radius",
             "lgf_block_spectrum", "lgf_context_set_timing", "lgf_context_stage_times",
-            "lgf_last_error", "lgf_status_string", "lgf_graph_create", "lgf_graph_create_batch", "lgf_graph_launch",
+            "lgf_last_error", "lgf_status_string", "lgf_build_id", "lgf_graph_create", "lgf_graph_create_batch", "lgf_graph_launch",
             "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
             "lgf_context_set_mac_method",
@@ -55,6 +55,21 @@ class Report(ctypes.Structure):
 _lib = None
 
 
+def _check_build(bid):
+    """The library must have been built from the sources beside it: a stale
+    liblgf.so would test and time other code than the tree holds."""
+    from . import build as _build
+    want = "sha256=" + _build.source_digest()
+    if not bid.startswith(want + " "):
+        raise RuntimeError("liblgf.so (%s) was built from other sources than %s (%s); rebuild with "
+                           "python -m paper_2010_13213_amd.build" % (bid, _HERE, want))
+
+
+def build_id():
+    """lgf_build_id() of the loaded library: source digest and target."""
+    return lib().lgf_build_id().decode()
+
+
 def lib():
     """Load liblgf.so; raise if it is missing (no CPU fallback exists)."""
     global _lib
@@ -68,6 +83,9 @@ def lib():
     # single runtime (loading the library first leaves torch without devices)
     import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    L.lgf_build_id.argtypes = []
+    L.lgf_build_id.restype = ctypes.c_char_p
+    _check_build(L.lgf_build_id().decode())
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     L.lgf_context_create.argtypes = [ctypes.c_int, sz, ctypes.POINTER(vp)]
     L.lgf_context_create.restype = ctypes.c_int

@@ -33,6 +33,18 @@ def test_status_strings():
     assert L.lgf_table_radius() == 128
 
 
+def test_build_id_names_the_sources_in_the_tree():
+    from paper_2010_13213_amd import build
+    bid = lgf.build_id()
+    assert re.fullmatch(r"sha256=[0-9a-f]{64} arch=gfx950", bid), bid
+    assert bid.split()[0] == "sha256=" + build.source_digest()
+
+
+def test_stale_library_is_refused():
+    with pytest.raises(RuntimeError, match="built from other sources"):
+        lgf._check_build("sha256=" + "0" * 64 + " arch=gfx950")
+
+
 def _cube(n, lo=0):
     return np.array([(x, y, z) for z in range(lo, lo + n) for y in range(lo, lo + n)
                      for x in range(lo, lo + n)])
