@@ -5,8 +5,7 @@
 //   per-thread array; all indices are compile-time so the array lives in
 //   VGPRs.  Forward uses exp(-2 pi i k / N), inverse exp(+2 pi i k / N), no
 //   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 64),
-//   folded into the unrolled butterflies; the trivial and quarter-turn ones
-//   cost no multiply (twmul).
+//   folded into the unrolled butterflies.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -108,16 +107,6 @@ template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddl
     return INV ? cmake(c, -s) : cmake(c, s);
 }
 
-// v * twiddle<R, N, INV>(k) for an index known at compile time after
-// unrolling: k = 0 returns v, the quarter turn (4k = N) swaps the components
-// with one sign change (what the full product gives for finite v, without
-// its multiplies), any other k is one complex product.
-template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twmul(cplx<R> v, int k) {
-    if (k == 0) return v;
-    if (4 * k == N) return INV ? cmake(-v.y, v.x) : cmake(v.y, -v.x);
-    return cmul(v, twiddle<R, N, INV>(k));
-}
-
 template <int N> struct bitrev {
     static constexpr int L = (N == 64) ? 6 : (N == 32) ? 5 : (N == 16) ? 4 : (N == 8) ? 3 : (N == 4) ? 2 : 1;
     static __host__ __device__ constexpr int of(int i) {
@@ -149,7 +138,7 @@ template <typename R, int N, bool INV> __device__ __forceinline__ void fft_reg(c
 #pragma unroll
             for (int k = 0; k < half; ++k) {
                 cplx<R> v = a[i + k + half];
-                v = twmul<R, N, INV>(v, k * (N / len));
+                if (k != 0) v = cmul(v, twiddle<R, N, INV>(k * (N / len)));
                 const cplx<R> u = a[i + k];
                 a[i + k] = cadd(u, v);
                 a[i + k + half] = csub(u, v);

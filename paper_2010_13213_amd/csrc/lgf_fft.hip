@@ -56,7 +56,7 @@ template <int NB> constexpr int fft_threads = 2 * NB * NB;   // FftShape<NB, R>:
 // x[n] * w^n (the odd half's input), n < M, w = exp(-2 pi i / N)
 template <typename R, int N, int M> __device__ __forceinline__ void odd_twiddle(cplx<R> (&a)[M]) {
 #pragma unroll
-    for (int n = 1; n < M; ++n) a[n] = twmul<R, N, false>(a[n], n);
+    for (int n = 1; n < M; ++n) a[n] = cmul(a[n], twiddle<R, N, false>(n));
 }
 
 // Spectrum position p of slot sl at Fhat[p * ws + sl * ss]: frequency-major

@@ -74,7 +74,7 @@ template <typename R, int L> __device__ __forceinline__ void pair_fwd(cplx<R> (&
 #pragma unroll
     for (int n = 1; n < L / 2; ++n) {
         // select on data, not on the twiddle: the constants stay literal
-        const cplx<R> t = twmul<R, L, false>(a[n], n);
+        const cplx<R> t = cmul(a[n], twiddle<R, L, false>(n));
         a[n] = csel(odd, t, a[n]);
     }
     fft_reg<R, L / 2, false>(a);
@@ -94,8 +94,8 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
         cplx<R> recv;
         recv.x = __shfl_xor(send.x, 1);
         recv.y = __shfl_xor(send.y, 1);
-        const cplx<R> ye = cadd(a[j], twmul<R, L, true>(recv, j));     // even lane: n = j
-        const cplx<R> yo = cadd(recv, twmul<R, L, true>(a[jo], jo));   // odd lane: n = jo
+        const cplx<R> ye = cadd(a[j], cmul(recv, twiddle<R, L, true>(j)));     // even lane: n = j
+        const cplx<R> yo = cadd(recv, cmul(a[jo], twiddle<R, L, true>(jo)));   // odd lane: n = jo
         out[j] = csel(odd, yo, ye);
     }
 }
@@ -216,7 +216,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
             for (int n = 0; n < MY; ++n) a[n] = prow[n];
             if (HF) {
 #pragma unroll
-                for (int n = 1; n < MY; ++n) a[n] = twmul<R, LY, false>(a[n], n);
+                for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
             }
             fft_reg<R, MY, false>(a);
         }
@@ -234,7 +234,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
             for (int n = 0; n < MY; ++n) a[n] = prow[n];
             if (HF) {
 #pragma unroll
-                for (int n = 1; n < MY; ++n) a[n] = twmul<R, LY, false>(a[n], n);
+                for (int n = 1; n < MY; ++n) a[n] = cmul(a[n], twiddle<R, LY, false>(n));
             }
             fft_reg<R, MY, false>(a);
 #pragma unroll
@@ -250,7 +250,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     for (int n = 0; n < MZ; ++n) a[n] = qline[n];
     if (HF) {
 #pragma unroll
-        for (int n = 1; n < MZ; ++n) a[n] = twmul<R, LZ, false>(a[n], n);
+        for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
     }
     fft_reg<R, MZ, false>(a);
 #pragma unroll
@@ -268,10 +268,10 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     __syncthreads();
     if (HF) {
 #pragma unroll
-        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], twmul<R, LZ, true>(a[j], j));
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
     } else {
 #pragma unroll
-        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], twmul<R, LZ, true>(qline[j], j));
+        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
     }
     __syncthreads();
     // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
@@ -301,10 +301,10 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
         if (on) {
             if (HF) {
 #pragma unroll
-                for (int j = MY / 2; j < MY; ++j) prow[j] = cadd(prow[j], twmul<R, LY, true>(b[j], j));
+                for (int j = MY / 2; j < MY; ++j) prow[j] = cadd(prow[j], cmul(b[j], twiddle<R, LY, true>(j)));
             } else {
 #pragma unroll
-                for (int j = 0; j < MY / 2; ++j) prow[j] = cadd(b[j], twmul<R, LY, true>(prow[j], j));
+                for (int j = 0; j < MY / 2; ++j) prow[j] = cadd(b[j], cmul(prow[j], twiddle<R, LY, true>(j)));
             }
         }
         __syncthreads();
