@@ -69,11 +69,16 @@ def lattice_len(extent):
     return L
 
 
-def config_table(ctx, reps=3):
+WORKLOADS = ["gaussian_box_32^3", "ring_128^3_vector", "two_level_ring", "colliding_rings_quarter",
+             "colliding_rings"]
+
+
+def config_table(ctx, reps=3, only=None):
     """Every workload of the hot path, FP64 and FP32+refine: plan time, median
-    solve time, target cells/s and the error against stored oracle samples
-    (tests/golden, written by scripts that call only the oracle) where such
-    samples exist, else the difference to the FP64 result."""
+    solve time (wall, and device time between events on the solve stream),
+    target cells/s and the error against stored oracle samples (tests/golden,
+    written by scripts that call only the oracle) where such samples exist,
+    else the difference to the FP64 result.  only: a list of workload names."""
     import numpy as np
     import torch
     from paper_2010_13213_amd import inputs, lgf
@@ -86,10 +91,12 @@ def config_table(ctx, reps=3):
          os.path.join(gold, "two_level_ring_samples.npz")),
         ("colliding_rings_quarter", lambda: inputs.colliding_rings(nb=8, dx0=1.0 / 8, components=(0, 2)),
          os.path.join(gold, "colliding_rings_quarter_samples.npz")),
-        ("colliding_rings", lambda: inputs.colliding_rings(), None),
+        ("colliding_rings", lambda: inputs.colliding_rings(), os.path.join(gold, "colliding_rings_full_samples.npz")),
     ]
     table = {}
     for name, make, gpath in cases:
+        if only and name not in only:
+            continue
         prob = make()
         f = torch.from_numpy(prob.flat_source()).cuda()
         cells = prob.n_cells() * prob.n_components
@@ -103,28 +110,40 @@ def config_table(ctx, reps=3):
             u = torch.empty_like(f)
             plan.solve(f, u)
             torch.cuda.synchronize()
-            ts = []
+            ts, dev = [], []
             for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 t0 = time.perf_counter()
+                e0.record()
                 plan.solve(f, u)
+                e1.record()
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
+                dev.append(e0.elapsed_time(e1))
+            ws = plan.workspace_bytes()
             plan.close()
             res[prec] = u.cpu().numpy().reshape(prob.n_components, -1)
             ms = 1e3 * float(np.median(ts))
-            print("config %s %s: plan %.2f s, solve %.3f ms" % (name, prec, t_plan, ms), file=sys.stderr, flush=True)
-            row[prec] = {"plan_s": round(t_plan, 3), "solve_ms": ms, "cells_per_s": cells / (ms * 1e-3)}
+            print("config %s %s: plan %.2f s, solve %.3f ms (device %.3f ms)"
+                  % (name, prec, t_plan, ms, float(np.median(dev))), file=sys.stderr, flush=True)
+            row[prec] = {"plan_s": round(t_plan, 3), "solve_ms": ms, "device_ms": float(np.median(dev)),
+                         "cells_per_s": cells / (ms * 1e-3), "plan_workspace_bytes": int(ws),
+                         "context_bytes": int(ctx.bytes())}
         if gpath is not None:
             g = np.load(gpath)
+            # stored component c of the samples: the problem's component
+            # g["components"][c] (all components of a 3-component problem),
+            # else the problem's c-th
+            pos = [int(x) for x in g["components"]] if "components" in g.files else list(range(prob.n_components))
             for prec in ("fp64", "fp32_refine"):
                 errs = []
                 base = 0
                 for k, lv in enumerate(prob.levels):
                     n = len(lv.blocks) * prob.nb ** 3
                     idx = g["sample%d" % k]
-                    for c in range(prob.n_components):
+                    for c in range(len(pos)):
                         ref = g["phi%d_c%d" % (k, c)]
-                        got = res[prec][c][base:base + n][idx]
+                        got = res[prec][pos[c]][base:base + n][idx]
                         errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
                     base += n
                 row[prec]["err_vs_oracle_max_rel_l2"] = max(errs)
@@ -263,6 +282,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="HBM budget of the serving context")
     ap.add_argument("--configs", action="store_true",
                     help="also time every workload (FP64 and FP32+refine) into a 'configs' entry")
+    ap.add_argument("--workload", action="append", choices=WORKLOADS, default=None,
+                    help="time only these workloads of the config table, print them as one JSON line and "
+                         "exit (no headline measurement; for profiling one workload)")
     ap.add_argument("--print-hash", choices=sorted(KERNELS),
                     help="print the hash of that kernel's sources (as counter summaries record it) and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -291,6 +313,11 @@ def main():
     ctx.set_mac_method(args.mac)
     if args.autotune:
         ctx.set_autotune(args.autotune)
+    if args.workload:
+        print(json.dumps({"configs": config_table(ctx, only=args.workload),
+                          "build": {"id": lgf.build_id()}}), flush=True)
+        ctx.close()
+        return
     prob = inputs.mstar()
     nb = prob.nb
     n_blocks = len(prob.levels[0].blocks)

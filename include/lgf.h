@@ -354,8 +354,8 @@ lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launch
  * MAC method and tuning.  The spectral multiply-accumulate of a level
  * convolution (at each block frequency, a convolution over the block
  * lattice) runs either as block pairs, compiled for a few tile shapes
- * (rectangles of target rows per workgroup), or, for boxes of at most 16
- * blocks along x and y and 32 along z, as a zero-padded FFT over the block lattice with
+ * (rectangles of target rows per workgroup), or, for boxes of at most 32
+ * blocks along x and y and 64 along z, as a zero-padded FFT over the block lattice with
  * real lattice spectra (exact up to rounding, O(L^3 log L) per frequency
  * instead of the O(E^6) pairs).  Which is fastest depends on the shape of
  * the block set.  A context keeps a table from convolution shape (block

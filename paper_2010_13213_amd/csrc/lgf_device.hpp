@@ -4,7 +4,7 @@
 // * fft_reg<N, INV>: an in-register radix-2 FFT of length N (2 to 64) on a
 //   per-thread array; all indices are compile-time so the array lives in
 //   VGPRs.  Forward uses exp(-2 pi i k / N), inverse exp(+2 pi i k / N), no
-//   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 64),
+//   scaling.  Twiddles are compile-time constants (cos, -sin)(2 pi k / 128),
 //   folded into the unrolled butterflies.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -61,49 +61,81 @@ template <typename R> __device__ __forceinline__ cplx<R> cmac(cplx<R> acc, cplx<
     return acc;
 }
 
-// exp(-2 pi i k / 64), k = 0..31, as (cos, -sin) pairs, each correctly
-// rounded to float64 (the even entries are the 32nds of a turn).
-constexpr double kTw64[32][2] = {
+// exp(-2 pi i k / 128), k = 0..63, as (cos, -sin) pairs, each correctly
+// rounded to float64 (every shorter length takes every (128 / N)-th entry).
+constexpr double kTw128[64][2] = {
     {1.0, 0.0},
+    {0.9987954562051724, -0.049067674327418015},
     {0.9951847266721969, -0.0980171403295606},
+    {0.989176509964781, -0.14673047445536175},
     {0.9807852804032304, -0.19509032201612828},
+    {0.970031253194544, -0.2429801799032639},
     {0.9569403357322088, -0.2902846772544624},
+    {0.9415440651830208, -0.33688985339222005},
     {0.9238795325112867, -0.3826834323650898},
+    {0.9039892931234433, -0.4275550934302821},
     {0.881921264348355, -0.47139673682599764},
+    {0.8577286100002721, -0.5141027441932218},
     {0.8314696123025452, -0.5555702330196022},
+    {0.8032075314806449, -0.5956993044924334},
     {0.773010453362737, -0.6343932841636455},
+    {0.7409511253549591, -0.6715589548470184},
     {0.7071067811865476, -0.7071067811865476},
+    {0.6715589548470184, -0.7409511253549591},
     {0.6343932841636455, -0.773010453362737},
+    {0.5956993044924334, -0.8032075314806449},
     {0.5555702330196022, -0.8314696123025452},
+    {0.5141027441932218, -0.8577286100002721},
     {0.47139673682599764, -0.881921264348355},
+    {0.4275550934302821, -0.9039892931234433},
     {0.3826834323650898, -0.9238795325112867},
+    {0.33688985339222005, -0.9415440651830208},
     {0.2902846772544624, -0.9569403357322088},
+    {0.2429801799032639, -0.970031253194544},
     {0.19509032201612828, -0.9807852804032304},
+    {0.14673047445536175, -0.989176509964781},
     {0.0980171403295606, -0.9951847266721969},
+    {0.049067674327418015, -0.9987954562051724},
     {0.0, -1.0},
+    {-0.049067674327418015, -0.9987954562051724},
     {-0.0980171403295606, -0.9951847266721969},
+    {-0.14673047445536175, -0.989176509964781},
     {-0.19509032201612828, -0.9807852804032304},
+    {-0.2429801799032639, -0.970031253194544},
     {-0.2902846772544624, -0.9569403357322088},
+    {-0.33688985339222005, -0.9415440651830208},
     {-0.3826834323650898, -0.9238795325112867},
+    {-0.4275550934302821, -0.9039892931234433},
     {-0.47139673682599764, -0.881921264348355},
+    {-0.5141027441932218, -0.8577286100002721},
     {-0.5555702330196022, -0.8314696123025452},
+    {-0.5956993044924334, -0.8032075314806449},
     {-0.6343932841636455, -0.773010453362737},
+    {-0.6715589548470184, -0.7409511253549591},
     {-0.7071067811865476, -0.7071067811865476},
+    {-0.7409511253549591, -0.6715589548470184},
     {-0.773010453362737, -0.6343932841636455},
+    {-0.8032075314806449, -0.5956993044924334},
     {-0.8314696123025452, -0.5555702330196022},
+    {-0.8577286100002721, -0.5141027441932218},
     {-0.881921264348355, -0.47139673682599764},
+    {-0.9039892931234433, -0.4275550934302821},
     {-0.9238795325112867, -0.3826834323650898},
+    {-0.9415440651830208, -0.33688985339222005},
     {-0.9569403357322088, -0.2902846772544624},
+    {-0.970031253194544, -0.2429801799032639},
     {-0.9807852804032304, -0.19509032201612828},
+    {-0.989176509964781, -0.14673047445536175},
     {-0.9951847266721969, -0.0980171403295606},
+    {-0.9987954562051724, -0.049067674327418015},
 };
 
 template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle(int k) {
-    // exp(-+2 pi i k / N) = table entry k * (64 / N), k < N / 2
-    static_assert(N >= 2 && N <= 64 && 64 % N == 0, "twiddle length");
-    const int j = k * (64 / N);
-    const R c = (R)kTw64[j][0];
-    const R s = (R)kTw64[j][1];
+    // exp(-+2 pi i k / N) = table entry k * (128 / N), k < N / 2
+    static_assert(N >= 2 && N <= 128 && 128 % N == 0, "twiddle length");
+    const int j = k * (128 / N);
+    const R c = (R)kTw128[j][0];
+    const R s = (R)kTw128[j][1];
     return INV ? cmake(c, -s) : cmake(c, s);
 }
 

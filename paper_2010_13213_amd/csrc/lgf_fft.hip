@@ -185,8 +185,8 @@ constexpr int kInvThreads = 256;
 // Re(v exp(+2 pi i j / N)), j a compile-time value after unrolling
 template <typename R, int N> __device__ __forceinline__ R re_rot(cplx<R> v, int j) {
     const int q = (j % N) * (64 / N);   // in 64ths of a turn
-    const R c = q < 32 ? (R)kTw64[q][0] : -(R)kTw64[q - 32][0];
-    const R s = q < 32 ? -(R)kTw64[q][1] : (R)kTw64[q - 32][1];   // sin(2 pi q / 64)
+    const R c = q < 32 ? (R)kTw128[2 * q][0] : -(R)kTw128[2 * (q - 32)][0];
+    const R s = q < 32 ? -(R)kTw128[2 * q][1] : (R)kTw128[2 * (q - 32)][1];   // sin(2 pi q / 64)
     return v.x * c - v.y * s;
 }
 

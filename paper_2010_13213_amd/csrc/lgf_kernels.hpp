@@ -148,6 +148,9 @@ struct LatGeom {
     int64_t n_slots;        // ex * ey * ez
     int64_t fstride, hstride;
     int hslab;
+    // source slots that hold a block (1) or not (0), or null when every slot
+    // does: the x pass reads empty slots as zero, so Fhat needs no clearing
+    const unsigned char *occ;
 };
 // Octant block-spectra table (offsets 0..XD-1 etc.) of FFT edge N = 2 nb.
 struct LatSpecGeom {
@@ -155,8 +158,8 @@ struct LatSpecGeom {
     int lx, ly, lz;
     int XD, YD, ZD;
 };
-bool lattice_len_ok(int L);    // compiled x and y lengths: 4, 8, 16, 32
-bool lattice_zlen_ok(int L);   // compiled z lengths: also 64
+bool lattice_len_ok(int L);    // compiled x and y lengths: 4, 8, 16, 32, 64
+bool lattice_zlen_ok(int L);   // compiled z lengths: also 128
 int lattice_len(int extent);   // smallest length L >= max(4, 2 extent - 1)
 int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (N/2 + 1)^3
 // Uhat[c] = the lattice convolution of Fhat[c] with the kernel whose

@@ -119,8 +119,8 @@ template <int TW> __device__ __forceinline__ XTile x_tile(const LatGeom &g, int 
 
 // x lines of Fhat -> H.  The tile's lines are staged through LDS: the loads
 // read each slot's kTW frequencies as one run, all issued before the first
-// is waited on.
-template <typename R, int LX>
+// is waited on.  MASKED: slots without a source block (g.occ) read as zero.
+template <typename R, int LX, bool MASKED>
 __global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R> *__restrict__ F,
                                                          cplx<R> *__restrict__ H) {
     constexpr int M = LX / 2, SP = M + 1, kTW = xtw<R>, kXThreads = xthreads<R>;   // rows padded against bank conflicts
@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R
         const int e = t + i * kXThreads;
         const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
         const int q = tl.q0 + ql, w = tl.w0 + wl;
-        const bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
+        bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
+        if (MASKED) ok = ok && g.occ[q * ex + x] != 0;
         const cplx<R> y = cload_nt(&Fc[ok ? (int64_t)(q * ex + x) * g.n_freq + w : 0]);
         v[i] = csel(ok, y, czero<R>());
     }
@@ -166,46 +167,29 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R
 // has at most one y line (LZ <= 2 LY), P lives at the start of Q: each
 // step reads its inputs into registers, and a barrier separates those
 // reads from the first write into the shared space.
+// Slabs per workgroup: one z line per lane of a half (SL = 128 / LY); at
+// LZ = 128 (WIDE) each half-line is split over the two waves of its half,
+// so one z line per lane of a wave (SL = 64 / LY).
 template <int LY, int LZ> struct YzLds {
-    static constexpr int SL = kLatThreads / (2 * LY);
+    static constexpr bool WIDE = LZ > 64;
+    static constexpr int SL = WIDE ? kLatThreads / (4 * LY) : kLatThreads / (2 * LY);
     static constexpr int MY = LY / 2, MZ = LZ / 2, PY = MY + 1, QZ = MZ + 1;
     static constexpr int P_ELEMS = SL * MZ * PY, Q_ELEMS = SL * LY * QZ;
     static constexpr bool ALIAS = SL * MZ <= kLatThreads / 2 && P_ELEMS <= Q_ELEMS;
     static constexpr int ELEMS = ALIAS ? Q_ELEMS : P_ELEMS + Q_ELEMS;
 };
 
-// Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
-// the zero-padded slabs in P.  Every index that depends on the half is a
-// constant here; both halves pass the same barriers in the same order.
+// Step 2 of lat_yz for the lanes of one half (HF: 0 even, 1 odd): the y
+// lines (s, z) of the zero-padded slabs in P, every z < MZ, MY inputs ->
+// this half's MY outputs, into Q.  Ends with a barrier.
 template <typename R, int LY, int LZ, int HF>
-__device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
-                                        const int (*sinfo)[2], int lane, int ez) {
+__device__ __forceinline__ void yz_ydft(cplx<R> *P, cplx<R> *Q, int lane) {
     using L = YzLds<LY, LZ>;
     constexpr int HL = kLatThreads / 2;
-    constexpr int SL = HL / LY;
+    constexpr int SL = L::SL;
     constexpr int MY = LY / 2, MZ = LZ / 2;
     constexpr int PY = MY + 1, QZ = MZ + 1;
     constexpr int YLINES = SL * MZ;
-    constexpr int YROUNDS = (YLINES + HL - 1) / HL;
-    const int zsl = lane / LY, ky = lane % LY;
-    // the spectra this lane's z line is multiplied by in step 3 (kz = 2m + HF),
-    // loaded first so that steps 2 and 3 hide the latency
-    R kv[MZ];
-    {
-        const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
-        const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
-        const int kyk = ry ? (LY - ky) % LY : ky;
-        // [kz][ky] plane of the slab; a reflected kz runs backwards from kz = LZ
-        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
-        const int ks = rz ? -LY : LY;
-        const R *kp = (rz ? kc + LZ * LY : kc) + HF * ks;   // kz = HF
-#pragma unroll
-        for (int m = 0; m < MZ; ++m) {
-            kv[m] = (HF == 0 && m == 0) ? kc[0] : *kp;
-            kp += 2 * ks;
-        }
-    }
-    // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
     if (L::ALIAS) {
         const int sl = lane / MZ, z = lane % MZ;
         const bool on = lane < YLINES;
@@ -242,40 +226,20 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
         }
     }
     __syncthreads();
-    // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
-    // inverse half DFT; then the halves combine through the line
-    cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
-    cplx<R> a[MZ];
-#pragma unroll
-    for (int n = 0; n < MZ; ++n) a[n] = qline[n];
-    if (HF) {
-#pragma unroll
-        for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
-    }
-    fft_reg<R, MZ, false>(a);
-#pragma unroll
-    for (int m = 0; m < MZ; ++m) a[m] = cmake<R>(a[m].x * kv[m], a[m].y * kv[m]);
-    fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
-    __syncthreads();   // every lane has read its line
-    // y[n] = E[n] + w^-n O[n]: the even half keeps n < MZ/2, the odd half the rest
-    if (HF) {
-#pragma unroll
-        for (int j = 0; j < (MZ + 1) / 2; ++j) qline[j] = a[j];                      // O[j] for the even half
-    } else {
-#pragma unroll
-        for (int j = MZ / 2; j < MZ; ++j) qline[j] = a[j];                           // E[j] for the odd half
-    }
-    __syncthreads();
-    if (HF) {
-#pragma unroll
-        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
-    } else {
-#pragma unroll
-        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
-    }
-    __syncthreads();
-    // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
-    // outputs, combined through the line's slab row in P
+}
+
+// Step 4 of lat_yz for one half: the inverse y lines (s, z), z < ez, this
+// half's MY inputs -> MY outputs, combined through the line's slab row in P.
+// Ends with a barrier.
+template <typename R, int LY, int LZ, int HF>
+__device__ __forceinline__ void yz_yinv(cplx<R> *P, const cplx<R> *Q, int lane, int ez) {
+    using L = YzLds<LY, LZ>;
+    constexpr int HL = kLatThreads / 2;
+    constexpr int SL = L::SL;
+    constexpr int MY = LY / 2, MZ = LZ / 2;
+    constexpr int PY = MY + 1, QZ = MZ + 1;
+    constexpr int YLINES = SL * MZ;
+    constexpr int YROUNDS = (YLINES + HL - 1) / HL;
     for (int r = 0; r < YROUNDS; ++r) {
         const int line = lane + r * HL;
         const int sl = line / MZ, z = line % MZ;
@@ -311,6 +275,181 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     }
 }
 
+// Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
+// the zero-padded slabs in P.  Every index that depends on the half is a
+// constant here; both halves pass the same barriers in the same order.
+template <typename R, int LY, int LZ, int HF>
+__device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
+                                        const int (*sinfo)[2], int lane, int ez) {
+    constexpr int MZ = LZ / 2;
+    constexpr int QZ = MZ + 1;
+    const int zsl = lane / LY, ky = lane % LY;
+    // the spectra this lane's z line is multiplied by in step 3 (kz = 2m + HF),
+    // loaded first so that steps 2 and 3 hide the latency
+    R kv[MZ];
+    {
+        const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
+        const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
+        const int kyk = ry ? (LY - ky) % LY : ky;
+        // [kz][ky] plane of the slab; a reflected kz runs backwards from kz = LZ
+        const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
+        const int ks = rz ? -LY : LY;
+        const R *kp = (rz ? kc + LZ * LY : kc) + HF * ks;   // kz = HF
+#pragma unroll
+        for (int m = 0; m < MZ; ++m) {
+            kv[m] = (HF == 0 && m == 0) ? kc[0] : *kp;
+            kp += 2 * ks;
+        }
+    }
+    // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
+    yz_ydft<R, LY, LZ, HF>(P, Q, lane);
+    // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
+    // inverse half DFT; then the halves combine through the line
+    cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
+    cplx<R> a[MZ];
+#pragma unroll
+    for (int n = 0; n < MZ; ++n) a[n] = qline[n];
+    if (HF) {
+#pragma unroll
+        for (int n = 1; n < MZ; ++n) a[n] = cmul(a[n], twiddle<R, LZ, false>(n));
+    }
+    fft_reg<R, MZ, false>(a);
+#pragma unroll
+    for (int m = 0; m < MZ; ++m) a[m] = cmake<R>(a[m].x * kv[m], a[m].y * kv[m]);
+    fft_reg<R, MZ, true>(a);   // even half: E[n]; odd half: O[n], n < MZ
+    __syncthreads();   // every lane has read its line
+    // y[n] = E[n] + w^-n O[n]: the even half keeps n < MZ/2, the odd half the rest
+    if (HF) {
+#pragma unroll
+        for (int j = 0; j < (MZ + 1) / 2; ++j) qline[j] = a[j];                      // O[j] for the even half
+    } else {
+#pragma unroll
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = a[j];                           // E[j] for the odd half
+    }
+    __syncthreads();
+    if (HF) {
+#pragma unroll
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
+    } else {
+#pragma unroll
+        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
+    }
+    __syncthreads();
+    // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
+    // outputs, combined through the line's slab row in P
+    yz_yinv<R, LY, LZ, HF>(P, Q, lane, ez);
+}
+
+// exp(-+2 pi i k / N) for any k in [0, N) known at compile time after
+// unrolling (the table holds k < N / 2; the rest are negated)
+template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle_full(int k) {
+    const cplx<R> w = twiddle<R, N, INV>(k % (N / 2));
+    return k < N / 2 ? w : cmake<R>(-w.x, -w.y);
+}
+
+// Step 3 of lat_yz at LZ = 128 for one wave: its quarter Q4 = HF + 2 ZP of
+// every z line of its slabs.  With x[n] the line (n < 64, zero beyond the
+// data) and w = exp(-2 pi i / 128), the frequencies kz = 4 j + Q4 are
+//     X[4 j + Q4] = DFT_32(v)[j],  v[n] = w^(Q4 n) (x[n] + (-i)^Q4 x[n + 32]),
+// and after the product with the spectra and the inverse DFT_32 of each
+// quarter (Y_Q4), the outputs n < 64 are
+//     y[n + 32 h] = sum_Q4 i^(Q4 h) T_Q4[n],  T_Q4[n] = w^(-Q4 n) Y_Q4[n],
+// summed through the line in LDS (quarters 2 and 3 hand theirs to 0 and 1,
+// which leave one partial sum each in the line for the other).  All four
+// variants pass the same five barriers.
+// kb: the spectra row of this lane at its first kz (kz = Q4), ks: the step
+// to the next kz (negative for a reflected kz), k0: the row at kz = 0.
+template <typename R, int LY, int HF, int ZP>
+__device__ __forceinline__ void yz128_zstep(cplx<R> *qline, const R *kb, const R *k0, int ks) {
+    constexpr int Q4 = HF + 2 * ZP;
+    cplx<R> v[32];
+#pragma unroll
+    for (int n = 0; n < 32; ++n) {
+        const cplx<R> x0 = qline[n], x1 = qline[n + 32];
+        // (-i)^Q4 x1: 1, -i, -1, i
+        const cplx<R> r1 = Q4 == 0 ? x1 : Q4 == 1 ? cmake<R>(x1.y, -x1.x) : Q4 == 2 ? cmake<R>(-x1.x, -x1.y)
+                                                                                    : cmake<R>(-x1.y, x1.x);
+        v[n] = cadd(x0, r1);
+        if (Q4 != 0 && n != 0) v[n] = cmul(v[n], twiddle_full<R, 128, false>(Q4 * n));
+    }
+    // the spectra at kz = 4 j + Q4, loaded here so that the forward DFT
+    // hides their latency (earlier they would be live through the y DFT)
+    R kv[32];
+    kv[0] = Q4 == 0 ? *k0 : *kb;
+    const R *kp = kb;
+#pragma unroll
+    for (int j = 1; j < 32; ++j) {
+        kp += 4 * ks;
+        kv[j] = *kp;
+    }
+    fft_reg<R, 32, false>(v);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) v[j] = cmake<R>(v[j].x * kv[j], v[j].y * kv[j]);
+    fft_reg<R, 32, true>(v);
+    if (Q4 != 0) {
+#pragma unroll
+        for (int n = 1; n < 32; ++n) v[n] = cmul(v[n], twiddle_full<R, 128, true>(Q4 * n));
+    }
+    __syncthreads();   // (1) every lane has read its line
+    if (ZP) {
+        // quarters 2 and 3 hand over T_2 (at n) and T_3 (at n + 32)
+#pragma unroll
+        for (int n = 0; n < 32; ++n) qline[n + 32 * HF] = v[n];
+        __syncthreads();   // (2)
+        __syncthreads();   // (3)
+        __syncthreads();   // (4)
+        __syncthreads();   // (5)
+    } else {
+        __syncthreads();   // (2)
+        // quarter 0: A = T0 + T2 kept, B = T0 - T2 left at n;
+        // quarter 1: D = i (T1 - T3) kept, C = T1 + T3 left at n + 32
+#pragma unroll
+        for (int n = 0; n < 32; ++n) {
+            const cplx<R> o = qline[n + 32 * HF];
+            if (HF) {
+                qline[n + 32] = cadd(v[n], o);
+                const cplx<R> d = csub(v[n], o);
+                v[n] = cmake<R>(-d.y, d.x);
+            } else {
+                qline[n] = csub(v[n], o);
+                v[n] = cadd(v[n], o);
+            }
+        }
+        __syncthreads();   // (3)
+        // quarter 0: y[n] = A + C; quarter 1: y[n + 32] = D + B
+#pragma unroll
+        for (int n = 0; n < 32; ++n) v[n] = cadd(v[n], qline[n + 32 * (1 - HF)]);
+        __syncthreads();   // (4) C and B are read
+#pragma unroll
+        for (int n = 0; n < 32; ++n) qline[n + 32 * HF] = v[n];
+        __syncthreads();   // (5)
+    }
+}
+
+// Steps 2-4 of lat_yz at LZ = 128 for the lanes of one half (HF); the two
+// waves of the half (zp) take the two quarters of its z frequencies.
+template <typename R, int LY, int HF>
+__device__ __forceinline__ void yz128_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
+                                           const int (*sinfo)[2], int lane, int ez) {
+    constexpr int LZ = 128, QZ = LZ / 2 + 1;
+    const int zp = __builtin_amdgcn_readfirstlane(lane >> 6);   // uniform per wave
+    const int l64 = lane & 63;
+    const int zsl = l64 / LY, ky = l64 % LY;
+    // spectra rows of this lane's z line, kz = 4 j + 2 zp + HF
+    const int wr = sinfo[zsl][0], kf = sinfo[zsl][1];
+    const int kx = kf & 255, ry = (kf >> 8) & 1, rz = kf >> 9;
+    const int kyk = ry ? (LY - ky) % LY : ky;
+    const R *kc = Khat + ((int64_t)wr * g.lx + kx) * LZ * LY + kyk;
+    const int ks = rz ? -LY : LY;
+    // a reflected kz runs backwards from kz = LZ; kz = 0 is its own reflection
+    const R *kb = (rz ? kc + LZ * LY : kc) + (2 * zp + HF) * ks;
+    yz_ydft<R, LY, LZ, HF>(P, Q, lane);
+    cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
+    if (zp) yz128_zstep<R, LY, HF, 1>(qline, kb, kc, ks);
+    else yz128_zstep<R, LY, HF, 0>(qline, kb, kc, ks);
+    yz_yinv<R, LY, LZ, HF>(P, Q, lane, ez);
+}
+
 // One (c, omega, kx) slab of H per 2 Ly lanes: y DFT, z DFT, product with
 // the spectra, inverse z and y DFTs, in place.  The two halves of every
 // line are taken by lanes of different waves (waves 0-1 the even half,
@@ -323,13 +462,15 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
 // consecutive ones run on one XCD: the reflections share one stored Khat
 // plane, which is then read from HBM once and from that XCD's L2 for the
 // others.
-// Occupancy: 4 workgroups per CU up to LZ = 32; at LZ = 64 the z lines
-// of a lane take twice the registers and Q twice the LDS, so 2.
+// Occupancy: 4 workgroups per CU up to LY, LZ = 32; at LZ = 64 the z lines
+// of a lane take twice the registers and Q twice the LDS (at LY = 64 the y
+// lines), so 2; at LZ = 128 a lane holds a quarter line (as many registers
+// as at 64).
 template <typename R, int LY, int LZ>
-__global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(LZ <= 32 ? 4 : 2))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
+__global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_eu(LZ <= 32 && LY <= 32 ? 4 : 2))) lat_yz(LatGeom g, cplx<R> *__restrict__ H, const R *__restrict__ Khat,
                                                       const int *__restrict__ worder) {
     constexpr int HL = kLatThreads / 2;                 // lanes per half
-    constexpr int SL = HL / LY;                         // slabs per workgroup: one z line per lane pair
+    constexpr int SL = YzLds<LY, LZ>::SL;               // slabs per workgroup
     constexpr int MY = LY / 2, MZ = LZ / 2;
     // lines padded by one element: unpadded, the lines a wave reads at once
     // start 256 B apart and fall into one LDS bank
@@ -387,8 +528,13 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
     }
     __syncthreads();
     // 2-4, each wave in its half's copy (the same barriers in both)
-    if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
-    else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
+    if constexpr (L::WIDE) {
+        if (half) yz128_half<R, LY, 1>(g, Khat, P, Q, sinfo, lane, ez);
+        else yz128_half<R, LY, 0>(g, Khat, P, Q, sinfo, lane, ez);
+    } else {
+        if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
+        else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
+    }
     // 5. store the slabs back (streaming stores: lat_x_inv reads them from HBM)
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -525,6 +671,112 @@ __global__ void __launch_bounds__(kLatThreads) latspec_z(LatSpecGeom s, const cp
     for (int kz = 0; kz < LZ; ++kz) out[kz * s.ly] = a[kz].x * scale;
 }
 
+// Lattice spectra for lengths beyond the register kernels (x or y of 64, z
+// of 128): the same gather and DFTs, each DFT summed directly from a line
+// in LDS (once per context; O(L) per output).  w[q] = exp(-2 pi i q / 128)
+// for q < 128, in LDS.
+template <typename R> __device__ __forceinline__ void tw128_fill(cplx<R> *w, int t) {
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q)
+            if (t == q) {
+                w[q] = cmake<R>((R)kTw128[q][0], (R)kTw128[q][1]);
+                w[q + 64] = cmake<R>(-(R)kTw128[q][0], -(R)kTw128[q][1]);
+            }
+    }
+}
+
+constexpr int kWideXY = 64 * 64;   // largest x-y plane of the wide build
+
+// One (stored omega, pz) plane per workgroup: gather K_d into LDS, DFT along
+// x, then along y, into S[wl][pz][ky][kx].
+template <typename R>
+__global__ void __launch_bounds__(kLatThreads) latspec_wide_xy(LatSpecGeom s, const cplx<R> *__restrict__ T,
+                                                               cplx<R> *__restrict__ S, int w0, int nw) {
+    __shared__ cplx<R> X[kWideXY];
+    __shared__ cplx<R> w[128];
+    constexpr int PER = kWideXY / kLatThreads;
+    const int t = threadIdx.x;
+    const int lx = s.lx, ly = s.ly, n = lx * ly;
+    const int wl = blockIdx.x / s.lz, pz = blockIdx.x % s.lz;
+    if (wl >= nw) return;
+    tw128_fill(w, t);
+    const int om = stored_omega(w0 + wl, s.N);
+    bool uz;
+    const int dz = lat_offset(pz, s.lz, uz);
+    for (int e = t; e < n; e += kLatThreads) {
+        const int py = e / lx, px = e % lx;
+        bool ux, uy;
+        const int dx = lat_offset(px, lx, ux), dy = lat_offset(py, ly, uy);
+        X[e] = (ux && uy && uz) ? octant_value<R>(s, T, om, dx, dy, dz) : czero<R>();
+    }
+    __syncthreads();
+    const int sx = 128 / lx, sy = 128 / ly;
+    cplx<R> acc[PER];
+    // x: X[py][kx] = sum_px X[py][px] w^(kx px)
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = t + i * kLatThreads;
+        acc[i] = czero<R>();
+        if (e < n) {
+            const int py = e / lx, kx = e % lx;
+            for (int px = 0; px < lx; ++px) acc[i] = cmac(acc[i], X[py * lx + px], w[(kx * px % lx) * sx]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        if (t + i * kLatThreads < n) X[t + i * kLatThreads] = acc[i];
+    __syncthreads();
+    // y: X[ky][kx] = sum_py X[py][kx] w^(ky py)
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = t + i * kLatThreads;
+        acc[i] = czero<R>();
+        if (e < n) {
+            const int ky = e / lx, kx = e % lx;
+            for (int py = 0; py < ly; ++py) acc[i] = cmac(acc[i], X[py * lx + kx], w[(ky * py % ly) * sy]);
+        }
+    }
+    cplx<R> *out = S + ((int64_t)wl * s.lz + pz) * n;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        if (t + i * kLatThreads < n) out[t + i * kLatThreads] = acc[i];
+}
+
+// z DFT of 16 consecutive columns (ky, kx) of S per workgroup; the real
+// part, scaled, into Khat[wr][kx][kz][ky].
+constexpr int kWideCols = 16;
+template <typename R>
+__global__ void __launch_bounds__(kLatThreads) latspec_wide_z(LatSpecGeom s, const cplx<R> *__restrict__ S,
+                                                              R *__restrict__ Khat, int w0, int nw, R scale) {
+    __shared__ cplx<R> C[128 * kWideCols];
+    __shared__ cplx<R> w[128];
+    const int t = threadIdx.x;
+    const int lz = s.lz;
+    const int64_t plane = (int64_t)s.lx * s.ly;
+    const int64_t col0 = (int64_t)blockIdx.x * kWideCols;
+    const int64_t n_cols = (int64_t)nw * plane;
+    tw128_fill(w, t);
+    for (int e = t; e < lz * kWideCols; e += kLatThreads) {
+        const int pz = e / kWideCols, c = e % kWideCols;
+        const int64_t col = col0 + c;
+        C[e] = col < n_cols ? S[((col / plane) * lz + pz) * plane + col % plane] : czero<R>();
+    }
+    __syncthreads();
+    const int sz = 128 / lz;
+    for (int e = t; e < lz * kWideCols; e += kLatThreads) {
+        const int kz = e / kWideCols, c = e % kWideCols;
+        const int64_t col = col0 + c;
+        if (col >= n_cols) continue;
+        cplx<R> acc = czero<R>();
+        for (int pz = 0; pz < lz; ++pz) acc = cmac(acc, C[pz * kWideCols + c], w[(kz * pz % lz) * sz]);
+        const int64_t wl = col / plane, q = col % plane;
+        const int ky = (int)(q / s.lx), kx = (int)(q % s.lx);
+        Khat[(((int64_t)(w0 + wl) * s.lx + kx) * lz + kz) * s.ly + ky] = acc.x * scale;
+    }
+}
+
 // ---- dispatch over the compiled lattice lengths ----
 
 template <typename F> hipError_t with_len(int L, F &&f) {
@@ -537,11 +789,23 @@ template <typename F> hipError_t with_len(int L, F &&f) {
     }
 }
 
-// z lengths: also 64 (boxes up to 32 blocks along z; the z lines are the
-// only ones held whole per lane pair, the x and y lengths stay <= 32)
+// z lengths of the register spectra build: also 64
 template <typename F> hipError_t with_zlen(int L, F &&f) {
     if (L == 64) return f(std::integral_constant<int, 64>());
     return with_len(L, static_cast<F &&>(f));
+}
+
+// x and y lengths of the MAC kernels: also 64 (boxes up to 32 blocks)
+template <typename F> hipError_t with_xlen(int L, F &&f) {
+    if (L == 64) return f(std::integral_constant<int, 64>());
+    return with_len(L, static_cast<F &&>(f));
+}
+
+// z lengths of lat_yz: also 64 and 128 (boxes up to 64 blocks; at 128 a
+// z half-line is split over two waves)
+template <typename F> hipError_t with_yz_zlen(int L, F &&f) {
+    if (L == 128) return f(std::integral_constant<int, 128>());
+    return with_zlen(L, static_cast<F &&>(f));
 }
 
 // workgroups of the x kernels: one per (component, frequency tile, row tile)
@@ -552,10 +816,14 @@ template <typename R> unsigned x_tiles(const LatGeom &g) {
 
 template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void *H, hipStream_t s) {
     const unsigned blocks = x_tiles<R>(g);
-    return with_len(g.lx, [&](auto lx) {
+    return with_xlen(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
-        hipLaunchKernelGGL((lat_x_fwd<R, LX>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)F,
-                           (cplx<R> *)H);
+        if (g.occ)
+            hipLaunchKernelGGL((lat_x_fwd<R, LX, true>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)F,
+                               (cplx<R> *)H);
+        else
+            hipLaunchKernelGGL((lat_x_fwd<R, LX, false>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)F,
+                               (cplx<R> *)H);
         return hipGetLastError();
     });
 }
@@ -564,10 +832,10 @@ template <typename R>
 hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worder, hipStream_t s) {
     const int64_t slabs = (int64_t)g.nc * g.n_freq * g.lx;
     if (slabs >= INT32_MAX) return hipErrorInvalidValue;   // the kernel counts slabs in 32 bits
-    return with_len(g.ly, [&](auto ly) {
-        return with_zlen(g.lz, [&](auto lz) {
+    return with_xlen(g.ly, [&](auto ly) {
+        return with_yz_zlen(g.lz, [&](auto lz) {
             constexpr int LY = decltype(ly)::value, LZ = decltype(lz)::value;
-            constexpr int SL = kLatThreads / (2 * LY);
+            constexpr int SL = YzLds<LY, LZ>::SL;
             hipLaunchKernelGGL((lat_yz<R, LY, LZ>), dim3((unsigned)((slabs + SL - 1) / SL)), dim3(kLatThreads), 0,
                                s, g, (cplx<R> *)H, (const R *)Khat, worder);
             return hipGetLastError();
@@ -577,7 +845,7 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
 
 template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
     const unsigned blocks = x_tiles<R>(g);
-    return with_len(g.lx, [&](auto lx) {
+    return with_xlen(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
         hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)H,
                            (cplx<R> *)U);
@@ -591,8 +859,21 @@ template <typename R> hipError_t spec_impl(const LatSpecGeom &sg, const void *T,
     const int64_t chunk = std::max<int64_t>(1, (int64_t)(scratch_bytes / (sizeof(cplx<R>) * per_w)));
     const R scale = (R)(1.0 / (double)per_w);
     const int n_stored = lattice_stored_freqs(sg.N);
+    const bool wide = sg.lx > 32 || sg.ly > 32 || sg.lz > 64;
     for (int64_t w0 = 0; w0 < n_stored; w0 += chunk) {
         const int nw = (int)std::min<int64_t>(chunk, n_stored - w0);
+        if (wide) {
+            hipLaunchKernelGGL((latspec_wide_xy<R>), dim3((unsigned)(nw * sg.lz)), dim3(kLatThreads), 0, s, sg,
+                               (const cplx<R> *)T, (cplx<R> *)scratch, (int)w0, nw);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const int64_t cols = (int64_t)nw * sg.lx * sg.ly;
+            hipLaunchKernelGGL((latspec_wide_z<R>), dim3((unsigned)((cols + kWideCols - 1) / kWideCols)),
+                               dim3(kLatThreads), 0, s, sg, (const cplx<R> *)scratch, (R *)Khat, (int)w0, nw, scale);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            continue;
+        }
         hipError_t e = with_len(sg.lx, [&](auto lx) {
             return with_len(sg.ly, [&](auto ly) {
                 constexpr int LX = decltype(lx)::value, LY = decltype(ly)::value;
@@ -616,9 +897,9 @@ template <typename R> hipError_t spec_impl(const LatSpecGeom &sg, const void *T,
 
 }  // namespace
 
-bool lattice_len_ok(int L) { return L == 4 || L == 8 || L == 16 || L == 32; }
+bool lattice_len_ok(int L) { return L == 4 || L == 8 || L == 16 || L == 32 || L == 64; }
 
-bool lattice_zlen_ok(int L) { return lattice_len_ok(L) || L == 64; }
+bool lattice_zlen_ok(int L) { return lattice_len_ok(L) || L == 128; }
 
 int lattice_len(int extent) {
     int L = 4;

@@ -365,6 +365,12 @@ static void build_conv_lattice(lgf_plan *plan, Conv &c, const std::vector<Blk> &
         t_off.push_back(b.off);
     }
     upload_slots(ctx, c, s_slot, t_slot, s_off, t_off);
+    if ((int64_t)src.size() != c.n_slots) {
+        std::vector<unsigned char> occ((size_t)c.n_slots, 0);
+        for (int sl : s_slot) occ[(size_t)sl] = 1;
+        c.d_src_occ.alloc(ctx, occ.size(), "source slots");
+        hip_check(hipMemcpy(c.d_src_occ.ptr, occ.data(), occ.size(), hipMemcpyHostToDevice), "upload source slots");
+    }
 }
 
 LatGeom lat_geom(const Conv &c, int nc) {
@@ -386,6 +392,7 @@ LatGeom lat_geom(const Conv &c, int nc) {
     const int per_w = c.ey * c.ez;
     g.hslab = per_w % 32 == 0 ? per_w + 8 : per_w;
     g.hstride = (int64_t)c.spec->n_freq * c.lx * g.hslab;
+    g.occ = (const unsigned char *)c.d_src_occ.ptr;
     return g;
 }
 
@@ -659,7 +666,7 @@ static double model_lattice_ms(int nb, bool fp32, int nc, const std::vector<Blk>
 
 // Build a convolution with the MAC method of the context's tuning table for
 // its shape: block pairs with one of the compiled tile shapes, or (boxes up
-// to 16 blocks along x and y, 32 along z) the lattice FFT.  With autotuning on and no entry
+// to 32 blocks along x and y, 64 along z) the lattice FFT.  With autotuning on and no entry
 // yet, every candidate is built and timed on this convolution's own
 // geometry; the fastest is recorded if it beats the default (pairs with the
 // first tile shape) by more than the 3% that repeated timings of one
@@ -1007,15 +1014,17 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     const SpecWs &ws = plan->ws_scratch ? *plan->ws_scratch : own;
     if (nc < 1 || nc > kMacComponents || (size_t)nc * fs * elem > ws.fhat_bytes || (size_t)nc * fs * elem > ws.uhat_bytes)
         throw Failure(LGF_E_INVALID, "internal: component count outside the spectral workspace");
-    // empty slots of Fhat must read as zero; the forward FFT writes only
-    // occupied slots, so clear when another slot map used the buffer last
-    // (a convolution with a source in every slot overwrites all it reads).
-    // Shared scratch may hold anything: clear it whenever a slot is empty.
+    // empty slots of Fhat must read as zero for the block-pair MAC; the
+    // forward FFT writes only occupied slots, so clear when another slot map
+    // used the buffer last (a convolution with a source in every slot
+    // overwrites all it reads).  Shared scratch may hold anything: clear it
+    // whenever a slot is empty.  The lattice x pass skips empty slots itself.
+    const bool needs_zeros = !fhat_full(c) && c.method != kMethodLattice;
     if (plan->ws_scratch) {
-        if (!fhat_full(c)) hip_check(zero_fill(ws.fhat, (size_t)nc * fs * elem, s), "clear Fhat");
+        if (needs_zeros) hip_check(zero_fill(ws.fhat, (size_t)nc * fs * elem, s), "clear Fhat");
     } else if (plan->fhat_conv != &c) {
-        if (!fhat_full(c)) hip_check(zero_fill(ws.fhat, ws.fhat_bytes, s), "clear Fhat");
-        plan->fhat_conv = &c;
+        if (needs_zeros) hip_check(zero_fill(ws.fhat, ws.fhat_bytes, s), "clear Fhat");
+        plan->fhat_conv = needs_zeros ? &c : nullptr;
     }
     for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 0, s);

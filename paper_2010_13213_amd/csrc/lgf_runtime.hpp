@@ -159,7 +159,7 @@ struct SubConv {
 
 // One blockwise LGF convolution on a level (sources -> targets).  The
 // spectral MAC runs either as block pairs (parts, below) or, for boxes of at
-// most 16 blocks along x and y and 32 along z, as an FFT over the block
+// most 32 blocks along x and y and 64 along z, as an FFT over the block
 // lattice (method 1).
 constexpr int kMethodPairs = 0, kMethodLattice = 1;
 struct Conv {
@@ -177,6 +177,7 @@ struct Conv {
     int n_src = 0, n_tgt = 0;
     SpecTable *spec = nullptr;
     DeviceBuffer d_src_slot, d_tgt_slot, d_src_off, d_tgt_off;
+    DeviceBuffer d_src_occ;   // lattice: 1 per source slot of the box (absent when every slot has a source)
     std::vector<std::unique_ptr<SubConv>> parts;   // in phase order
 };
 

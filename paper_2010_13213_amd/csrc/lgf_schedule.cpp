@@ -622,8 +622,9 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     if (calls.empty()) return;
     for (const ConvCall &k : calls)
         if (k.p->fhat_conv != k.c) {
-            if (!fhat_full(*k.c)) hip_check(zero_fill(k.p->Fhat.ptr, k.p->Fhat.bytes, s), "clear Fhat");
-            k.p->fhat_conv = k.c;
+            const bool needs_zeros = !fhat_full(*k.c) && k.c->method != kMethodLattice;
+            if (needs_zeros) hip_check(zero_fill(k.p->Fhat.ptr, k.p->Fhat.bytes, s), "clear Fhat");
+            k.p->fhat_conv = needs_zeros ? k.c : nullptr;
         }
     const int nb = calls[0].p->nb;
     for (const ConvCall &k : calls)

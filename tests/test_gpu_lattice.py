@@ -7,9 +7,11 @@ lattice spectra.  These tests force that method (LGF_MAC_LATTICE) and check
 it against the oracle's direct sum (FP64 1e-12, mixed 1e-10) on boxes of
 every compiled length, ragged and sparse supports, one-block-thick boxes,
 vector and composite solves; against the block-pair method on the dense
-256^3 box; and the bit-for-bit identities of the product path (vector =
+256^3 box and on boxes that need the wide lengths (64 along x or y, 128
+along z); and the bit-for-bit identities of the product path (vector =
 scalar components, batch = alone, graph replay = eager) under it.  A box
-longer than 16 blocks along an axis falls back to block pairs.
+longer than 32 blocks along x or y, or 64 along z, falls back to block
+pairs.
 """
 import numpy as np
 import pytest
@@ -98,12 +100,58 @@ def test_lattice_long_z_boxes_sampled(lat_ctx, ext, nb, precision, tol):
     assert rel_l2(u[idx], direct.direct_sum(c, f, c[idx], 0.6)) < tol
 
 
-def test_lattice_z_extent_33_takes_block_pairs(lat_ctx):
-    """Past 32 blocks along z there is no compiled lattice length: the
-    lattice-only setting falls back to block pairs, still exact."""
+def _lattice_stages(ctx, prob, precision="fp64"):
+    ctx.set_timing(True)
+    ctx.stage_times()
+    try:
+        u = gpu_solve(ctx, prob, precision)
+        st = ctx.stage_times()
+    finally:
+        ctx.set_timing(False)
+    return u, st
+
+
+@pytest.mark.parametrize("ext,nb,precision,tol", [((17, 3, 2), 8, "fp64", TOL64), ((2, 20, 3), 8, "fp64", TOL64),
+                                                   ((2, 2, 40), 8, "fp64", TOL64), ((3, 18, 35), 8, "fp64", TOL64),
+                                                   ((3, 17, 3), 16, "fp64", TOL64),
+                                                   ((2, 3, 33), 16, "fp32_refine", TOLMIX),
+                                                   ((18, 17, 33), 8, "fp32_refine", TOLMIX)])
+def test_lattice_wide_boxes_sampled(lat_ctx, ext, nb, precision, tol):
+    """x or y extents 17..32 take the DFT length 64 and z extents 33..64 the
+    length 128 (the z line split over four waves); ragged extents, both
+    block sizes, both precisions."""
+    rng = np.random.default_rng(sum(ext) * 13 + nb)
+    blocks = _box(*ext, lo=(-5, 3, -9))
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    u, st = _lattice_stages(lat_ctx, _problem(blocks, nb, f, 0.4), precision)
+    assert st["lat_yz"][1] > 0 and st["smac"][1] == 0, st
+    n = 400 if len(c) > 1_000_000 else 1200
+    idx = np.concatenate([rng.choice(len(c), n, replace=False), [0, len(c) - 1]])
+    assert rel_l2(u[0][idx], direct.direct_sum(c, f, c[idx], 0.4)) < tol
+
+
+@pytest.mark.parametrize("ext", [(17, 5, 34), (4, 26, 3)])
+def test_wide_lattice_matches_pairs_full_field(lat_ctx, pairs_ctx, ext):
+    """On every cell: the wide lattice lengths against the block pairs."""
+    rng = np.random.default_rng(sum(ext))
+    nb = 8
+    blocks = _box(*ext, lo=(1, -2, 0))
+    blocks = blocks[rng.uniform(size=len(blocks)) < 0.6]
+    c = inputs.cell_coords(blocks, nb)
+    f = rng.standard_normal(len(c))
+    a = gpu_solve(lat_ctx, _problem(blocks, nb, f, 0.5))[0]
+    b = gpu_solve(pairs_ctx, _problem(blocks, nb, f, 0.5))[0]
+    assert rel_l2(a, b) < 1e-13
+
+
+def test_lattice_y_extent_33_takes_block_pairs(lat_ctx):
+    """Past 32 blocks along y there is no compiled lattice length (levels
+    reach 64 blocks per axis): the lattice-only setting falls back to block
+    pairs, still exact."""
     rng = np.random.default_rng(77)
     nb = 8
-    blocks = _box(2, 2, 33, lo=(0, 0, -16))
+    blocks = _box(2, 33, 2, lo=(0, -16, 0))
     c = inputs.cell_coords(blocks, nb)
     f = rng.standard_normal(len(c))
     lat_ctx.set_timing(True)
@@ -235,9 +283,9 @@ def test_lattice_graph_replays_equal_eager(lat_ctx):
     plan.close()
 
 
-def test_box_longer_than_16_blocks_along_x_uses_pairs(lat_ctx):
+def test_box_longer_than_32_blocks_along_x_uses_pairs(lat_ctx):
     nb = 8
-    blocks = _box(17, 2, 1)
+    blocks = _box(33, 2, 1)
     rng = np.random.default_rng(12)
     c = inputs.cell_coords(blocks, nb)
     f = rng.standard_normal(len(c))
