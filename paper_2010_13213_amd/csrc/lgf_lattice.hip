@@ -340,6 +340,18 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     yz_yinv<R, LY, LZ, HF>(P, Q, lane, ez);
 }
 
+// w[q] = exp(-2 pi i q / 128), q < 128, into LDS (threads t < 64 write)
+template <typename R> __device__ __forceinline__ void tw128_fill(cplx<R> *w, int t) {
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q)
+            if (t == q) {
+                w[q] = cmake<R>((R)kTw128[q][0], (R)kTw128[q][1]);
+                w[q + 64] = cmake<R>(-(R)kTw128[q][0], -(R)kTw128[q][1]);
+            }
+    }
+}
+
 // exp(-+2 pi i k / N) for any k in [0, N) known at compile time after
 // unrolling (the table holds k < N / 2; the rest are negated)
 template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle_full(int k) {
@@ -494,7 +506,10 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         const int si = s0 + t;
         const bool live = si < n_slabs;
         const int wk = live ? si % per_c : 0;
-        const int p = worder[wk / g.lx], kx = wk % g.lx;
+        // slabs (frequency, kx), kx fastest; at LZ = 128 (one slab per
+        // workgroup, 64 KB spectra planes) frequency fastest, so that the
+        // reflections sharing a spectra plane run next to each other
+        const int p = worder[L::WIDE ? wk % g.n_freq : wk / g.lx], kx = L::WIDE ? wk / g.n_freq : wk % g.lx;
         // spectrum position p -> block frequency (fx, fyv, fzv) -> stored
         // frequency (ky, kz in [0, N/2]) and reflections
         const int N = g.N, Hh = N / 2 + 1;
@@ -673,18 +688,8 @@ __global__ void __launch_bounds__(kLatThreads) latspec_z(LatSpecGeom s, const cp
 
 // Lattice spectra for lengths beyond the register kernels (x or y of 64, z
 // of 128): the same gather and DFTs, each DFT summed directly from a line
-// in LDS (once per context; O(L) per output).  w[q] = exp(-2 pi i q / 128)
-// for q < 128, in LDS.
-template <typename R> __device__ __forceinline__ void tw128_fill(cplx<R> *w, int t) {
-    if (t < 64) {
-#pragma unroll
-        for (int q = 0; q < 64; ++q)
-            if (t == q) {
-                w[q] = cmake<R>((R)kTw128[q][0], (R)kTw128[q][1]);
-                w[q + 64] = cmake<R>(-(R)kTw128[q][0], -(R)kTw128[q][1]);
-            }
-    }
-}
+// in LDS (once per context; O(L) per output), with the twiddles of
+// tw128_fill.
 
 constexpr int kWideXY = 64 * 64;   // largest x-y plane of the wide build
 
