@@ -156,6 +156,45 @@ def config_table(ctx, reps=3, only=None):
     return table
 
 
+def flgf_table(ctx, reps=3):
+    """The fast-LGF approximation (lgf_plan_create_flgf) on the vector ring
+    (208 blocks of 16^3) and the dense 256^3 box, near radii 1 and 2: device
+    time per solve and the relative L2 error against the exact FP64 solve of
+    the same context."""
+    import numpy as np
+    import torch
+    from paper_2010_13213_amd import inputs, lgf
+
+    def run(prob, near):
+        plan = lgf.Plan.for_problem(ctx, prob, "fp64", flgf_near=near)
+        f = torch.from_numpy(prob.flat_source()).cuda()
+        u = torch.empty_like(f)
+        plan.solve(f, u)
+        torch.cuda.synchronize()
+        dev = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.solve(f, u)
+            e1.record()
+            torch.cuda.synchronize()
+            dev.append(e0.elapsed_time(e1))
+        plan.close()
+        return u.cpu().numpy().reshape(prob.n_components, -1), float(np.median(dev))
+
+    out = {}
+    for name, prob in (("ring_128^3_vector", inputs.single_ring(components=(0, 1))), ("dense_256^3", inputs.mstar())):
+        exact, t_exact = run(prob, None)
+        row = {"exact_device_ms": t_exact}
+        for near in (1, 2):
+            u, t = run(prob, near)
+            err = max(float(np.linalg.norm(u[c] - exact[c]) / np.linalg.norm(exact[c])) for c in range(prob.n_components))
+            row["near_%d" % near] = {"device_ms": t, "rel_l2_vs_exact": err}
+        print("fast-LGF %s: %s" % (name, json.dumps(row)), file=sys.stderr, flush=True)
+        out[name] = row
+    return out
+
+
 def _pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -282,6 +321,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="HBM budget of the serving context")
     ap.add_argument("--configs", action="store_true",
                     help="also time every workload (FP64 and FP32+refine) into a 'configs' entry")
+    ap.add_argument("--flgf", action="store_true",
+                    help="time the fast-LGF approximation (near radii 1, 2) against the exact solve, print "
+                         "one JSON line and exit")
     ap.add_argument("--workload", action="append", choices=WORKLOADS, default=None,
                     help="time only these workloads of the config table, print them as one JSON line and "
                          "exit (no headline measurement; for profiling one workload)")
@@ -313,6 +355,10 @@ def main():
     ctx.set_mac_method(args.mac)
     if args.autotune:
         ctx.set_autotune(args.autotune)
+    if args.flgf:
+        print(json.dumps({"flgf": flgf_table(ctx), "build": {"id": lgf.build_id()}}), flush=True)
+        ctx.close()
+        return
     if args.workload:
         print(json.dumps({"configs": config_table(ctx, only=args.workload),
                           "build": {"id": lgf.build_id()}}), flush=True)
