@@ -169,11 +169,19 @@ template <typename R, int N, bool INV> __device__ __forceinline__ void fft_reg(c
         for (int i = 0; i < N; i += len) {
 #pragma unroll
             for (int k = 0; k < half; ++k) {
-                cplx<R> v = a[i + k + half];
-                if (k != 0) v = cmul(v, twiddle<R, N, INV>(k * (N / len)));
-                const cplx<R> u = a[i + k];
-                a[i + k] = cadd(u, v);
-                a[i + k + half] = csub(u, v);
+                const cplx<R> u = a[i + k], v = a[i + k + half];
+                if (k == 0) {
+                    a[i + k] = cadd(u, v);
+                    a[i + k + half] = csub(u, v);
+                } else {
+                    // u + w v with four fused multiply-adds, then u - w v = 2u - (u + w v)
+                    const cplx<R> w = twiddle<R, N, INV>(k * (N / len));
+                    cplx<R> p;
+                    p.x = fma(w.x, v.x, fma(-w.y, v.y, u.x));
+                    p.y = fma(w.x, v.y, fma(w.y, v.x, u.y));
+                    a[i + k] = p;
+                    a[i + k + half] = cmake<R>(fma((R)2, u.x, -p.x), fma((R)2, u.y, -p.y));
+                }
             }
         }
     }
