@@ -94,8 +94,8 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
         cplx<R> recv;
         recv.x = __shfl_xor(send.x, 1);
         recv.y = __shfl_xor(send.y, 1);
-        const cplx<R> ye = cadd(a[j], cmul(recv, twiddle<R, L, true>(j)));     // even lane: n = j
-        const cplx<R> yo = cadd(recv, cmul(a[jo], twiddle<R, L, true>(jo)));   // odd lane: n = jo
+        const cplx<R> ye = cmac(a[j], recv, twiddle<R, L, true>(j));     // even lane: n = j
+        const cplx<R> yo = cmac(recv, a[jo], twiddle<R, L, true>(jo));   // odd lane: n = jo
         out[j] = csel(odd, yo, ye);
     }
 }
@@ -265,10 +265,10 @@ __device__ __forceinline__ void yz_yinv(cplx<R> *P, const cplx<R> *Q, int lane, 
         if (on) {
             if (HF) {
 #pragma unroll
-                for (int j = MY / 2; j < MY; ++j) prow[j] = cadd(prow[j], cmul(b[j], twiddle<R, LY, true>(j)));
+                for (int j = MY / 2; j < MY; ++j) prow[j] = cmac(prow[j], b[j], twiddle<R, LY, true>(j));
             } else {
 #pragma unroll
-                for (int j = 0; j < MY / 2; ++j) prow[j] = cadd(b[j], cmul(prow[j], twiddle<R, LY, true>(j)));
+                for (int j = 0; j < MY / 2; ++j) prow[j] = cmac(b[j], prow[j], twiddle<R, LY, true>(j));
             }
         }
         __syncthreads();
@@ -329,10 +329,10 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     __syncthreads();
     if (HF) {
 #pragma unroll
-        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cadd(qline[j], cmul(a[j], twiddle<R, LZ, true>(j)));
+        for (int j = MZ / 2; j < MZ; ++j) qline[j] = cmac(qline[j], a[j], twiddle<R, LZ, true>(j));
     } else {
 #pragma unroll
-        for (int j = 0; j < MZ / 2; ++j) qline[j] = cadd(a[j], cmul(qline[j], twiddle<R, LZ, true>(j)));
+        for (int j = 0; j < MZ / 2; ++j) qline[j] = cmac(a[j], qline[j], twiddle<R, LZ, true>(j));
     }
     __syncthreads();
     // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
