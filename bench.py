@@ -251,6 +251,19 @@ def cpu_baseline(problem, budget_s=10.0, seed=0):
     t0 = time.perf_counter()
     direct.direct_sum(cg, gb.flat_source(), cg, gb.dx0)
     t_gb = time.perf_counter() - t0
+    # the vector ring (208 blocks of 16^3, two non-zero components): sampled
+    # targets, both components, and the full solve extrapolated from them
+    ring = inputs.single_ring()
+    cr = inputs.cell_coords(ring.levels[0].blocks, ring.nb)
+    nr = 32 * threads
+    tr = cr[rng.choice(len(cr), nr, replace=False)]
+    t0 = time.perf_counter()
+    for comp in (0, 1):
+        fr = ring.levels[0].values[comp].reshape(-1)
+        nz = fr != 0
+        direct.direct_sum(cr[nz], fr[nz], tr, ring.dx0)
+    t_ring = time.perf_counter() - t0
+    ring_rate = 2 * nr / t_ring
     tg = c[rng.choice(len(c), 64, replace=False)]
     u_tg = direct.direct_sum(c, f, tg, problem.dx0)
     return {"value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
@@ -262,6 +275,11 @@ def cpu_baseline(problem, budget_s=10.0, seed=0):
             "gaussian_box_32_full": {"value": len(cg) / t_gb, "unit": "cells/s", "cores": threads,
                                      "sample": "all %d cells against all %d sources, %.2f s"
                                                % (len(cg), len(cg), t_gb)},
+            "ring_128_vector": {"value": ring_rate, "unit": "cells/s", "cores": threads,
+                                "full_solve_s_extrapolated": 2 * len(cr) / ring_rate,
+                                "sample": "%d random target cells of the 128^3 ring support (208 blocks of 16^3), "
+                                          "components x and y against their non-zero sources, %.1f s; the z "
+                                          "component is zero" % (nr, t_ring)},
             "fft_comparator": cpu_fft_comparator(problem, c, f, tg, u_tg)}
 
 
