@@ -100,6 +100,13 @@ __device__ __forceinline__ void pair_inv(cplx<R> (&a)[L / 2], int odd, cplx<R> (
     }
 }
 
+// exp(-+2 pi i k / N) for any k in [0, N) known at compile time after
+// unrolling (the table holds k < N / 2; the rest are negated)
+template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle_full(int k) {
+    const cplx<R> w = twiddle<R, N, INV>(k % (N / 2));
+    return k < N / 2 ? w : cmake<R>(-w.x, -w.y);
+}
+
 // Tile of the x kernels: xtw<R> consecutive frequencies (one 128-byte run
 // per slot: 8 in float64, 16 in float32) x kTQ consecutive (y, z) rows q of
 // one component, a lane pair per line (xthreads<R> threads); row
@@ -111,11 +118,22 @@ template <typename R> constexpr int xthreads = 2 * xtw<R> * kTQ;
 struct XTile {
     int c, w0, q0;
 };
-template <int TW> __device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
+template <int TW, int TQ = kTQ> __device__ __forceinline__ XTile x_tile(const LatGeom &g, int b) {
     const int per_w = g.ey * g.ez;
-    const int wt = (g.n_freq + TW - 1) / TW, qt = (per_w + kTQ - 1) / kTQ;
-    return XTile{b / (wt * qt), (b % wt) * TW, ((b / wt) % qt) * kTQ};
+    const int wt = (g.n_freq + TW - 1) / TW, qt = (per_w + TQ - 1) / TQ;
+    return XTile{b / (wt * qt), (b % wt) * TW, ((b / wt) % qt) * TQ};
 }
+
+// Forward x lines at LX = 64 in float64: a lane pair would hold 32 values
+// per lane (256 registers, two waves per SIMD), so each line is split over
+// four waves instead, one quarter of its frequencies per wave: with x[n]
+// the line (n < 32, zero beyond the data) and w = exp(-2 pi i / 64),
+//     X[4 m + r] = DFT_16(v)[m],  v[n] = w^(r n) (x[n] + (-i)^r x[n + 16]).
+// A tile is kTQ rows of 8 frequencies (128 lines, the pair kernels' tile) on
+// 512 threads: wave w takes quarter w mod 4 of lines 64 (w / 4) .. + 63.
+// (The inverse split the same way needs more than 128 registers per lane
+// for its four-way sum, and in float32 the pair kernels stay faster.)
+constexpr int kX4Threads = 512;
 
 // x lines of Fhat -> H.  The tile's lines are staged through LDS: the loads
 // read each slot's kTW frequencies as one run, all issued before the first
@@ -159,6 +177,69 @@ __global__ void __launch_bounds__(xthreads<R>) lat_x_fwd(LatGeom g, const cplx<R
 #pragma unroll
         for (int m = 0; m < M; ++m) out[(2 * m + odd) * g.hslab] = a[m];
     }
+}
+
+// One wave's quarter r of the x lines of a tile (LX = 64), from the staged
+// line in LDS (row: x[n], n < 32).
+template <typename R, int Q4>
+__device__ __forceinline__ void x64_fwd_quarter(const cplx<R> *row, cplx<R> *out, int64_t hslab, bool on) {
+    cplx<R> v[16];
+#pragma unroll
+    for (int n = 0; n < 16; ++n) {
+        const cplx<R> x0 = row[n], x1 = row[n + 16];
+        // (-i)^Q4 x1: 1, -i, -1, i
+        const cplx<R> r1 = Q4 == 0 ? x1 : Q4 == 1 ? cmake<R>(x1.y, -x1.x) : Q4 == 2 ? cmake<R>(-x1.x, -x1.y)
+                                                                                    : cmake<R>(-x1.y, x1.x);
+        v[n] = cadd(x0, r1);
+        if (Q4 != 0 && n != 0) v[n] = cmul(v[n], twiddle_full<R, 64, false>(Q4 * n));
+    }
+    fft_reg<R, 16, false>(v);
+    if (on) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) out[(4 * m + Q4) * hslab] = v[m];
+    }
+}
+
+// x lines of Fhat -> H at LX = 64, a line per four waves (x4tq above).
+template <typename R, bool MASKED>
+__global__ void __launch_bounds__(kX4Threads) lat_x_fwd64(LatGeom g, const cplx<R> *__restrict__ F,
+                                                         cplx<R> *__restrict__ H) {
+    constexpr int M = 32, SP = M + 1, kTW = xtw<R>, TQ = kTQ;
+    static_assert(kTW * TQ * 4 == kX4Threads, "one line per lane of every quarter");
+    constexpr int CELLS = kTW * TQ * M, NI = (CELLS + kX4Threads - 1) / kX4Threads;
+    __shared__ cplx<R> S[kTW * TQ * SP];
+    const int t = threadIdx.x;
+    const int ex = g.ex, per_w = g.ey * g.ez;
+    const XTile tl = x_tile<kTW, TQ>(g, blockIdx.x);
+    const cplx<R> *Fc = F + (int64_t)tl.c * g.fstride;
+    cplx<R> v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kX4Threads;
+        const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
+        const int q = tl.q0 + ql, w = tl.w0 + wl;
+        bool ok = e < CELLS && x < ex && q < per_w && w < g.n_freq;
+        if (MASKED) ok = ok && g.occ[q * ex + x] != 0;
+        const cplx<R> y = cload_nt(&Fc[ok ? (int64_t)(q * ex + x) * g.n_freq + w : 0]);
+        v[i] = csel(ok, y, czero<R>());
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kX4Threads;
+        const int wl = e % kTW, r = e / kTW, ql = r / M, x = r % M;
+        if (e < CELLS) S[(wl * TQ + ql) * SP + x] = v[i];
+    }
+    __syncthreads();
+    const int r4 = __builtin_amdgcn_readfirstlane((t >> 6) & 3);   // uniform per wave
+    const int rl = (t >> 8) * 64 + (t & 63);
+    const int q = tl.q0 + rl % TQ, w = tl.w0 + rl / TQ;
+    const bool on = q < per_w && w < g.n_freq;
+    cplx<R> *out = H + (int64_t)tl.c * g.hstride + (on ? (int64_t)w * 64 * g.hslab + q : 0);
+    const cplx<R> *row = S + rl * SP;
+    if (r4 == 0) x64_fwd_quarter<R, 0>(row, out, g.hslab, on);
+    else if (r4 == 1) x64_fwd_quarter<R, 1>(row, out, g.hslab, on);
+    else if (r4 == 2) x64_fwd_quarter<R, 2>(row, out, g.hslab, on);
+    else x64_fwd_quarter<R, 3>(row, out, g.hslab, on);
 }
 
 // LDS of lat_yz: the zero-padded slabs P [s][z][y] (rows of MY + 1) and the
@@ -352,12 +433,6 @@ template <typename R> __device__ __forceinline__ void tw128_fill(cplx<R> *w, int
     }
 }
 
-// exp(-+2 pi i k / N) for any k in [0, N) known at compile time after
-// unrolling (the table holds k < N / 2; the rest are negated)
-template <typename R, int N, bool INV> __device__ __forceinline__ cplx<R> twiddle_full(int k) {
-    const cplx<R> w = twiddle<R, N, INV>(k % (N / 2));
-    return k < N / 2 ? w : cmake<R>(-w.x, -w.y);
-}
 
 // Step 3 of lat_yz at LZ = 128 for one wave: its quarter Q4 = HF + 2 ZP of
 // every z line of its slabs.  With x[n] the line (n < 64, zero beyond the
@@ -814,13 +889,25 @@ template <typename F> hipError_t with_yz_zlen(int L, F &&f) {
 }
 
 // workgroups of the x kernels: one per (component, frequency tile, row tile)
-template <typename R> unsigned x_tiles(const LatGeom &g) {
+template <typename R> unsigned x_tiles(const LatGeom &g, int tq) {
     const int per_w = g.ey * g.ez;
-    return (unsigned)((int64_t)g.nc * ((g.n_freq + xtw<R> - 1) / xtw<R>) * ((per_w + kTQ - 1) / kTQ));
+    return (unsigned)((int64_t)g.nc * ((g.n_freq + xtw<R> - 1) / xtw<R>) * ((per_w + tq - 1) / tq));
 }
 
 template <typename R> hipError_t fwd_impl(const LatGeom &g, const void *F, void *H, hipStream_t s) {
-    const unsigned blocks = x_tiles<R>(g);
+    if constexpr (std::is_same<R, double>::value) {
+        if (g.lx == 64) {
+            const unsigned blocks = x_tiles<R>(g, kTQ);
+            if (g.occ)
+                hipLaunchKernelGGL((lat_x_fwd64<R, true>), dim3(blocks), dim3(kX4Threads), 0, s, g,
+                                   (const cplx<R> *)F, (cplx<R> *)H);
+            else
+                hipLaunchKernelGGL((lat_x_fwd64<R, false>), dim3(blocks), dim3(kX4Threads), 0, s, g,
+                                   (const cplx<R> *)F, (cplx<R> *)H);
+            return hipGetLastError();
+        }
+    }
+    const unsigned blocks = x_tiles<R>(g, kTQ);
     return with_xlen(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
         if (g.occ)
@@ -849,7 +936,7 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
 }
 
 template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
-    const unsigned blocks = x_tiles<R>(g);
+    const unsigned blocks = x_tiles<R>(g, kTQ);
     return with_xlen(g.lx, [&](auto lx) {
         constexpr int LX = decltype(lx)::value;
         hipLaunchKernelGGL((lat_x_inv<R, LX>), dim3(blocks), dim3(xthreads<R>), 0, s, g, (const cplx<R> *)H,
