@@ -559,9 +559,9 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
     constexpr int HL = kLatThreads / 2;                 // lanes per half
     constexpr int SL = YzLds<LY, LZ>::SL;               // slabs per workgroup
     constexpr int MY = LY / 2, MZ = LZ / 2;
-    // lines padded by one element: unpadded, the lines a wave reads at once
+    // rows padded by one element: unpadded, the lines a wave reads at once
     // start 256 B apart and fall into one LDS bank
-    constexpr int PY = MY + 1, QZ = MZ + 1;
+    constexpr int PY = MY + 1;
     constexpr int CELLS = SL * MZ * MY;                 // slab cells zero-padded to MZ x MY
     using L = YzLds<LY, LZ>;
     __shared__ cplx<R> lds[L::ELEMS];
