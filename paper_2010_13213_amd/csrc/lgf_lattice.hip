@@ -382,6 +382,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
             kp += 2 * ks;
         }
     }
+    __builtin_amdgcn_s_setprio(0);   // loads issued: arithmetic at normal priority
     // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
     yz_ydft<R, LY, LZ, HF>(P, Q, lane);
     // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
@@ -571,6 +572,11 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
     __shared__ int64_t hbase[SL];
     __shared__ int sinfo[SL][2];
     const int t = threadIdx.x;
+    // wave priority: a wave issuing its slab and spectra loads (or, at the
+    // end, its stores) goes ahead of the waves in their DFT phases, so the
+    // memory requests of one workgroup overlap the arithmetic of the others
+    // (1.53 -> 1.42 ms at 32 x 32 x 32)
+    if (!L::WIDE) __builtin_amdgcn_s_setprio(2);
     const int half = __builtin_amdgcn_readfirstlane(t / HL), lane = t % HL;   // half: uniform per wave
     const int ey = g.ey, ez = g.ez;
     // slab counts fit in 32 bits (the launch checks nc * n_freq * lx)
@@ -625,6 +631,7 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
         else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
     }
+    if (!L::WIDE) __builtin_amdgcn_s_setprio(2);
     // 5. store the slabs back (streaming stores: lat_x_inv reads them from HBM)
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
