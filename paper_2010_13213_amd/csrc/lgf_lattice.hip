@@ -531,6 +531,7 @@ __device__ __forceinline__ void yz128_half(const LatGeom &g, const R *__restrict
     const int ks = rz ? -LY : LY;
     // a reflected kz runs backwards from kz = LZ; kz = 0 is its own reflection
     const R *kb = (rz ? kc + LZ * LY : kc) + (2 * zp + HF) * ks;
+    __builtin_amdgcn_s_setprio(0);   // the slab loads are done: arithmetic at normal priority
     yz_ydft<R, LY, LZ, HF>(P, Q, lane);
     cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
     if (zp) yz128_zstep<R, LY, HF, 1>(qline, kb, kc, ks);
@@ -576,7 +577,7 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
     // end, its stores) goes ahead of the waves in their DFT phases, so the
     // memory requests of one workgroup overlap the arithmetic of the others
     // (1.53 -> 1.42 ms at 32 x 32 x 32)
-    if (!L::WIDE) __builtin_amdgcn_s_setprio(2);
+    __builtin_amdgcn_s_setprio(2);
     const int half = __builtin_amdgcn_readfirstlane(t / HL), lane = t % HL;   // half: uniform per wave
     const int ey = g.ey, ez = g.ez;
     // slab counts fit in 32 bits (the launch checks nc * n_freq * lx)
@@ -631,7 +632,7 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         if (half) yz_half<R, LY, LZ, 1>(g, Khat, P, Q, sinfo, lane, ez);
         else yz_half<R, LY, LZ, 0>(g, Khat, P, Q, sinfo, lane, ez);
     }
-    if (!L::WIDE) __builtin_amdgcn_s_setprio(2);
+    __builtin_amdgcn_s_setprio(2);
     // 5. store the slabs back (streaming stores: lat_x_inv reads them from HBM)
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
