@@ -59,6 +59,8 @@ def _check_build(bid):
     """The library must have been built from the sources beside it: a stale
     liblgf.so would test and time other code than the tree holds."""
     from . import build as _build
+    if not os.path.isdir(_build.CSRC):
+        return   # an installed library without its sources: nothing to compare against
     want = "sha256=" + _build.source_digest()
     if not bid.startswith(want + " "):
         raise RuntimeError("liblgf.so (%s) was built from other sources than %s (%s); rebuild with "
