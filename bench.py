@@ -32,6 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB
 # copy) and the sources whose hash that summary must record to be used.
 KERNELS = {
+    "lat_fused": ("lat_fused<double,false>", "lat_fused_fp64_dense256_traffic.txt",
+                  ["lgf_lattice.hip", "lgf_device.hpp", "lgf_kernels.hpp"]),
     "lat_yz": ("lat_yz<double,32,32>", "lat_yz_fp64_dense256_traffic.txt",
                ["lgf_lattice.hip", "lgf_device.hpp", "lgf_kernels.hpp"]),
     "smac": ("smac_kernel<16,8,16,8,double,dense,1 component>", "smac_fp64_dense256_traffic.txt",
@@ -349,6 +351,8 @@ def main():
                     help="print the hash of that kernel's sources (as counter summaries record it) and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration reference)")
+    ap.add_argument("--lattice-passes", type=int, choices=[1, 3], default=3,
+                    help="lattice MAC in three passes (3) or in one pass per frequency where the lengths allow (1)")
     ap.add_argument("--mac", choices=["auto", "pairs", "lattice"], default="auto",
                     help="spectral MAC method of the solves (auto: tuning table, else the cost model)")
     ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
@@ -371,6 +375,7 @@ def main():
     torch.cuda.init()
     ctx = lgf.Context(0)
     ctx.set_mac_method(args.mac)
+    ctx.set_lattice_passes(args.lattice_passes)
     if args.autotune:
         ctx.set_autotune(args.autotune)
     if args.flgf:
@@ -445,7 +450,28 @@ def main():
     # roofline of the dominant kernel (per launch, HIP events on the solve stream)
     n_freq = (2 * nb) ** 2 * (nb + 1)
     st = r64["stages"]
-    if st["lat_yz"][1] > 0:
+    if st["lat_fused"][1] > 0:
+        ext = [int(v) for v in (prob.levels[0].blocks.max(0) - prob.levels[0].blocks.min(0) + 1)]
+        L = [lattice_len(e) for e in ext]
+        n_stored = (nb + 1) ** 3               # lattice spectra kept for ky, kz in [0, N/2]
+        n_slots = ext[0] * ext[1] * ext[2]
+        # one pass per frequency: Fhat read once, the two terms of Uhat
+        # written once (complex float64), the stored spectra read once (real float64)
+        bytes_fu = n_freq * 16 * 3 * n_slots + n_stored * 8 * L[0] * L[1] * L[2]
+        fu_ms = st["lat_fused"][0] / st["lat_fused"][1]
+        achieved = bytes_fu / (fu_ms * 1e-3) / 1e9
+        # the whole solve: block FFTs read/write the field (8 B per cell) and
+        # the spectra (16 B per frequency per block); the inverse reads both terms
+        bytes_fft = n_blocks * (nb ** 3 * 8 + n_freq * 16)
+        solve_bytes = 2 * bytes_fft + n_blocks * n_freq * 16 + bytes_fu
+        roof = {"bound": "hbm", "kernel": KERNELS["lat_fused"][0], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("lat_fused"),
+                "traffic_unit": "bytes per launch (HBM, counters)", "algorithmic_bytes_per_launch": bytes_fu,
+                "avg_launch_ms": fu_ms, "lattice_lengths": L,
+                "mac_stage_ms_per_step": st["lat_fused"][0] / args.steps,
+                "solve_algorithmic_bytes": solve_bytes,
+                "solve_frac": solve_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    elif st["lat_yz"][1] > 0:
         ext = [int(v) for v in (prob.levels[0].blocks.max(0) - prob.levels[0].blocks.min(0) + 1)]
         L = [lattice_len(e) for e in ext]
         n_stored = (nb + 1) ** 3               # lattice spectra kept for ky, kz in [0, N/2]
@@ -495,7 +521,8 @@ def main():
         "config": {"workload": "dense 256^3 box, 4096 blocks of 16^3, dx=R/64, ring x-vorticity, "
                                "single level, scalar; value = FP64 path",
                    "cells": cells, "block_pairs": n_blocks * n_blocks, "plan_s": round(r64["plan_s"], 3),
-                   "mac_method": "lattice" if st["lat_yz"][1] > 0 else "pairs"},
+                   "mac_method": ("lattice, one pass" if st["lat_fused"][1] > 0 else
+                                  "lattice, three passes" if st["lat_yz"][1] > 0 else "pairs")},
         "latency_ms": {"p50": _pct(r64["lat"], 50), "p99": _pct(r64["lat"], 99)},
         "err_vs_oracle": {"fp64": err(r64["u"]),
                           "fp32_refine": err(r32["u"]) if r32 else None,

@@ -344,9 +344,10 @@ lgf_status lgf_block_spectrum(lgf_context *ctx, int nb, const int32_t d[3], doub
  * block FFT, 3 everything else, 4 lattice x DFTs, 5 lattice y/z slabs (y
  * and z DFTs, product with the lattice spectra, inverse z and y DFTs), 6
  * lattice inverse x DFTs (stages 4-6 form the spectral MAC of lattice
- * convolutions).
+ * convolutions in three passes), 7 the one-pass lattice MAC (all of 4-6 per
+ * frequency, see lgf_context_set_lattice_passes).
  */
-#define LGF_N_STAGES 7
+#define LGF_N_STAGES 8
 lgf_status lgf_context_set_timing(lgf_context *ctx, int enable);
 lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launches);
 
@@ -390,6 +391,25 @@ lgf_status lgf_context_stage_times(lgf_context *ctx, double *ms, int64_t *launch
  */
 typedef enum { LGF_MAC_AUTO = 0, LGF_MAC_PAIRS = 1, LGF_MAC_LATTICE = 2 } lgf_mac_method;
 lgf_status lgf_context_set_mac_method(lgf_context *ctx, int method);
+
+/*
+ * How the lattice FFT of a convolution is split into launches (same sum,
+ * Sec. 2.2, eq. lgf_convolution, evaluated per block frequency as a
+ * zero-padded lattice convolution).  passes = 3 (the default): lattice x
+ * DFTs of the source spectra into a workspace, then its y/z slabs (y and z
+ * DFTs, product with the lattice spectra, inverse z and y DFTs) in place,
+ * then inverse x DFTs into the target spectra: the workspace is written
+ * once and read twice.  passes = 1: where the DFT lengths are 32 x 32 x 32
+ * (boxes of 9 to 16 blocks along every axis), one launch does all of it per
+ * block frequency in on-chip memory, writing the terms of the even and the
+ * odd lattice x frequencies to two target spectra that the inverse block
+ * FFT adds; other lengths keep three passes.  It moves fewer bytes but, with
+ * the block-major spectra, reads and writes 16 bytes per slot and
+ * workgroup, and is slower on MI355X (3.8 against 2.8 ms per MAC on the
+ * 256^3 box).  The two splits agree to rounding.  Plans made before the call
+ * keep their split.  Returns LGF_E_INVALID for other values.
+ */
+lgf_status lgf_context_set_lattice_passes(lgf_context *ctx, int passes);
 lgf_status lgf_context_set_autotune(lgf_context *ctx, int reps);
 lgf_status lgf_context_save_tuning(lgf_context *ctx, const char *path);
 lgf_status lgf_context_load_tuning(lgf_context *ctx, const char *path);

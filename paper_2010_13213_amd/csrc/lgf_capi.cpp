@@ -596,6 +596,14 @@ lgf_status lgf_context_set_mac_method(lgf_context *ctx, int method) {
     });
 }
 
+lgf_status lgf_context_set_lattice_passes(lgf_context *ctx, int passes) {
+    return guard([&] {
+        require(ctx != nullptr, "null context");
+        require(passes == 1 || passes == 3, "lattice passes must be 1 or 3");
+        ctx->lat_passes = passes;
+    });
+}
+
 lgf_status lgf_context_set_autotune(lgf_context *ctx, int reps) {
     return guard([&] {
         require(ctx != nullptr, "null context");

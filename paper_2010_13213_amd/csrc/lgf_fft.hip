@@ -192,8 +192,9 @@ template <typename R, int N> __device__ __forceinline__ R re_rot(cplx<R> v, int 
 
 // C: [z][ky][kxl] after the z pass (FB_ELEMS), D: [z][y][kxl] after the y
 // pass (FA_ELEMS), the workgroup's LDS.
-template <int NB, typename R, bool BM>
-__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+template <int NB, typename R, bool BM, bool SUM2 = false>
+__device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, const cplx<R> *__restrict__ Uhat2,
+                                         int64_t n_slots,
                                          const int *__restrict__ slot, const int64_t *__restrict__ blk_off,
                                          double *__restrict__ dst, double scale, int accumulate, int b, cplx<R> *C,
                                          cplx<R> *D) {
@@ -202,6 +203,7 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
     static_assert(NB * NB <= kInvThreads, "one x row per thread");
     const int64_t ws = BM ? 1 : n_slots;
     const cplx<R> *Ub = Uhat + slot[b] * (BM ? fft_freqs<NB> : 1);
+    const cplx<R> *Ub2 = SUM2 ? Uhat2 + slot[b] * fft_freqs<NB> : nullptr;
     const int t = threadIdx.x;
     R acc[NB];
 #pragma unroll
@@ -221,6 +223,7 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
                     BM ? (int64_t)N * N * k0 + (kz * N + ky) * nk + kxl : ((int64_t)kz * N + ky) * H + k0 + kxl;
                 if constexpr (BM) a[kz] = cload_nt(&Ub[pos * ws]);
                 else a[kz] = Ub[pos * ws];
+                if constexpr (SUM2) a[kz] = cadd(a[kz], cload_nt(&Ub2[pos]));
             }
             fft_reg<R, N, true>(a);
 #pragma unroll
@@ -265,8 +268,10 @@ __device__ __forceinline__ void inv_body(const cplx<R> *__restrict__ Uhat, int64
     }
 }
 
-template <int NB, typename R>
-__global__ void __launch_bounds__(kInvThreads) inv_kernel(const cplx<R> *__restrict__ Uhat, int64_t n_slots,
+// SUM2: the spectrum is Uhat + Uhat2 (block-major)
+template <int NB, typename R, bool SUM2>
+__global__ void __launch_bounds__(kInvThreads) inv_kernel(const cplx<R> *__restrict__ Uhat,
+                                                  const cplx<R> *__restrict__ Uhat2, int64_t n_slots,
                                                   int block_major, const int *__restrict__ slot,
                                                   const int64_t *__restrict__ blk_off, double *__restrict__ dst,
                                                   double scale, int accumulate) {
@@ -274,8 +279,9 @@ __global__ void __launch_bounds__(kInvThreads) inv_kernel(const cplx<R> *__restr
     __shared__ cplx<R> C[S::FB_ELEMS];
     __shared__ cplx<R> D[S::FA_ELEMS];
     const int b = (int)xcd_order(blockIdx.x, gridDim.x);
-    if (block_major) inv_body<NB, R, true>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
-    else inv_body<NB, R, false>(Uhat, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
+    if (SUM2) inv_body<NB, R, true, true>(Uhat, Uhat2, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
+    else if (block_major) inv_body<NB, R, true>(Uhat, nullptr, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
+    else inv_body<NB, R, false>(Uhat, nullptr, n_slots, slot, blk_off, dst, scale, accumulate, b, C, D);
 }
 
 template <int NB, typename R>
@@ -285,12 +291,15 @@ __global__ void __launch_bounds__(kInvThreads) inv_batch_kernel(const FftJob *__
     __shared__ cplx<R> D[S::FA_ELEMS];
     const int b = (int)xcd_order(blockIdx.x, gridDim.x);
     const FftJob &j = jobs[find_job(jobs, n_jobs, b)];
-    if (j.block_major)
-        inv_body<NB, R, true>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
-                              b - j.blk_begin, C, D);
+    if (j.spec2)
+        inv_body<NB, R, true, true>((const cplx<R> *)j.spec, (const cplx<R> *)j.spec2, j.n_slots, j.slot, j.blk_off,
+                                    j.dst, j.scale, j.accumulate, b - j.blk_begin, C, D);
+    else if (j.block_major)
+        inv_body<NB, R, true>((const cplx<R> *)j.spec, nullptr, j.n_slots, j.slot, j.blk_off, j.dst, j.scale,
+                              j.accumulate, b - j.blk_begin, C, D);
     else
-        inv_body<NB, R, false>((const cplx<R> *)j.spec, j.n_slots, j.slot, j.blk_off, j.dst, j.scale, j.accumulate,
-                               b - j.blk_begin, C, D);
+        inv_body<NB, R, false>((const cplx<R> *)j.spec, nullptr, j.n_slots, j.slot, j.blk_off, j.dst, j.scale,
+                               j.accumulate, b - j.blk_begin, C, D);
 }
 
 template <int NB, typename R>
@@ -318,11 +327,16 @@ hipError_t fwd_launch(const double *src, const int64_t *blk_off, const int *slot
 }
 
 template <int NB, typename R>
-hipError_t inv_launch(const void *Uhat, int64_t n_slots, bool block_major, const int *slot, const int64_t *blk_off,
-                      int n_blocks, double *dst, double scale, int accumulate, hipStream_t s) {
+hipError_t inv_launch(const void *Uhat, const void *Uhat2, int64_t n_slots, bool block_major, const int *slot,
+                      const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((inv_kernel<NB, R>), dim3(n_blocks), dim3(kInvThreads), 0, s, (const cplx<R> *)Uhat, n_slots,
-                       (int)block_major, slot, blk_off, dst, scale, accumulate);
+    if (Uhat2 != nullptr && !block_major) return hipErrorInvalidValue;
+    if (Uhat2 != nullptr)
+        hipLaunchKernelGGL((inv_kernel<NB, R, true>), dim3(n_blocks), dim3(kInvThreads), 0, s, (const cplx<R> *)Uhat,
+                           (const cplx<R> *)Uhat2, n_slots, (int)block_major, slot, blk_off, dst, scale, accumulate);
+    else
+        hipLaunchKernelGGL((inv_kernel<NB, R, false>), dim3(n_blocks), dim3(kInvThreads), 0, s, (const cplx<R> *)Uhat,
+                           nullptr, n_slots, (int)block_major, slot, blk_off, dst, scale, accumulate);
     return hipGetLastError();
 }
 
@@ -361,17 +375,19 @@ hipError_t block_fft_inverse_batch(int nb, bool fp32, const FftJob *jobs, int n_
     return hipErrorInvalidValue;
 }
 
-hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, bool block_major, const int *slot,
-                             const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
-                             hipStream_t s) {
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, const void *Uhat2, int64_t n_slots,
+                             bool block_major, const int *slot, const int64_t *blk_off, int n_blocks, double *dst,
+                             double scale, int accumulate, hipStream_t s) {
     if (nb == 16)
-        return fp32 ? inv_launch<16, float>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate, s)
-                    : inv_launch<16, double>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate,
-                                             s);
+        return fp32 ? inv_launch<16, float>(Uhat, Uhat2, n_slots, block_major, slot, blk_off, n_blocks, dst, scale,
+                                            accumulate, s)
+                    : inv_launch<16, double>(Uhat, Uhat2, n_slots, block_major, slot, blk_off, n_blocks, dst, scale,
+                                             accumulate, s);
     if (nb == 8)
-        return fp32 ? inv_launch<8, float>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate, s)
-                    : inv_launch<8, double>(Uhat, n_slots, block_major, slot, blk_off, n_blocks, dst, scale, accumulate,
-                                            s);
+        return fp32 ? inv_launch<8, float>(Uhat, Uhat2, n_slots, block_major, slot, blk_off, n_blocks, dst, scale,
+                                           accumulate, s)
+                    : inv_launch<8, double>(Uhat, Uhat2, n_slots, block_major, slot, blk_off, n_blocks, dst, scale,
+                                            accumulate, s);
     return hipErrorInvalidValue;
 }
 

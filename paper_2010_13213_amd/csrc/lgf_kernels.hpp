@@ -49,10 +49,11 @@ __host__ __device__ inline void spec_freq(int N, int p, int &kx, int &ky, int &k
 // r2c-transform and store the spectrum of slot[i] in Fhat.
 hipError_t block_fft_forward(int nb, bool fp32, const double *src, const int64_t *blk_off, const int *slot,
                              int n_blocks, void *Fhat, int64_t n_slots, bool block_major, double scale, hipStream_t s);
-// Inverse: for each listed block i, gather the spectrum of slot[i] from Uhat,
-// c2r-transform, keep the [0, nb)^3 corner, multiply by `scale` and write
-// (accumulate = 0) or add (accumulate = 1) into dst + blk_off[i].
-hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, int64_t n_slots, bool block_major, const int *slot,
+// Inverse: for each listed block i, gather the spectrum of slot[i] from Uhat
+// (plus Uhat2 when not null: block-major only), c2r-transform, keep the
+// [0, nb)^3 corner, multiply by `scale` and write (accumulate = 0) or add
+// (accumulate = 1) into dst + blk_off[i].
+hipError_t block_fft_inverse(int nb, bool fp32, const void *Uhat, const void *Uhat2, int64_t n_slots, bool block_major, const int *slot,
                              const int64_t *blk_off, int n_blocks, double *dst, double scale, int accumulate,
                              hipStream_t s);
 
@@ -63,6 +64,7 @@ struct FftJob {
     const int64_t *blk_off; // per block: element offset in src / dst
     const int *slot;        // per block: slot in the spectral workspace
     void *spec;             // forward: Fhat; inverse: Uhat
+    const void *spec2;      // inverse: a second Uhat added to the first (block-major), or null
     int64_t n_slots;
     int block_major;        // spectral layout (see block_fft_forward)
     double scale;
@@ -165,15 +167,20 @@ int lattice_stored_freqs(int N);   // frequencies with stored lattice spectra: (
 // Uhat[c] = the lattice convolution of Fhat[c] with the kernel whose
 // spectrum is Khat, for the nc components: lattice_fwd (x DFTs into H),
 // lattice_yz (y and z DFTs, product, inverse z and y DFTs in H),
-// lattice_inv (inverse x DFTs into Uhat), or all three by lattice_conv.
+// lattice_inv (inverse x DFTs into Uhat).
 hipError_t lattice_fwd(const LatGeom &g, bool fp32, const void *Fhat, void *H, hipStream_t s);
 // worder: the n_freq spectrum positions (spec_pos) in the order lattice_yz
 // takes them (any permutation; reflection partners adjacent lets them share
 // Khat in L2).
 hipError_t lattice_yz(const LatGeom &g, bool fp32, void *H, const void *Khat, const int *worder, hipStream_t s);
 hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, hipStream_t s);
-hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, const int *worder,
-                        void *Uhat, hipStream_t s);
+// The same convolution in one pass per frequency, at lengths 32 x 32 x 32
+// only (lattice_fused_ok): the terms of the even and the odd lattice x
+// frequencies go to Uhat and Uhat2 (same layout), whose sum is the result
+// (block_fft_inverse adds them); no H.
+bool lattice_fused_ok(const LatGeom &g);
+hipError_t lattice_fused(const LatGeom &g, bool fp32, const void *Fhat, const void *Khat, void *Uhat, void *Uhat2,
+                         hipStream_t s);
 // Khat for lattice lengths (lx, ly, lz) from the octant table (same
 // precision), scaled by 1 / (lx ly lz); scratch holds the complex
 // intermediate of a chunk of frequencies.

@@ -251,22 +251,23 @@ __global__ void __launch_bounds__(kX4Threads) lat_x_fwd64(LatGeom g, const cplx<
 // Slabs per workgroup: one z line per lane of a half (SL = 128 / LY); at
 // LZ = 128 (WIDE) each half-line is split over the two waves of its half,
 // so one z line per lane of a wave (SL = 64 / LY).
-template <int LY, int LZ> struct YzLds {
+template <int LY, int LZ, int NT = kLatThreads> struct YzLds {
     static constexpr bool WIDE = LZ > 64;
-    static constexpr int SL = WIDE ? kLatThreads / (4 * LY) : kLatThreads / (2 * LY);
+    static constexpr int SL = WIDE ? NT / (4 * LY) : NT / (2 * LY);
     static constexpr int MY = LY / 2, MZ = LZ / 2, PY = MY + 1, QZ = MZ + 1;
     static constexpr int P_ELEMS = SL * MZ * PY, Q_ELEMS = SL * LY * QZ;
-    static constexpr bool ALIAS = SL * MZ <= kLatThreads / 2 && P_ELEMS <= Q_ELEMS;
+    static constexpr bool ALIAS = SL * MZ <= NT / 2 && P_ELEMS <= Q_ELEMS;
     static constexpr int ELEMS = ALIAS ? Q_ELEMS : P_ELEMS + Q_ELEMS;
 };
 
 // Step 2 of lat_yz for the lanes of one half (HF: 0 even, 1 odd): the y
 // lines (s, z) of the zero-padded slabs in P, every z < MZ, MY inputs ->
-// this half's MY outputs, into Q.  Ends with a barrier.
-template <typename R, int LY, int LZ, int HF>
+// this half's MY outputs, into Q.  Ends with a barrier.  NT: threads of the
+// workgroup, NT / 2 lanes per half.
+template <typename R, int LY, int LZ, int HF, int NT = kLatThreads>
 __device__ __forceinline__ void yz_ydft(cplx<R> *P, cplx<R> *Q, int lane) {
-    using L = YzLds<LY, LZ>;
-    constexpr int HL = kLatThreads / 2;
+    using L = YzLds<LY, LZ, NT>;
+    constexpr int HL = NT / 2;
     constexpr int SL = L::SL;
     constexpr int MY = LY / 2, MZ = LZ / 2;
     constexpr int PY = MY + 1, QZ = MZ + 1;
@@ -312,10 +313,10 @@ __device__ __forceinline__ void yz_ydft(cplx<R> *P, cplx<R> *Q, int lane) {
 // Step 4 of lat_yz for one half: the inverse y lines (s, z), z < ez, this
 // half's MY inputs -> MY outputs, combined through the line's slab row in P.
 // Ends with a barrier.
-template <typename R, int LY, int LZ, int HF>
+template <typename R, int LY, int LZ, int HF, int NT = kLatThreads>
 __device__ __forceinline__ void yz_yinv(cplx<R> *P, const cplx<R> *Q, int lane, int ez) {
-    using L = YzLds<LY, LZ>;
-    constexpr int HL = kLatThreads / 2;
+    using L = YzLds<LY, LZ, NT>;
+    constexpr int HL = NT / 2;
     constexpr int SL = L::SL;
     constexpr int MY = LY / 2, MZ = LZ / 2;
     constexpr int PY = MY + 1, QZ = MZ + 1;
@@ -359,7 +360,7 @@ __device__ __forceinline__ void yz_yinv(cplx<R> *P, const cplx<R> *Q, int lane, 
 // Steps 2-4 of lat_yz for the lanes of one half (HF: 0 even, 1 odd), on
 // the zero-padded slabs in P.  Every index that depends on the half is a
 // constant here; both halves pass the same barriers in the same order.
-template <typename R, int LY, int LZ, int HF>
+template <typename R, int LY, int LZ, int HF, int NT = kLatThreads>
 __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ Khat, cplx<R> *P, cplx<R> *Q,
                                         const int (*sinfo)[2], int lane, int ez) {
     constexpr int MZ = LZ / 2;
@@ -384,7 +385,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     }
     __builtin_amdgcn_s_setprio(0);   // loads issued: arithmetic at normal priority
     // 2. y lines (s, z), every z < MZ: MY inputs -> this half's MY outputs
-    yz_ydft<R, LY, LZ, HF>(P, Q, lane);
+    yz_ydft<R, LY, LZ, HF, NT>(P, Q, lane);
     // 3. z lines (s, ky): X[2m + HF] of the line, product with the spectra,
     // inverse half DFT; then the halves combine through the line
     cplx<R> *qline = Q + (zsl * LY + ky) * QZ;
@@ -419,7 +420,7 @@ __device__ __forceinline__ void yz_half(const LatGeom &g, const R *__restrict__ 
     __syncthreads();
     // 4. inverse y lines (s, z), z < ez: this half's MY inputs -> MY
     // outputs, combined through the line's slab row in P
-    yz_yinv<R, LY, LZ, HF>(P, Q, lane, ez);
+    yz_yinv<R, LY, LZ, HF, NT>(P, Q, lane, ez);
 }
 
 // w[q] = exp(-2 pi i q / 128), q < 128, into LDS (threads t < 64 write)
@@ -640,6 +641,117 @@ __global__ void __launch_bounds__(kLatThreads) __attribute__((amdgpu_waves_per_e
         const int sl = e / (MZ * MY), z = (e / MY) % MZ, y = e % MY;
         const int64_t hb = e < CELLS ? hbase[sl] : -1;
         if (hb >= 0 && y < ey && z < ez) cstore_nt(&H[hb + z * ey + y], P[(sl * MZ + z) * PY + y]);
+    }
+}
+
+// The whole lattice MAC of one frequency at lengths 32 x 32 x 32 (boxes up
+// to 16 blocks per axis), in LDS: a workgroup takes (component, frequency,
+// kx parity h) and the 16 kx = 2 m + h of that frequency.  With x[n] an x
+// line (n < 16, zero beyond the data) and w = exp(-2 pi i / 32),
+//     X[2 m + h] = DFT_16(w^(h n) x[n])[m]
+// fills 16 slabs [m][z][y]; they go through the y/z steps of lat_yz (16
+// slabs per 1024 threads, so the slab cells never leave LDS), and the
+// inverse x lines keep n < 16 of
+//     y[n] = IDFT_16(Y[2 m])[n] + w^(-n) IDFT_16(Y[2 m + 1])[n]:
+// parity 0 writes its term into U0, parity 1 its term into U1, and the
+// inverse block FFT adds the two.  Fhat is read and each term written once,
+// where the three-pass split writes the box after the x DFT (H) once and
+// reads it twice; but a workgroup reads and writes 16 bytes per slot (one
+// frequency of the block-major spectra), so the frequencies of one
+// 128-byte run go to neighbouring workgroups: the two parities of a
+// frequency run next to each other and frequencies in spectrum order, and
+// the loads and stores go through L2 (streaming stores of partial lines
+// measured 2x slower).  MASKED: slots without a source block (g.occ) read
+// as zero.
+constexpr int kFuThreads = 1024;
+
+template <typename R, bool MASKED>
+__global__ void __launch_bounds__(kFuThreads) lat_fused(LatGeom g, const cplx<R> *__restrict__ F,
+                                                       const R *__restrict__ Khat, cplx<R> *__restrict__ U0,
+                                                       cplx<R> *__restrict__ U1) {
+    constexpr int L = 32, M = 16;
+    using Y = YzLds<L, L, kFuThreads>;
+    static_assert(Y::SL == M && Y::ALIAS, "one slab per kx of a parity, the slabs inside Q");
+    constexpr int PY = M + 1;                             // slab rows [m][z][y] (lat_yz's P)
+    constexpr int SX = M + 1;                             // staged x lines [z][y][x]
+    static_assert(Y::P_ELEMS + M * M * SX <= Y::ELEMS, "the staged lines fit beside the slabs");
+    constexpr int NI = M * M * M / kFuThreads;
+    __shared__ cplx<R> lds[Y::ELEMS];
+    __shared__ int sinfo[M][2];
+    cplx<R> *P = lds, *Q = lds, *S = lds + Y::P_ELEMS;
+    const int t = threadIdx.x;
+    const int item = (int)xcd_order(blockIdx.x, gridDim.x);
+    const int h = item & 1, wc = item >> 1;
+    const int c = wc / g.n_freq, p = wc % g.n_freq;
+    const int ex = g.ex, ey = g.ey, ez = g.ez;
+    if (t < M) {
+        const int N = g.N, Hh = N / 2 + 1;
+        int fx, fyv, fzv;
+        spec_freq(N, p, fx, fyv, fzv);
+        const int ry = fyv > N / 2, rz = fzv > N / 2;
+        sinfo[t][0] = ((rz ? N - fzv : fzv) * Hh + (ry ? N - fyv : fyv)) * Hh + fx;
+        sinfo[t][1] = (2 * t + h) | ry << 8 | rz << 9;
+    }
+    // 1. the frequency's value in every slot, staged as x lines (all loads
+    // issued before the first is waited on; cells outside the data read
+    // element 0 and are replaced by zero)
+    const cplx<R> *Fc = F + (int64_t)c * g.fstride;
+    cplx<R> v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kFuThreads;
+        const int x = e % M, y = (e / M) % M, z = e / (M * M);
+        const int slot = (z * ey + y) * ex + x;
+        bool ok = x < ex && y < ey && z < ez;
+        if (MASKED) ok = ok && g.occ[ok ? slot : 0] != 0;
+        const cplx<R> f = Fc[ok ? (int64_t)slot * g.n_freq + p : 0];
+        v[i] = csel(ok, f, czero<R>());
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int e = t + i * kFuThreads;
+        S[(e / M) * SX + e % M] = v[i];
+    }
+    __syncthreads();
+    // 2. x DFTs of this parity: line (y, z) -> slab row m (zero where the
+    // line holds no data, as lat_yz's zero-padded slabs)
+    if (t < M * M) {
+        const int y = t % M, z = t / M;
+        cplx<R> a[M];
+#pragma unroll
+        for (int n = 0; n < M; ++n) a[n] = S[t * SX + n];
+        if (h) {
+#pragma unroll
+            for (int n = 1; n < M; ++n) a[n] = cmul(a[n], twiddle<R, L, false>(n));
+        }
+        fft_reg<R, M, false>(a);
+#pragma unroll
+        for (int m = 0; m < M; ++m) P[(m * M + z) * PY + y] = a[m];
+    }
+    __syncthreads();
+    // 3. y DFTs, z DFTs, product with the spectra, inverse z and y DFTs of
+    // the 16 slabs (each wave in its half's copy; ends with a barrier)
+    const int half = __builtin_amdgcn_readfirstlane(t / (kFuThreads / 2)), lane = t % (kFuThreads / 2);
+    if (half) yz_half<R, L, L, 1, kFuThreads>(g, Khat, P, Q, sinfo, lane, ez);
+    else yz_half<R, L, L, 0, kFuThreads>(g, Khat, P, Q, sinfo, lane, ez);
+    // 4. inverse x DFTs of this parity over the slabs, this parity's term
+    // of the outputs n < ex
+    if (t < M * M) {
+        const int y = t % M, z = t / M;
+        if (y < ey && z < ez) {
+            cplx<R> b[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) b[m] = P[(m * M + z) * PY + y];
+            fft_reg<R, M, true>(b);
+            if (h) {
+#pragma unroll
+                for (int n = 1; n < M; ++n) b[n] = cmul(b[n], twiddle<R, L, true>(n));
+            }
+            cplx<R> *out = (h ? U1 : U0) + (int64_t)c * g.fstride + (int64_t)((z * ey + y) * ex) * g.n_freq + p;
+#pragma unroll
+            for (int n = 0; n < M; ++n)
+                if (n < ex) out[(int64_t)n * g.n_freq] = b[n];
+        }
     }
 }
 
@@ -943,6 +1055,19 @@ hipError_t yz_impl(const LatGeom &g, void *H, const void *Khat, const int *worde
     });
 }
 
+template <typename R>
+hipError_t fused_impl(const LatGeom &g, const void *F, const void *Khat, void *U0, void *U1, hipStream_t s) {
+    const int64_t items = (int64_t)g.nc * g.n_freq * 2;
+    if (items >= INT32_MAX) return hipErrorInvalidValue;   // the kernel counts items in 32 bits
+    if (g.occ)
+        hipLaunchKernelGGL((lat_fused<R, true>), dim3((unsigned)items), dim3(kFuThreads), 0, s, g,
+                           (const cplx<R> *)F, (const R *)Khat, (cplx<R> *)U0, (cplx<R> *)U1);
+    else
+        hipLaunchKernelGGL((lat_fused<R, false>), dim3((unsigned)items), dim3(kFuThreads), 0, s, g,
+                           (const cplx<R> *)F, (const R *)Khat, (cplx<R> *)U0, (cplx<R> *)U1);
+    return hipGetLastError();
+}
+
 template <typename R> hipError_t inv_impl(const LatGeom &g, const void *H, void *U, hipStream_t s) {
     const unsigned blocks = x_tiles<R>(g, kTQ);
     return with_xlen(g.lx, [&](auto lx) {
@@ -1032,12 +1157,12 @@ hipError_t lattice_inv(const LatGeom &g, bool fp32, const void *H, void *Uhat, h
     return fp32 ? inv_impl<float>(g, H, Uhat, s) : inv_impl<double>(g, H, Uhat, s);
 }
 
-hipError_t lattice_conv(const LatGeom &g, bool fp32, const void *Fhat, void *H, const void *Khat, const int *worder,
-                        void *Uhat, hipStream_t s) {
-    hipError_t e = lattice_fwd(g, fp32, Fhat, H, s);
-    if (e == hipSuccess) e = lattice_yz(g, fp32, H, Khat, worder, s);
-    if (e == hipSuccess) e = lattice_inv(g, fp32, H, Uhat, s);
-    return e;
+bool lattice_fused_ok(const LatGeom &g) { return g.lx == 32 && g.ly == 32 && g.lz == 32; }
+
+hipError_t lattice_fused(const LatGeom &g, bool fp32, const void *Fhat, const void *Khat, void *Uhat, void *Uhat2,
+                         hipStream_t s) {
+    if (!geom_ok(g) || !lattice_fused_ok(g) || Uhat2 == nullptr) return hipErrorInvalidValue;
+    return fp32 ? fused_impl<float>(g, Fhat, Khat, Uhat, Uhat2, s) : fused_impl<double>(g, Fhat, Khat, Uhat, Uhat2, s);
 }
 
 hipError_t lattice_spectra(const LatSpecGeom &sg, bool fp32, const void *octant, void *Khat, void *scratch,

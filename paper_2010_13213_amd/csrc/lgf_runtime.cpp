@@ -371,6 +371,28 @@ static void build_conv_lattice(lgf_plan *plan, Conv &c, const std::vector<Blk> &
         c.d_src_occ.alloc(ctx, occ.size(), "source slots");
         hip_check(hipMemcpy(c.d_src_occ.ptr, occ.data(), occ.size(), hipMemcpyHostToDevice), "upload source slots");
     }
+    c.lat_fused = ctx->lat_passes == 1 && lattice_fused_ok(lat_geom(c, 1));
+}
+
+const void *lattice_mac(lgf_context *ctx, const Conv &c, const LatGeom &g, const void *fhat, void *lat, void *uhat,
+                        hipStream_t s) {
+    if (c.lat_fused) {
+        StageTimer t(ctx, kStageLatFused, s);
+        hip_check(lattice_fused(g, c.fp32, fhat, c.lspec->data.ptr, uhat, lat, s),
+                  "one-pass lattice MAC");
+        return lat;
+    }
+    {
+        StageTimer t(ctx, kStageLatX, s);
+        hip_check(lattice_fwd(g, c.fp32, fhat, lat, s), "lattice x DFT");
+    }
+    {
+        StageTimer t(ctx, kStageLatYZ, s);
+        hip_check(lattice_yz(g, c.fp32, lat, c.lspec->data.ptr, c.lspec->order, s), "lattice y/z slabs");
+    }
+    StageTimer t(ctx, kStageLatInv, s);
+    hip_check(lattice_inv(g, c.fp32, lat, uhat, s), "lattice inverse x DFT");
+    return nullptr;
 }
 
 LatGeom lat_geom(const Conv &c, int nc) {
@@ -611,8 +633,7 @@ static double time_mac(lgf_plan *plan, const Conv &c, int reps) {
     hip_check(zero_fill(F.ptr, bytes, ctx->stream), "tuning clear");
     auto run = [&] {
         if (c.method == kMethodLattice) {
-            hip_check(lattice_conv(lat_geom(c, nc), c.fp32, F.ptr, Hb.ptr, c.lspec->data.ptr, c.lspec->order, U.ptr, ctx->stream),
-                      "tuning lattice MAC");
+            lattice_mac(ctx, c, lat_geom(c, nc), F.ptr, Hb.ptr, U.ptr, ctx->stream);
             return;
         }
         for (const auto &p : c.parts) {
@@ -1033,18 +1054,9 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
                                     c.n_slots, c.method == kMethodLattice, 1.0, s),
                   "forward block FFT");
     }
+    const void *uhat2 = nullptr;   // the one-pass lattice MAC's second term
     if (c.method == kMethodLattice) {
-        const LatGeom g = lat_geom(c, nc);
-        {
-            StageTimer t(plan->ctx, kStageLatX, s);
-            hip_check(lattice_fwd(g, c.fp32, ws.fhat, ws.lat, s), "lattice x DFT");
-        }
-        {
-            StageTimer t(plan->ctx, kStageLatYZ, s);
-            hip_check(lattice_yz(g, c.fp32, ws.lat, c.lspec->data.ptr, c.lspec->order, s), "lattice y/z slabs");
-        }
-        StageTimer t(plan->ctx, kStageLatInv, s);
-        hip_check(lattice_inv(g, c.fp32, ws.lat, ws.uhat, s), "lattice inverse x DFT");
+        uhat2 = lattice_mac(plan->ctx, c, lat_geom(c, nc), ws.fhat, ws.lat, ws.uhat, s);
     } else if (c.parts.empty()) {   // no source or no target: the convolution is zero
         hip_check(zero_fill(ws.uhat, (size_t)nc * fs * elem, s), "clear Uhat");
     }
@@ -1058,7 +1070,8 @@ void run_conv(lgf_plan *plan, const Conv &c, const double *src, int64_t sstride,
     }
     for (int k = 0; k < nc; ++k) {
         StageTimer t(plan->ctx, 2, s);
-        hip_check(block_fft_inverse(nb, c.fp32, (char *)ws.uhat + k * fs * elem, c.n_slots,
+        hip_check(block_fft_inverse(nb, c.fp32, (char *)ws.uhat + k * fs * elem,
+                                    uhat2 ? (const char *)uhat2 + k * fs * elem : nullptr, c.n_slots,
                                     c.method == kMethodLattice, (const int *)c.d_tgt_slot.ptr, (const int64_t *)c.d_tgt_off.ptr, c.n_tgt,
                                     dst + (size_t)k * dstride, conv_scale(plan, dx) / N3, accumulate, s),
                   "inverse block FFT");

@@ -124,6 +124,7 @@ struct lgf_context_impl {
     bool timing = false;
     int autotune_reps = 0;                       // > 0: time MAC candidates for new shapes
     int mac_method = LGF_MAC_AUTO;               // lgf_mac_method
+    int lat_passes = 3;                          // lattice FFT split: 3, or 1 where the lengths allow
     std::map<std::string, TuneEntry> tune;       // shape key -> tile shape (guarded by mu)
     JobRing ring;
     std::vector<StageEvent> pending;
@@ -166,6 +167,7 @@ struct Conv {
     int method = kMethodPairs;
     int lx = 0, ly = 0, lz = 0;     // lattice DFT lengths (method 1)
     LatSpec *lspec = nullptr;       // lattice spectra (method 1)
+    bool lat_fused = false;         // method 1 in one pass per frequency (lattice_fused)
     int bx = 0;             // MAC row template (8 or 16)
     int ty = 0, tz = 0;     // MAC tile shape in rows
     int axis = 0;           // rows along lattice x (0) or y (1)
@@ -224,6 +226,11 @@ struct LevelSched {
 SpecTable *get_spectra(lgf_context *ctx, int nb, bool fp32, int XH, int YH, int ZH, const KernelId &ka);
 LatSpec *get_lat_spectra(lgf_context *ctx, int nb, bool fp32, int lx, int ly, int lz, const KernelId &ka);
 LatGeom lat_geom(const Conv &c, int nc);
+// The lattice MAC of c (method 1) on the stream: Fhat -> Uhat through the
+// workspace lat (H, or the second term of the one-pass split, which is then
+// returned: the inverse block FFT adds it; else null).
+const void *lattice_mac(lgf_context *ctx, const Conv &c, const LatGeom &g, const void *fhat, void *lat, void *uhat,
+                        hipStream_t s);
 // every slot of the convolution holds a source block: its forward FFTs
 // write the whole spectral region it reads
 inline bool fhat_full(const Conv &c) { return (int64_t)c.n_src == c.n_slots; }
@@ -286,9 +293,9 @@ inline double conv_scale(const lgf_plan *p, double dx) { return p->if_a0 > 0.0 ?
 // Timed stages: block FFT forward, block-pair MAC, block FFT inverse, other,
 // lattice x DFTs, lattice y/z slabs (DFTs, product, inverse DFTs), lattice
 // inverse x DFTs.
-constexpr int kStages = 7;
+constexpr int kStages = 8;
 enum { kStageFwd = 0, kStagePairs = 1, kStageInv = 2, kStageOther = 3, kStageLatX = 4, kStageLatYZ = 5,
-       kStageLatInv = 6 };
+       kStageLatInv = 6, kStageLatFused = 7 };
 // Records an event before/after a stage launch when timing is on.
 struct StageTimer {
     lgf_context *ctx;

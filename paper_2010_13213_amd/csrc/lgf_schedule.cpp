@@ -654,22 +654,15 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
                   "batched forward FFT");
         ring_mark(ctx, slot, s);
     }
-    for (const ConvCall &k : calls)
+    std::vector<const void *> uhat2(calls.size(), nullptr);   // second terms of one-pass lattice MACs
+    for (size_t i = 0; i < calls.size(); ++i) {
+        const ConvCall &k = calls[i];
         if (k.c->method == kMethodLattice) {
-            const LatGeom g = lat_geom(*k.c, 1);
-            {
-                StageTimer t(ctx, kStageLatX, s);
-                hip_check(lattice_fwd(g, k.c->fp32, k.p->Fhat.ptr, k.p->ws_lat.ptr, s), "lattice x DFT");
-            }
-            {
-                StageTimer t(ctx, kStageLatYZ, s);
-                hip_check(lattice_yz(g, k.c->fp32, k.p->ws_lat.ptr, k.c->lspec->data.ptr, k.c->lspec->order, s), "lattice y/z slabs");
-            }
-            StageTimer t(ctx, kStageLatInv, s);
-            hip_check(lattice_inv(g, k.c->fp32, k.p->ws_lat.ptr, k.p->Uhat.ptr, s), "lattice inverse x DFT");
+            uhat2[i] = lattice_mac(ctx, *k.c, lat_geom(*k.c, 1), k.p->Fhat.ptr, k.p->ws_lat.ptr, k.p->Uhat.ptr, s);
         } else if (k.c->parts.empty()) {
             hip_check(zero_fill(k.p->Uhat.ptr, k.p->Uhat.bytes, s), "clear Uhat");
         }
+    }
     // parts of one target segment are in different phases: one launch per
     // (phase, precision, template, sparse flag)
     int n_phase = 0;
@@ -713,13 +706,15 @@ void run_conv_batch(lgf_context *ctx, const std::vector<ConvCall> &calls, hipStr
     for (int fp = 0; fp < 2; ++fp) {
         std::vector<FftJob> fj;
         int total = 0;
-        for (const ConvCall &k : calls) {
+        for (size_t i = 0; i < calls.size(); ++i) {
+            const ConvCall &k = calls[i];
             if ((int)k.c->fp32 != fp || k.c->n_tgt == 0) continue;
             FftJob j{};
             j.dst = k.dst;
             j.blk_off = (const int64_t *)k.c->d_tgt_off.ptr;
             j.slot = (const int *)k.c->d_tgt_slot.ptr;
             j.spec = k.p->Uhat.ptr;
+            j.spec2 = uhat2[i];
             j.n_slots = k.c->n_slots;
             j.block_major = k.c->method == kMethodLattice;
             j.scale = conv_scale(k.p, k.dx) / N3;

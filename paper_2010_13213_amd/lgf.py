@@ -26,7 +26,7 @@ EXPORTED = ["lgf_context_create", "lgf_context_destroy", "lgf_context_bytes", "l
             "lgf_last_error", "lgf_status_string", "lgf_build_id", "lgf_graph_create", "lgf_graph_create_batch", "lgf_graph_launch",
             "lgf_graph_destroy",
             "lgf_context_set_autotune", "lgf_context_save_tuning", "lgf_context_load_tuning",
-            "lgf_context_set_mac_method",
+            "lgf_context_set_mac_method", "lgf_context_set_lattice_passes",
             "lgf_context_tuning_size"]
 
 
@@ -134,6 +134,8 @@ def lib():
     L.lgf_block_spectrum.restype = ctypes.c_int
     L.lgf_context_set_mac_method.argtypes = [vp, ctypes.c_int]
     L.lgf_context_set_mac_method.restype = ctypes.c_int
+    L.lgf_context_set_lattice_passes.argtypes = [vp, ctypes.c_int]
+    L.lgf_context_set_lattice_passes.restype = ctypes.c_int
     L.lgf_context_set_autotune.argtypes = [vp, ctypes.c_int]
     L.lgf_context_set_autotune.restype = ctypes.c_int
     L.lgf_context_save_tuning.argtypes = [vp, ctypes.c_char_p]
@@ -213,13 +215,17 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("fwd_fft", "smac", "inv_fft", "other", "lat_x", "lat_yz", "lat_xinv")
+    STAGES = ("fwd_fft", "smac", "inv_fft", "other", "lat_x", "lat_yz", "lat_xinv", "lat_fused")
 
     MAC_METHODS = {"auto": 0, "pairs": 1, "lattice": 2}
 
     def set_mac_method(self, method):
         """'auto' (tuning table, else model), 'pairs' or 'lattice' (where the box allows it)."""
         _check(lib().lgf_context_set_mac_method(self._h, self.MAC_METHODS[method]))
+
+    def set_lattice_passes(self, passes):
+        """3: the lattice MAC in three passes (default); 1: in one pass per frequency where its lengths are 32^3."""
+        _check(lib().lgf_context_set_lattice_passes(self._h, int(passes)))
 
     def set_autotune(self, reps):
         """Time every compiled MAC tile shape on new convolution shapes (reps > 0) or not (0)."""
