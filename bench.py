@@ -9,11 +9,14 @@ of the headline metric.  A step is one full solve through the C ABI
 pairs -- by an FFT over the block lattice or pair by pair -- inverse block
 FFTs), with the source already resident in HBM.
 
-Prints one JSON line (rank 0, N = 1).  The roofline entry is for the
-dominant kernel of the solve, timed with HIP events recorded by the library
-around each of its launches on the solve stream: the lattice y/z-slab kernel
-(HBM-bound) when the spectral product runs as an FFT over the block lattice,
-the block-pair kernel (FP64 ALU-bound) when it runs as block pairs.
+Prints one JSON line (rank 0, N = 1).  The timed solves run without
+instrumentation (launched one by one, or replayed from a HIP graph with
+--launch graph).  The roofline entry is for the dominant kernel of the
+solve, timed in a second pass of the same solves with HIP events recorded by
+the library around each of its launches on the solve stream: the lattice
+y/z-slab kernel (HBM-bound) when the spectral product runs as an FFT over
+the block lattice, the block-pair kernel (FP64 ALU-bound) when it runs as
+block pairs.
 """
 import argparse
 import json
@@ -351,6 +354,8 @@ def main():
                     help="print the hash of that kernel's sources (as counter summaries record it) and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration reference)")
+    ap.add_argument("--launch", choices=["eager", "graph"], default="eager",
+                    help="timed solves launched one by one, or replayed from a HIP graph of one solve (lgf_graph_create)")
     ap.add_argument("--lattice-passes", type=int, choices=[1, 3], default=3,
                     help="lattice MAC in three passes (3) or in one pass per frequency where the lengths allow (1)")
     ap.add_argument("--mac", choices=["auto", "pairs", "lattice"], default="auto",
@@ -404,26 +409,40 @@ def main():
         plan = lgf.Plan.for_problem(ctx, prob, precision)
         t_plan = time.perf_counter() - t_plan
         u = torch.empty_like(f)
-        for _ in range(args.warmup):
-            plan.solve(f, u)
-        torch.cuda.synchronize()
-        ctx.set_timing(True)
-        ctx.stage_times()
         stream = torch.cuda.current_stream()
+        graph = lgf.Graph(plan, f, u) if args.launch == "graph" else None
+
+        def run():
+            if graph is not None:
+                graph.launch(stream)
+            else:
+                plan.solve(f, u, stream=stream)
+
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for a, b in evs:
             a.record(stream)
-            plan.solve(f, u)
+            run()
             b.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        st = ctx.stage_times()
-        ctx.set_timing(False)
         lat = [a.elapsed_time(b) for a, b in evs]
         host = u.cpu().numpy()
+        # a second pass of the same solves with the library's stage events
+        # (per launch of every kernel), outside the timed region above
+        ctx.set_timing(True)
+        ctx.stage_times()
+        for _ in range(args.steps):
+            plan.solve(f, u, stream=stream)
+        st = ctx.stage_times()
+        ctx.set_timing(False)
+        if graph is not None:
+            graph.close()
         plan.close()
         return {"wall": t1 - t0, "lat": lat, "stages": st, "plan_s": t_plan, "u": host}
 
